@@ -1,0 +1,318 @@
+"""FP64 CPU oracle of the bi-level planner hot path (arXiv 2212.02224).
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. It shares no
+code with the HIP path (``paper_2212_02224_amd``) and never imports it.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, literal). This module is
+the ctypes marshalling around it and its build step (``gcc``).
+
+Parity status: pinned by the CPU tests in ``tests/test_oracle_*.py`` except
+the values of the projection iterates at finite K (parity unpinned; their
+fixed points, invariances and convergence are pinned).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_oracle.so")
+_lib = None
+
+NC, NX, NP = 11, 22, 8
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into oracle/_oracle.so with gcc (OpenMP, FP64)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+               "-fno-fast-math", "-ffp-contract=off",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("T", C.c_int), ("M", C.c_int), ("K", C.c_int), ("L", C.c_int),
+        ("t_f", C.c_double),
+        ("k_p", C.c_double), ("k_v", C.c_double),
+        ("w_s", C.c_double), ("w_l", C.c_double), ("w_v", C.c_double),
+        ("rho", C.c_double),
+        ("ell_a", C.c_double), ("ell_b", C.c_double),
+        ("v_min", C.c_double), ("v_max", C.c_double), ("a_max", C.c_double),
+        ("kappa_max", C.c_double), ("c_max", C.c_double),
+        ("y_lb", C.c_double), ("y_ub", C.c_double),
+        ("v_eps", C.c_double),
+        ("eta", C.c_double), ("gamma", C.c_double),
+        ("cov_jitter", C.c_double),
+        ("frac_ces", C.c_double), ("frac_es", C.c_double),
+        ("lane_c", C.c_double * 3), ("lane_sigma", C.c_double),
+        ("vd_lo", C.c_double), ("vd_hi", C.c_double),
+    ]
+
+
+class _Scene(C.Structure):
+    _fields_ = [("ego", C.c_double * 6), ("kappa_road", C.c_double),
+                ("obs", C.POINTER(C.c_double))]
+
+
+class _PlanOut(C.Structure):
+    _fields_ = [("best_index", C.c_int), ("p_best", C.c_double * NP),
+                ("xi_best", C.c_double * NX), ("cost_upper", C.c_double),
+                ("residual", C.c_double), ("mu", C.c_double * NP),
+                ("Sigma", C.c_double * (NP * NP))]
+
+
+_PD = C.POINTER(C.c_double)
+_PI = C.POINTER(C.c_int)
+
+
+class _Trace(C.Structure):
+    _fields_ = [("p", _PD), ("xi_bar", _PD), ("xi_star", _PD), ("r", _PD),
+                ("cu", _PD), ("ces", _PI), ("es", _PI), ("c_es", _PD),
+                ("mu", _PD), ("Sigma", _PD)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = C.CDLL(_LIB_PATH)
+    P = C.POINTER(Params)
+    S = C.POINTER(_Scene)
+    lib.orc_default_params.argtypes = [P]
+    lib.orc_elite_sizes.argtypes = [P, C.c_int, _PI, _PI]
+    lib.orc_basis.argtypes = [C.c_int, C.c_double, _PD, _PD, _PD]
+    lib.orc_lower_cost.argtypes = [P, _PD, _PD]
+    lib.orc_lower_cost.restype = C.c_double
+    lib.orc_step1.argtypes = [P, S, _PD, C.c_int, _PD]
+    lib.orc_project.argtypes = [P, S, _PD, C.c_int, _PD, _PD]
+    lib.orc_targets.argtypes = [P, S, _PD, _PD, _PD, _PD, _PD]
+    lib.orc_residual_cost.argtypes = [P, S, _PD, C.c_int, _PD, _PD]
+    lib.orc_select.argtypes = [_PD, _PD, C.c_int, C.c_int, C.c_int, _PI, _PI, _PD]
+    lib.orc_update.argtypes = [P, _PD, _PD, _PD, _PI, _PD, C.c_int, _PD, _PD]
+    lib.orc_cholesky.argtypes = [_PD, C.c_int, C.c_double, _PD]
+    lib.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                      C.POINTER(C.c_uint32)]
+    lib.orc_initial_moments.argtypes = [P, _PD, _PD]
+    lib.orc_sample.argtypes = [P, C.c_uint64, C.c_int, C.c_int, C.c_int, _PD, _PD, _PD]
+    lib.orc_plan.argtypes = [P, S, C.c_uint64, C.c_int, _PD, _PD,
+                             C.POINTER(_PlanOut), C.POINTER(_Trace)]
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_get_threads.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _pd(a: np.ndarray):
+    return a.ctypes.data_as(_PD)
+
+
+def _pi(a: np.ndarray):
+    return a.ctypes.data_as(_PI)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+def default_params(**over) -> Params:
+    """Parameters with the default reading of every open point, overridden
+    by keyword (e.g. ``default_params(T=50, M=4, K=10, L=3)``)."""
+    par = Params()
+    _load().orc_default_params(C.byref(par))
+    for k, v in over.items():
+        if k == "lane_c":
+            par.lane_c = (C.c_double * 3)(*v)
+        else:
+            setattr(par, k, v)
+    return par
+
+
+@dataclass
+class Scene:
+    """Ego state b_0 = (x0, y0, vx0, vy0, ax0, ay0), neighbours (M x 4:
+    x, y, vx, vy at t = 0, constant velocity) and road curvature."""
+    ego: np.ndarray
+    obs: np.ndarray
+    kappa_road: float = 0.0
+    _keep: list = field(default_factory=list, repr=False)
+
+    def c(self) -> _Scene:
+        obs = _f64(self.obs).reshape(-1, 4) if np.size(self.obs) else np.zeros((1, 4))
+        obs = np.ascontiguousarray(obs)
+        self._keep = [obs]
+        s = _Scene()
+        s.ego = (C.c_double * 6)(*[float(v) for v in np.asarray(self.ego).ravel()])
+        s.kappa_road = float(self.kappa_road)
+        s.obs = _pd(obs)
+        return s
+
+
+def elite_sizes(par: Params, N: int):
+    n, q = C.c_int(), C.c_int()
+    _load().orc_elite_sizes(C.byref(par), int(N), C.byref(n), C.byref(q))
+    return n.value, q.value
+
+
+def basis(T: int, t_f: float):
+    W = np.zeros((T, NC)); Wd = np.zeros((T, NC)); Wdd = np.zeros((T, NC))
+    _load().orc_basis(int(T), float(t_f), _pd(W), _pd(Wd), _pd(Wdd))
+    return W, Wd, Wdd
+
+
+def lower_cost(par: Params, p, xi) -> float:
+    p = _f64(p); xi = _f64(xi)
+    return float(_load().orc_lower_cost(C.byref(par), _pd(p), _pd(xi)))
+
+
+def step1(par: Params, scene: Scene, p) -> np.ndarray:
+    p = _f64(p).reshape(-1, NP)
+    out = np.zeros((p.shape[0], NX))
+    sc = scene.c()
+    rc = _load().orc_step1(C.byref(par), C.byref(sc), _pd(p), p.shape[0], _pd(out))
+    if rc != 0:
+        raise RuntimeError("oracle step1 failed: singular KKT")
+    return out
+
+
+def project(par: Params, scene: Scene, xi_bar, return_iterates: bool = False):
+    xb = _f64(xi_bar).reshape(-1, NX)
+    N = xb.shape[0]
+    out = np.zeros((N, NX))
+    it = np.zeros((N, par.K + 1, NX)) if return_iterates else None
+    sc = scene.c()
+    _load().orc_project(C.byref(par), C.byref(sc), _pd(xb), N, _pd(out),
+                        _pd(it) if it is not None else None)
+    return (out, it) if return_iterates else out
+
+
+def targets(par: Params, scene: Scene, xi, da_prev):
+    xi = _f64(xi); da_prev = _f64(da_prev)
+    T, M = par.T, par.M
+    h = np.zeros(2 * (M + 2) * T); s = np.zeros(2 * T); da = np.zeros(T)
+    sc = scene.c()
+    _load().orc_targets(C.byref(par), C.byref(sc), _pd(xi), _pd(da_prev),
+                        _pd(h), _pd(s), _pd(da))
+    return h, s, da
+
+
+def residual_cost(par: Params, scene: Scene, xi):
+    xi = _f64(xi).reshape(-1, NX)
+    N = xi.shape[0]
+    r = np.zeros(N); cu = np.zeros(N)
+    sc = scene.c()
+    _load().orc_residual_cost(C.byref(par), C.byref(sc), _pd(xi), N, _pd(r), _pd(cu))
+    return r, cu
+
+
+def select(r, cu, n: int, q: int):
+    r = _f64(r); cu = _f64(cu)
+    ces = np.zeros(n, np.int32); es = np.zeros(q, np.int32); c_es = np.zeros(q)
+    _load().orc_select(_pd(r), _pd(cu), r.size, int(n), int(q), _pi(ces), _pi(es), _pd(c_es))
+    return ces, es, c_es
+
+
+def update(par: Params, mu, Sigma, p, es, c_es):
+    mu = _f64(mu); Sigma = _f64(Sigma); p = _f64(p).reshape(-1, NP)
+    es = np.ascontiguousarray(np.asarray(es, np.int32)); c_es = _f64(c_es)
+    mo = np.zeros(NP); So = np.zeros((NP, NP))
+    _load().orc_update(C.byref(par), _pd(mu), _pd(Sigma), _pd(p), _pi(es), _pd(c_es),
+                       es.size, _pd(mo), _pd(So))
+    return mo, So
+
+
+def cholesky(A, jitter: float = 0.0):
+    A = _f64(A)
+    n = A.shape[0]
+    L = np.zeros((n, n))
+    rc = _load().orc_cholesky(_pd(A), n, float(jitter), _pd(L))
+    if rc != 0:
+        raise np.linalg.LinAlgError("oracle cholesky: not positive definite")
+    return L
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(v) & 0xffffffff for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    o = (C.c_uint32 * 4)()
+    _load().orc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def initial_moments(par: Params):
+    mu = np.zeros(NP); S = np.zeros((NP, NP))
+    _load().orc_initial_moments(C.byref(par), _pd(mu), _pd(S))
+    return mu, S
+
+
+def sample(par: Params, seed: int, l: int, N: int, structured: bool,
+           mu=None, Lchol=None) -> np.ndarray:
+    mu = _f64(mu if mu is not None else np.zeros(NP))
+    Lc = _f64(Lchol if Lchol is not None else np.eye(NP))
+    p = np.zeros((N, NP))
+    _load().orc_sample(C.byref(par), C.c_uint64(int(seed)), int(l), int(N),
+                       1 if structured else 0, _pd(mu), _pd(Lc), _pd(p))
+    return p
+
+
+@dataclass
+class PlanResult:
+    best_index: int
+    p_best: np.ndarray
+    xi_best: np.ndarray
+    cost_upper: float
+    residual: float
+    mu: np.ndarray
+    Sigma: np.ndarray
+    trace: dict | None = None
+
+
+def plan(par: Params, scene: Scene, seed: int, N: int, mu0=None, Sigma0=None,
+         trace: bool = False) -> PlanResult:
+    """Alg. 1 with the lower level of Alg. 2, FP64."""
+    n, q = elite_sizes(par, N)
+    L = par.L
+    out = _PlanOut()
+    tr = None
+    arrays = None
+    if trace:
+        arrays = dict(p=np.zeros((L, N, NP)), xi_bar=np.zeros((L, N, NX)),
+                      xi_star=np.zeros((L, N, NX)), r=np.zeros((L, N)),
+                      cu=np.zeros((L, N)), ces=np.zeros((L, n), np.int32),
+                      es=np.zeros((L, q), np.int32), c_es=np.zeros((L, q)),
+                      mu=np.zeros((L, NP)), Sigma=np.zeros((L, NP, NP)))
+        tr = _Trace()
+        for k, v in arrays.items():
+            setattr(tr, k, _pi(v) if v.dtype == np.int32 else _pd(v))
+    sc = scene.c()
+    m0 = _f64(mu0) if mu0 is not None else None
+    S0 = _f64(Sigma0) if Sigma0 is not None else None
+    rc = _load().orc_plan(C.byref(par), C.byref(sc), C.c_uint64(int(seed)), int(N),
+                          _pd(m0) if m0 is not None else None,
+                          _pd(S0) if S0 is not None else None,
+                          C.byref(out), C.byref(tr) if tr is not None else None)
+    if rc != 0:
+        raise RuntimeError(f"oracle plan failed rc={rc}")
+    return PlanResult(out.best_index, np.array(out.p_best), np.array(out.xi_best),
+                      out.cost_upper, out.residual, np.array(out.mu),
+                      np.array(out.Sigma).reshape(NP, NP), arrays)
