@@ -1,0 +1,148 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched bi-level planner on one MI355X.
+
+Workload: one plan at paper-like scale (Alg. 1 with its lower level):
+N = 1000 behavioural samples, T = 100 instants over 5 s, M = 10 neighbours,
+L = 5 upper iterations, K = 20 projection iterations, FP32, on a seeded
+synthetic highway scene. One step = one whole plan (sampling, Step-1 QP,
+projection, residual/cost, elite selection, distribution update for all 5
+upper iterations) with its inputs already resident in HBM.
+
+Metric: lower-level QP solves per second = N * L / plan time.
+
+Prints one JSON line (see the keys below), including the roofline of the
+dominant kernel (lower_kernel, timed with HIP events on the library's stream
+over the timed region) and the FP64 oracle timed on host cores on the same
+scene.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "lower-level QP solves/sec at ≤1e-4 m error; p99 plan latency (served)"
+CFG_ID = 2
+PEAK_ALU_TFLOPS = 78.6  # FP32 FMA without packed math: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+
+def lower_flops_per_sample(T: int, M: int, K: int) -> float:
+    """Algorithmic FP32 operations of one lower-level solve (FMA = 2,
+    other arithmetic and transcendental = 1): Step 1 through its affine map,
+    K target passes and xi-updates of Alg. 2 in the free coordinates, and the
+    residual/cost pass. Per instant of a target pass: trajectory evaluation
+    (45 FMA + 6 adds), 8 per neighbour (distance test), ~40 for the
+    velocity/acceleration polar step and clips, 3 for the lane, 45 FMA for
+    the accumulation of N^T g; per xi-update 271 (+30 for the multiplier);
+    residual pass 126 + 9 M per instant."""
+    step1 = 15 * 12 * 2
+    per_pass_instant = 96 + 8 * M + 40 + 3 + 90
+    per_update = 271 + 30
+    residual = T * (126 + 9 * M)
+    return step1 + K * per_update + K * T * per_pass_instant + residual
+
+
+def cpu_baseline(scene, c, threads: int):
+    import oracle
+    oracle.build(force=False)
+    oracle.set_threads(threads)
+    par = oracle.default_params(T=c["T"], M=c["M"], K=c["K"], L=c["L"])
+    sc = oracle.Scene(scene.ego, scene.obstacles)
+    N = c["N"] if threads >= 4 else 250
+    t0 = time.perf_counter()
+    oracle.plan(par, sc, scene.seed, N)
+    dt = time.perf_counter() - t0
+    return {"value": N * c["L"] / dt, "unit": "QP-solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full plan of the same scene: N={N} L={c['L']} K={c['K']} T={c['T']} M={c['M']}, "
+                      f"FP64, OpenMP over samples ({dt:.2f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): requests are independent, "
+              "so more GPUs would each run their own share; no multi-GPU figure is produced.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2212_02224_amd as pl
+    from paper_2212_02224_amd import workload
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    c = workload.CONFIGS[CFG_ID]
+    N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
+    cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=1)
+    ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    h = pl.plan_create(cfg, workspace=ws, stream=stream.cuda_stream)
+    scene = workload.scene(CFG_ID, 0, M)
+    req = pl.Request(N=N, T=T, ego=scene.ego, obstacles=scene.obstacles, seed=scene.seed)
+    pl.plan_stage(h, [req])  # inputs into HBM before the timed region
+
+    for _ in range(args.warmup):
+        pl.plan_launch(h)
+    torch.cuda.synchronize()
+    pl.plan_profile(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pl.plan_launch(h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, cnt = pl.plan_profile_read(h)
+    pl.plan_profile(h, False)
+    res = pl.plan_collect(h)[0]
+    if res.status != 0:
+        print(f"plan failed: {pl.plan_last_error(h)}", file=sys.stderr)
+        return 1
+
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N * L * args.steps / elapsed
+    lower_avg_ms = ms["lower"] / max(1, cnt["lower"])
+    flop = N * lower_flops_per_sample(T, M, K)
+    achieved = flop / (lower_avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "QP-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": c["name"] + f"-L{L}-K{K}", "N": N, "T": T, "M": M, "L": L, "K": K,
+                   "requests_per_step": 1},
+        "roofline": {"bound": "alu", "kernel": "lower_kernel", "achieved": achieved,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": None, "avg_ms": lower_avg_ms, "flop_per_launch": flop,
+                     "launches": cnt["lower"]},
+        "kernel_ms_per_step": {k: ms[k] / args.steps for k in ms},
+        "plan": {"best_index": res.best_index, "cost_upper": res.cost_upper, "residual": res.residual},
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(scene, c, threads)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,241 @@
+/*
+ * plan.h -- C ABI of the MI355X batched bi-level trajectory planner.
+ *
+ * The library implements the data-parallel hot path of the bi-level planner
+ * of Singh, Shrestha and Albarella, "Bi-Level Optimization Augmented with
+ * Conditional Variational Autoencoder for Autonomous Driving in Dense
+ * Traffic" (arXiv 2212.02224):
+ *
+ *   Alg. 1 (Sec. III-B)   sample behavioural inputs p_j ~ N(mu, Sigma);
+ *                         solve the lower level for every p_j; residual r_j;
+ *                         ConstraintEliteSet (n lowest r), EliteSet (q lowest
+ *                         c_u + r); update mu, Sigma (eqs. mean_update,
+ *                         cov_update, s_formula); repeat; return the best.
+ *   lower level           Step 1: equality-constrained QP (Sec. III-C,
+ *                         eqs. over_2 / over_3), Step 2: projection onto the
+ *                         constraints of Table ineq_list by the alternating
+ *                         minimisation of Alg. 2 (App. "GPU Accelerated Batch
+ *                         Projection", eqs. aug_lag .. update_lagrange).
+ *
+ * Every step runs in HIP kernels on the GPU. The host part only validates,
+ * precomputes the sample-independent matrices in FP64 once (Sec. III-C: the
+ * KKT inverse is computed once, irrespective of the batch size), and moves
+ * a few hundred bytes per request.
+ *
+ * Conventions
+ *   - Coordinates: x along the road (Frenet frame, Sec. II-C), y lateral.
+ *   - xi = (c_x, c_y): 22 Bernstein coefficients of degree 10 on
+ *     tau = t / t_f, c_x first (eq. param, Sec. V-A).
+ *   - p = [y_d1..y_d4, v_d1..v_d4] (eq. behaviour_param, Sec. V-A): lateral
+ *     offset and longitudinal velocity set-points of 4 equal horizon parts.
+ *   - Time grid t_k = k t_f / (T - 1), k = 0..T-1.
+ *   - All host arrays are row-major and owned by the caller unless stated.
+ *   - Every function returns a plan_status; nothing throws across the ABI.
+ *     plan_last_error() gives a message for the last failing call.
+ *   - A handle is not thread-safe; one host thread drives it.
+ */
+#ifndef PLAN_H
+#define PLAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLAN_NC 11      /* coefficients per axis (10th-order polynomial)  */
+#define PLAN_NX 22      /* coefficients of xi                              */
+#define PLAN_NP 8       /* behavioural inputs                              */
+#define PLAN_MAX_T 256  /* horizon samples per request                    */
+#define PLAN_MAX_M 32   /* neighbouring vehicles per request              */
+#define PLAN_MAX_N 4096 /* behavioural samples per request                */
+#define PLAN_MAX_L 16   /* upper-level iterations                         */
+
+typedef enum plan_status {
+  PLAN_OK = 0,
+  PLAN_E_INVALID = -1,     /* bad argument or request (NaN, T/M/N out of set) */
+  PLAN_E_NOMEM = -2,       /* workspace / HBM budget too small               */
+  PLAN_E_DEVICE = -3,      /* HIP runtime error                              */
+  PLAN_E_BUSY = -4,        /* plan_poll: not finished yet                    */
+  PLAN_E_UNSUPPORTED = -5  /* configuration the library does not implement   */
+} plan_status;
+
+/* plan_result.flags */
+#define PLAN_F_INFEASIBLE 1u /* the returned trajectory has residual r > 0 */
+#define PLAN_F_WARM 2u       /* iteration 0 sampled from a warm start       */
+
+typedef enum plan_precision {
+  PLAN_PREC_FP32 = 0 /* every lower-level product and evaluation in FP32 */
+} plan_precision;
+
+/*
+ * Configuration. plan_config_init() fills the defaults; every point the paper
+ * leaves open is a field here.
+ *   T_set/M_set     horizon lengths and obstacle counts that get precomputed
+ *                   matrices; a request must use one of each.
+ *   t_f             horizon [s].
+ *   max_N           largest sample count of a request (<= PLAN_MAX_N).
+ *   max_requests    request slots resident on the device at once.
+ *   proj_iters      K, iterations of Alg. 2 (its maxiter).
+ *   upper_iters     L, iterations of Alg. 1 (its N).
+ *   frac_ces/es     n = max(q, round(frac_ces N)), q = max(1, round(frac_es N))
+ *                   (150 and 50 of 1000 in Sec. V-A).
+ *   eta, gamma      learning rate and temperature of eqs. mean_update,
+ *                   cov_update, s_formula (gamma = 0.9 in Sec. V-A).
+ *   rho             penalty of eq. aug_lag.
+ *   k_p, k_v        PD gains and w_s, w_l, w_v weights of c_s, c_l, c_v
+ *                   (Sec. II-C).
+ *   cov_jitter      epsilon of chol(Sigma + eps I) before sampling.
+ *   v_min .. y_ub   bounds of Table ineq_list; ell_a, ell_b the ellipse
+ *                   denominators of its collision row; v_eps the speed floor
+ *                   of the curvature residual.
+ *   lane_c, lane_sigma, vd_lo, vd_hi   the structured initial sampler (used
+ *                   when a request has no warm start).
+ *   device_workspace/workspace_bytes   optional caller-owned device memory
+ *                   (e.g. a torch tensor); NULL lets the library allocate.
+ *                   The size is the HBM budget: see plan_workspace_bytes().
+ *   stream          hipStream_t the library enqueues on (NULL: its own).
+ */
+typedef struct plan_config {
+  int32_t T_set[4];
+  int32_t n_T;
+  int32_t M_set[8];
+  int32_t n_M;
+  double t_f;
+  int32_t max_N;
+  int32_t max_requests;
+  int32_t proj_iters;
+  int32_t upper_iters;
+  double frac_ces, frac_es;
+  double eta, gamma, rho;
+  double k_p, k_v, w_s, w_l, w_v;
+  double cov_jitter;
+  double v_min, v_max, a_max, kappa_max, c_max, y_lb, y_ub;
+  double ell_a, ell_b, v_eps;
+  double lane_c[3];
+  double lane_sigma, vd_lo, vd_hi;
+  int32_t precision;
+  int32_t trace; /* nonzero: keep per-iteration elite sets and mu, Sigma */
+  void *device_workspace;
+  size_t workspace_bytes;
+  void *stream;
+} plan_config;
+
+/*
+ * One planning request (one call of Alg. 1).
+ *   request_id   caller's tag, echoed nowhere but useful for logs.
+ *   session_id   key of the device-resident warm start (0 = none): after a
+ *                request of a session finishes, its mu, Sigma stay on the
+ *                device and seed the next request of that session
+ *                (warm start across planning cycles, Sec. IV).
+ *   seed         64-bit key of the sample stream (Philox4x32-10).
+ *   N, M, T      samples, neighbours, horizon samples.
+ *   ego          b_0 = (x0, y0, vx0, vy0, ax0, ay0) (eq. boundary_cond_initial).
+ *   obstacles    host, M x 4 doubles: (x, y, vx, vy) at t = 0; neighbours move
+ *                at constant velocity x_o(t) = x + vx t (Fig. learned_sampler).
+ *   kappa_road   road curvature (0: straight road).
+ *   mu0, sigma0  optional initial distribution (8, 8x8); if NULL the session
+ *                warm start is used, else the structured initial sampler.
+ *   first_iter   index of the first upper iteration (normally 0). It keys
+ *                the sample stream, so a request started from the
+ *                distribution of iteration l with first_iter = l draws the
+ *                same samples as iteration l of a longer run.
+ */
+typedef struct plan_request {
+  uint64_t request_id;
+  uint64_t session_id;
+  uint64_t seed;
+  int32_t N, M, T;
+  double ego[6];
+  const double *obstacles;
+  double kappa_road;
+  const double *mu0;
+  const double *sigma0;
+  int32_t first_iter;
+} plan_request;
+
+/*
+ * Result of one request (Alg. 1, return step): the sample of the final
+ * EliteSet with the smallest augmented cost c_u + r (ties: lower index), its
+ * behavioural input and projected trajectory, and the sampling distribution
+ * after the last update (the warm start of the next planning cycle).
+ */
+typedef struct plan_result {
+  int32_t status;
+  uint32_t flags;
+  int32_t best_index;
+  int32_t iterations;
+  double p_best[PLAN_NP];
+  double xi_best[PLAN_NX];
+  double cost_upper; /* c_u of the best sample */
+  double residual;   /* r of the best sample   */
+  double mu[PLAN_NP];
+  double sigma[PLAN_NP * PLAN_NP];
+  double latency_s;  /* submit -> completion (served path), else solve time */
+} plan_result;
+
+typedef struct plan_handle plan_handle; /* opaque, owned by the library */
+
+/* Fill *cfg with the defaults (T_set {50, 100}, M_set {4, 10, 20}, t_f 5,
+ * K 20, L 5, n/q fractions 0.15/0.05, gamma 0.9, eta 0.6, rho 1, ...). */
+void plan_config_init(plan_config *cfg);
+
+/* Device bytes the library needs for cfg (tables + max_requests slots). */
+size_t plan_workspace_bytes(const plan_config *cfg);
+
+/* Validate cfg, precompute the sample-independent matrices in FP64 (once,
+ * Sec. III-C), and set up device memory. *out receives the handle.
+ * Errors: PLAN_E_INVALID (cfg), PLAN_E_NOMEM (workspace too small),
+ * PLAN_E_DEVICE (HIP). */
+plan_status plan_create(const plan_config *cfg, plan_handle **out);
+
+/* Release everything the handle owns (not the caller's workspace). */
+void plan_destroy(plan_handle *h);
+
+/* Message of the last failing call on h (or of plan_create if h is NULL). */
+const char *plan_last_error(const plan_handle *h);
+
+/* Solve n requests (Alg. 1 each) and wait. out[i] gets request i's result;
+ * a bad request fails alone (its status), the call returns the worst status.
+ * Requests beyond max_requests run in successive groups. */
+plan_status plan_solve_batch(plan_handle *h, const plan_request *reqs,
+                             int32_t n, plan_result *out);
+
+/* Device-resident form of plan_solve_batch for timing with inputs already in
+ * HBM: plan_stage uploads n <= max_requests requests; plan_launch enqueues
+ * the whole hot path of all staged requests on the stream and returns
+ * without waiting (each call repeats the same work from the staged inputs);
+ * plan_collect waits and copies the results out. */
+plan_status plan_stage(plan_handle *h, const plan_request *reqs, int32_t n);
+plan_status plan_launch(plan_handle *h);
+plan_status plan_collect(plan_handle *h, plan_result *out);
+
+/* Lower level only (Alg. 1 Steps 1-2 and the residual/cost) for the given
+ * behavioural inputs p (host, N x 8), one request's scene. Outputs (host,
+ * nullable): xi_bar, xi_star (N x 22), resid, cost_upper (N). */
+plan_status plan_lower_solve(plan_handle *h, const plan_request *req,
+                             const double *p, int32_t N, double *xi_bar,
+                             double *xi_star, double *resid,
+                             double *cost_upper);
+
+/* Per-iteration record of the last plan_solve_batch / plan_collect for
+ * staged request i (needs cfg.trace): samples p (L x N x 8), residuals and
+ * costs (L x N), ConstraintEliteSet (L x n) and EliteSet (L x q) indices,
+ * mu (L x 8) and Sigma (L x 64) after each update. Any pointer may be NULL. */
+plan_status plan_get_trace(plan_handle *h, int32_t i, double *p, double *resid,
+                           double *cost_upper, int32_t *ces, int32_t *es,
+                           double *mu, double *sigma);
+
+/* Kernel timing by HIP events recorded on the library's stream around every
+ * launch of plan_launch / plan_solve_batch. enable != 0 starts recording (and
+ * clears the totals); plan_profile_read waits for the stream and returns the
+ * summed milliseconds and launch counts per kernel: [0] init, [1] lower level
+ * (Steps 1-2 + residual), [2] selection / update. */
+plan_status plan_profile(plan_handle *h, int32_t enable);
+plan_status plan_profile_read(plan_handle *h, double ms[3], int64_t count[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

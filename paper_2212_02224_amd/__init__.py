@@ -1,0 +1,13 @@
+"""MI355X batched bi-level trajectory planner (arXiv 2212.02224 hot path).
+
+The planner runs as HIP kernels in ``libplan.so`` behind the C ABI of
+``include/plan.h``; ``binding`` is its ctypes binding (same names), and
+``workload`` builds seeded synthetic scenes.
+"""
+from .binding import (PLAN_E_BUSY, PLAN_E_DEVICE, PLAN_E_INVALID, PLAN_E_NOMEM,  # noqa: F401
+                      PLAN_E_UNSUPPORTED, PLAN_F_INFEASIBLE, PLAN_F_WARM, PLAN_OK, Handle,
+                      PlanError, Request, Result, elite_sizes, exported_symbols, load,
+                      plan_collect, plan_config_init, plan_create, plan_destroy,
+                      plan_get_trace, plan_last_error, plan_launch, plan_lower_solve,
+                      plan_profile, plan_profile_read, plan_solve_batch, plan_stage,
+                      plan_workspace_bytes)

@@ -1,0 +1,831 @@
+// capi.cpp -- the C ABI of include/plan.h: validation, device memory layout,
+// request staging and the launch sequence of Alg. 1 on a HIP stream.
+//
+// Launch sequence of one batch of resident requests (all on one stream):
+//   init_kernel                         iteration-0 distribution and draw
+//   for l in 0..L-1:
+//     lower_kernel                      Steps 1-2 of Alg. 1 + residual/cost
+//     select_update_kernel(l)           elite sets, update, next draw
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "plan_internal.h"
+#include "precompute.h"
+
+namespace plan {
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds,
+                        hipStream_t st);
+hipError_t launch_init(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st);
+hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, int l, hipStream_t st);
+}  // namespace plan
+
+using namespace plan;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int round_half_up(double v) { return (int)std::floor(v + 0.5); }
+
+void elite_sizes(const plan_config &c, int N, int &n, int &q) {
+  q = std::max(1, round_half_up(c.frac_es * N));
+  n = std::max(q, round_half_up(c.frac_ces * N));
+  n = std::min(n, N);
+  q = std::min(q, n);
+}
+
+bool finite_all(const double *v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+struct DevBuf {
+  char *base = nullptr;
+  size_t used = 0, cap = 0;
+  void *take(size_t bytes) {
+    size_t off = (used + 255) & ~(size_t)255;
+    if (off + bytes > cap) return nullptr;
+    used = off + bytes;
+    return base + off;
+  }
+};
+
+// Device bytes of every region, in allocation order.
+struct Layout {
+  size_t basis = 0, step1 = 0, proj = 0, offs = 0;
+  size_t desc = 0, dist = 0, result = 0, slots = 0;
+  size_t p = 0, zs = 0, rc = 0, blocks = 0, sess = 0, xiout = 0;
+  size_t tr_p = 0, tr_rc = 0, tr_idx = 0, tr_dist = 0;
+  size_t total() const {
+    size_t s = 0;
+    for (size_t b : {basis, step1, proj, offs, desc, dist, result, slots, p, zs, rc, blocks, sess,
+                     xiout, tr_p, tr_rc, tr_idx, tr_dist})
+      s += (b + 255) & ~(size_t)255;
+    return s;
+  }
+};
+
+int max_sessions(const plan_config &c) { return std::max(64, 2 * c.max_requests); }
+
+Layout compute_layout(const plan_config &c) {
+  Layout L;
+  size_t S = (size_t)c.max_requests, N = (size_t)c.max_N;
+  for (int i = 0; i < c.n_T; ++i) L.basis += (size_t)kBasisCols * ((c.T_set[i] + 63) / 64 * 64) * 4;
+  L.step1 = (size_t)c.n_T * kStep1Floats * 4;
+  L.proj = (size_t)c.n_T * c.n_M * kProjFloats * 4;
+  L.offs = (size_t)c.n_T * 2 * 4;
+  L.desc = S * sizeof(ReqDesc);
+  L.dist = S * sizeof(DistState);
+  L.result = S * sizeof(ResultRec);
+  L.slots = S * 4;
+  L.p = S * N * 8 * 4;
+  L.zs = S * N * kZ * 4;
+  L.rc = S * N * 2 * 4;
+  L.blocks = S * N * sizeof(int2);
+  L.sess = (size_t)max_sessions(c) * 72 * 8;
+  L.xiout = N * 22 * 2 * 8;
+  if (c.trace) {
+    int n, q;
+    elite_sizes(c, c.max_N, n, q);
+    size_t Lit = (size_t)c.upper_iters;
+    L.tr_p = S * Lit * N * 8 * 4;
+    L.tr_rc = S * Lit * N * 2 * 4;
+    L.tr_idx = S * Lit * (size_t)(n + q) * 4;
+    L.tr_dist = S * Lit * 72 * 8;
+  }
+  return L;
+}
+
+const char *validate_config(const plan_config &c) {
+  if (c.n_T < 1 || c.n_T > 4 || c.n_M < 1 || c.n_M > 8) return "n_T must be 1..4 and n_M 1..8";
+  for (int i = 0; i < c.n_T; ++i)
+    if (c.T_set[i] < 16 || c.T_set[i] > PLAN_MAX_T) return "T must be in [16, PLAN_MAX_T]";
+  for (int i = 0; i < c.n_M; ++i)
+    if (c.M_set[i] < 0 || c.M_set[i] > PLAN_MAX_M) return "M must be in [0, PLAN_MAX_M]";
+  if (c.max_N < 1 || c.max_N > PLAN_MAX_N) return "max_N must be in [1, PLAN_MAX_N]";
+  if (c.max_requests < 1 || c.max_requests > 65536) return "max_requests must be in [1, 65536]";
+  if (c.proj_iters < 1 || c.proj_iters > 10000) return "proj_iters must be >= 1";
+  if (c.upper_iters < 1 || c.upper_iters > PLAN_MAX_L) return "upper_iters must be in [1, PLAN_MAX_L]";
+  if (!(c.t_f > 0) || !(c.rho > 0) || !(c.gamma > 0) || !(c.eta >= 0 && c.eta <= 1))
+    return "t_f, rho, gamma must be > 0 and eta in [0, 1]";
+  if (!(c.ell_a > 0) || !(c.ell_b > 0) || !(c.kappa_max > 0) || !(c.v_eps > 0))
+    return "ell_a, ell_b, kappa_max, v_eps must be > 0";
+  if (!(c.y_lb < c.y_ub) || !(c.v_min <= c.v_max) || !(c.a_max >= 0) || !(c.c_max >= 0))
+    return "bounds must satisfy y_lb < y_ub, v_min <= v_max, a_max >= 0, c_max >= 0";
+  if (!(c.frac_es > 0) || !(c.frac_ces >= c.frac_es) || c.frac_ces > 1.0)
+    return "need 0 < frac_es <= frac_ces <= 1";
+  int n, q;
+  elite_sizes(c, c.max_N, n, q);
+  if (n > kMaxCes) return "ConstraintEliteSet larger than 1024 samples is not supported";
+  if (c.precision != PLAN_PREC_FP32) return "unsupported precision";
+  return nullptr;
+}
+
+}  // namespace
+
+struct plan_handle {
+  plan_config cfg;
+  MethodParams mp;
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool own_mem = false;
+  DevBuf mem;
+  Layout lay;
+  // tables
+  float *basis = nullptr, *step1 = nullptr, *proj = nullptr;
+  int32_t *basis_off = nullptr, *basis_tpad = nullptr;
+  // slots
+  ReqDesc *desc = nullptr;
+  DistState *dist = nullptr;
+  ResultRec *result = nullptr;
+  int32_t *slots = nullptr;
+  float *p = nullptr, *zs = nullptr, *resid = nullptr, *cost = nullptr;
+  int2 *blocks = nullptr;
+  double *sess = nullptr;
+  double *xi_out = nullptr;
+  float *tr_p = nullptr, *tr_r = nullptr, *tr_c = nullptr;
+  int32_t *tr_ces = nullptr, *tr_es = nullptr;
+  double *tr_mu = nullptr, *tr_sigma = nullptr;
+  int max_ces = 0, max_es = 0;
+  // host staging (pinned)
+  ReqDesc *h_desc = nullptr;
+  int2 *h_blocks = nullptr;
+  int32_t *h_slots = nullptr;
+  ResultRec *h_result = nullptr;
+  // staged batch
+  int staged = 0;                  // requests staged (slots 0..staged-1)
+  int nblocks = 0;
+  size_t lds = 0;
+  std::vector<int> staged_req;     // original request index per slot
+  std::vector<int> staged_status;  // per original request in the last stage
+  int staged_total = 0;
+  std::vector<uint64_t> staged_session;
+  std::chrono::steady_clock::time_point t_stage;
+  // sessions
+  std::unordered_map<uint64_t, int> sess_index;
+  std::vector<uint64_t> sess_key;
+  std::vector<uint64_t> sess_used;
+  std::vector<char> sess_valid;
+  uint64_t sess_clock = 0;
+  // kernel timing
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_count[3] = {0, 0, 0};
+};
+
+namespace {
+
+plan_status fail(plan_handle *h, plan_status st, const std::string &msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+plan_status hip_fail(plan_handle *h, hipError_t e, const char *what) {
+  return fail(h, PLAN_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, expr)                                   \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
+  } while (0)
+
+MethodParams method_params(const plan_config &c) {
+  MethodParams m;
+  m.t_f = c.t_f;
+  m.rho = c.rho;
+  m.ell_a = c.ell_a;
+  m.ell_b = c.ell_b;
+  m.v_min = c.v_min;
+  m.v_max = c.v_max;
+  m.a_max = c.a_max;
+  m.kappa_max = c.kappa_max;
+  m.c_max = c.c_max;
+  m.y_lb = c.y_lb;
+  m.y_ub = c.y_ub;
+  m.v_eps = c.v_eps;
+  m.eta = c.eta;
+  m.gamma = c.gamma;
+  m.cov_jitter = c.cov_jitter;
+  for (int i = 0; i < 3; ++i) m.lane_c[i] = c.lane_c[i];
+  m.lane_sigma = c.lane_sigma;
+  m.vd_lo = c.vd_lo;
+  m.vd_hi = c.vd_hi;
+  m.K = c.proj_iters;
+  m.L = c.upper_iters;
+  return m;
+}
+
+int find_T(const plan_config &c, int T) {
+  for (int i = 0; i < c.n_T; ++i)
+    if (c.T_set[i] == T) return i;
+  return -1;
+}
+int find_M(const plan_config &c, int M) {
+  for (int i = 0; i < c.n_M; ++i)
+    if (c.M_set[i] == M) return i;
+  return -1;
+}
+
+// Validate one request; fill its descriptor (init_mode resolved by caller).
+const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &d) {
+  const plan_config &c = h->cfg;
+  if (r.N < 1 || r.N > c.max_N) return "N out of range";
+  int ti = find_T(c, r.T), mi = find_M(c, r.M);
+  if (ti < 0) return "T not in T_set";
+  if (mi < 0) return "M not in M_set";
+  if ((size_t)r.M * r.T * sizeof(float2) > 60 * 1024) return "M * T too large for the LDS table";
+  if (!finite_all(r.ego, 6) || !std::isfinite(r.kappa_road)) return "non-finite ego state";
+  if (r.M > 0 && r.obstacles == nullptr) return "obstacles missing";
+  if (r.M > 0 && !finite_all(r.obstacles, 4 * r.M)) return "non-finite obstacle";
+  if ((r.mu0 == nullptr) != (r.sigma0 == nullptr)) return "mu0 and sigma0 must be given together";
+  if (r.mu0 && (!finite_all(r.mu0, 8) || !finite_all(r.sigma0, 64))) return "non-finite mu0/sigma0";
+  std::memset(&d, 0, sizeof(d));
+  d.T = r.T;
+  d.M = r.M;
+  d.N = r.N;
+  elite_sizes(c, r.N, d.n_ces, d.n_es);
+  d.t_idx = ti;
+  d.tm_idx = ti * c.n_M + mi;
+  d.session = -1;
+  d.session_wb = -1;
+  d.seed = r.seed;
+  if (r.first_iter < 0 || r.first_iter > (1 << 20)) return "first_iter out of range";
+  d.first_iter = r.first_iter;
+  std::memcpy(d.ego, r.ego, sizeof(d.ego));
+  d.kappa = r.kappa_road;
+  for (int i = 0; i < r.M; ++i)
+    for (int k = 0; k < 4; ++k) d.obs[i][k] = r.obstacles[4 * i + k];
+  if (r.mu0) {
+    std::memcpy(d.mu0, r.mu0, sizeof(d.mu0));
+    std::memcpy(d.sigma0, r.sigma0, sizeof(d.sigma0));
+    d.init_mode = kInitGiven;
+  } else {
+    d.init_mode = kInitStructured;
+  }
+  return nullptr;
+}
+
+int session_slot(plan_handle *h, uint64_t key) {
+  auto it = h->sess_index.find(key);
+  if (it != h->sess_index.end()) {
+    h->sess_used[it->second] = ++h->sess_clock;
+    return it->second;
+  }
+  int ns = (int)h->sess_key.size();
+  int victim = 0;
+  for (int i = 1; i < ns; ++i)
+    if (h->sess_used[i] < h->sess_used[victim]) victim = i;
+  if (h->sess_key[victim] != 0) h->sess_index.erase(h->sess_key[victim]);
+  h->sess_key[victim] = key;
+  h->sess_used[victim] = ++h->sess_clock;
+  h->sess_valid[victim] = 0;
+  h->sess_index[key] = victim;
+  return victim;
+}
+
+SelArgs sel_args(plan_handle *h) {
+  SelArgs a;
+  a.desc = h->desc;
+  a.slots = h->slots;
+  a.p = h->p;
+  a.zs = h->zs;
+  a.resid = h->resid;
+  a.cost = h->cost;
+  a.dist = h->dist;
+  a.result = h->result;
+  a.sess = h->sess;
+  a.tr_p = h->tr_p;
+  a.tr_r = h->tr_r;
+  a.tr_c = h->tr_c;
+  a.tr_ces = h->tr_ces;
+  a.tr_es = h->tr_es;
+  a.tr_mu = h->tr_mu;
+  a.tr_sigma = h->tr_sigma;
+  a.max_N = h->cfg.max_N;
+  a.max_ces = h->max_ces;
+  a.max_es = h->max_es;
+  return a;
+}
+
+LowerArgs lower_args(plan_handle *h) {
+  LowerArgs a;
+  a.desc = h->desc;
+  a.blocks = h->blocks;
+  a.basis = h->basis;
+  a.basis_off = h->basis_off;
+  a.basis_tpad = h->basis_tpad;
+  a.step1 = h->step1;
+  a.proj = h->proj;
+  a.p = h->p;
+  a.zs = h->zs;
+  a.resid = h->resid;
+  a.cost = h->cost;
+  a.xi_bar_out = nullptr;
+  a.xi_star_out = nullptr;
+  a.max_N = h->cfg.max_N;
+  a.obs_stride = 0;
+  return a;
+}
+
+
+
+// Stage requests into slots 0..k-1: host descriptors and the workgroup table,
+// then one H2D copy each. Invalid requests are reported and skipped.
+plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int first) {
+  h->staged = 0;
+  h->nblocks = 0;
+  h->lds = 0;
+  h->staged_req.clear();
+  h->staged_session.clear();
+  h->staged_status.assign(n, PLAN_OK);
+  h->staged_total = n;
+  std::unordered_map<uint64_t, int> last_of_session;
+  for (int i = 0; i < n; ++i)
+    if (reqs[i].session_id != 0) last_of_session[reqs[i].session_id] = i;
+  for (int i = 0; i < n; ++i) {
+    if (h->staged >= h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more requests than max_requests");
+    ReqDesc &d = h->h_desc[h->staged];
+    if (const char *why = check_request(h, reqs[i], d)) {
+      h->staged_status[i] = PLAN_E_INVALID;
+      h->err = "request " + std::to_string(first + i) + ": " + why;
+      continue;
+    }
+    const uint64_t sk = reqs[i].session_id;
+    if (sk != 0) {
+      int s = session_slot(h, sk);
+      if (d.init_mode == kInitStructured && h->sess_valid[s]) {
+        d.init_mode = kInitSession;  // device-resident warm start
+        d.session = s;
+      }
+      if (last_of_session[sk] == i) d.session_wb = s;
+    }
+    const int slot = h->staged++;
+    h->staged_req.push_back(i);
+    h->staged_session.push_back(sk);
+    const int nw = (d.T + kWave - 1) / kWave, spb = 4 / nw;
+    const int nb = (d.N + spb - 1) / spb;
+    for (int b = 0; b < nb; ++b) h->h_blocks[h->nblocks + b] = make_int2(slot, b * spb);
+    h->nblocks += nb;
+    h->lds = std::max(h->lds, (size_t)d.M * d.T * sizeof(float2));
+    h->h_slots[slot] = slot;
+  }
+  if (h->staged == 0) return PLAN_OK;
+  HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc) * h->staged, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->blocks, h->h_blocks, sizeof(int2) * h->nblocks, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->slots, h->h_slots, sizeof(int32_t) * h->staged, hipMemcpyHostToDevice, h->stream));
+  return PLAN_OK;
+}
+
+// Event pair around one launch when profiling (kind: 0 init, 1 lower, 2 select).
+hipError_t prof_begin(plan_handle *h, std::pair<hipEvent_t, hipEvent_t> &ev) {
+  if (h->ev_free.empty()) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    h->ev_free.push_back({a, b});
+  }
+  ev = h->ev_free.back();
+  h->ev_free.pop_back();
+  return hipEventRecord(ev.first, h->stream);
+}
+
+hipError_t prof_end(plan_handle *h, int kind, std::pair<hipEvent_t, hipEvent_t> ev) {
+  h->ev_pending.push_back({kind, ev});
+  return hipEventRecord(ev.second, h->stream);
+}
+
+template <class F>
+plan_status timed(plan_handle *h, int kind, F &&launch, const char *what) {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (h->profiling) HIP_TRY(h, prof_begin(h, ev));
+  hipError_t e = launch();
+  if (e != hipSuccess) return hip_fail(h, e, what);
+  if (h->profiling) HIP_TRY(h, prof_end(h, kind, ev));
+  return PLAN_OK;
+}
+
+plan_status launch_impl(plan_handle *h) {
+  if (h->staged == 0) return PLAN_OK;
+  const SelArgs sa = sel_args(h);
+  const LowerArgs la = lower_args(h);
+  plan_status st = timed(h, 0, [&] { return launch_init(sa, h->mp, h->staged, h->stream); }, "init_kernel");
+  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) {
+    st = timed(h, 1, [&] { return launch_lower(la, h->mp, h->nblocks, h->lds, h->stream); }, "lower_kernel");
+    if (st == PLAN_OK)
+      st = timed(h, 2, [&] { return launch_select(sa, h->mp, h->staged, l, h->stream); }, "select_update_kernel");
+  }
+  return st;
+}
+
+// Wait for the staged batch and copy results into out[0..staged_total).
+plan_status collect_impl(plan_handle *h, plan_result *out, double elapsed) {
+  std::vector<DistState> ds(h->staged);
+  if (h->staged > 0) {
+    HIP_TRY(h, hipMemcpyAsync(h->h_result, h->result, sizeof(ResultRec) * h->staged, hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipMemcpyAsync(ds.data(), h->dist, sizeof(DistState) * h->staged, hipMemcpyDeviceToHost,
+                              h->stream));
+  }
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  plan_status worst = PLAN_OK;
+  for (int i = 0; i < h->staged_total; ++i) {
+    std::memset(&out[i], 0, sizeof(plan_result));
+    out[i].status = h->staged_status[i];
+    out[i].best_index = -1;
+    if (out[i].status != PLAN_OK) worst = std::min(worst, (plan_status)out[i].status);
+  }
+  for (int s = 0; s < h->staged; ++s) {
+    plan_result &o = out[h->staged_req[s]];
+    const ResultRec &R = h->h_result[s];
+    o.status = R.status;
+    o.flags = R.flags;
+    o.best_index = R.best;
+    o.iterations = R.iterations;
+    std::memcpy(o.p_best, R.p, sizeof(o.p_best));
+    std::memcpy(o.xi_best, R.xi, sizeof(o.xi_best));
+    o.cost_upper = R.cost_upper;
+    o.residual = R.residual;
+    std::memcpy(o.mu, ds[s].mu, sizeof(o.mu));
+    std::memcpy(o.sigma, ds[s].sigma, sizeof(o.sigma));
+    o.latency_s = elapsed;
+    if (R.status != 0) {
+      worst = std::min(worst, (plan_status)R.status);
+    } else if (h->h_desc[s].session_wb >= 0) {
+      h->sess_valid[h->h_desc[s].session_wb] = 1;
+    }
+  }
+  return worst;
+}
+
+void free_handle(plan_handle *h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  for (auto &e : h->ev_free) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  for (auto &e : h->ev_pending) {
+    hipEventDestroy(e.second.first);
+    hipEventDestroy(e.second.second);
+  }
+  if (h->own_mem && h->mem.base) hipFree(h->mem.base);
+  if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+  if (h->h_desc) hipHostFree(h->h_desc);
+  if (h->h_blocks) hipHostFree(h->h_blocks);
+  if (h->h_slots) hipHostFree(h->h_slots);
+  if (h->h_result) hipHostFree(h->h_result);
+  delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+void plan_config_init(plan_config *c) {
+  std::memset(c, 0, sizeof(*c));
+  c->T_set[0] = 50;
+  c->T_set[1] = 100;
+  c->n_T = 2;
+  c->M_set[0] = 4;
+  c->M_set[1] = 10;
+  c->M_set[2] = 20;
+  c->n_M = 3;
+  c->t_f = 5.0;
+  c->max_N = 1024;
+  c->max_requests = 1;
+  c->proj_iters = 20;
+  c->upper_iters = 5;
+  c->frac_ces = 0.15;
+  c->frac_es = 0.05;
+  c->eta = 0.6;
+  c->gamma = 0.9;
+  c->rho = 1.0;
+  c->k_p = 1.0;
+  c->k_v = 2.0;
+  c->w_s = c->w_l = c->w_v = 1.0;
+  c->cov_jitter = 1e-6;
+  c->v_min = 0.0;
+  c->v_max = 30.0;
+  c->a_max = 8.0;
+  c->kappa_max = 0.2;
+  c->c_max = 4.0;
+  c->y_lb = -7.0;
+  c->y_ub = 7.0;
+  c->ell_a = 4.5;
+  c->ell_b = 2.0;
+  c->v_eps = 0.1;
+  c->lane_c[0] = -3.5;
+  c->lane_c[1] = 0.0;
+  c->lane_c[2] = 3.5;
+  c->lane_sigma = 0.3;
+  c->vd_lo = 5.0;
+  c->vd_hi = 25.0;
+  c->precision = PLAN_PREC_FP32;
+}
+
+size_t plan_workspace_bytes(const plan_config *cfg) {
+  if (!cfg || validate_config(*cfg)) return 0;
+  return compute_layout(*cfg).total() + 4096;
+}
+
+const char *plan_last_error(const plan_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+plan_status plan_create(const plan_config *cfg, plan_handle **out) {
+  if (!cfg || !out) {
+    g_create_error = "null argument";
+    return PLAN_E_INVALID;
+  }
+  *out = nullptr;
+  if (const char *why = validate_config(*cfg)) {
+    g_create_error = why;
+    return PLAN_E_INVALID;
+  }
+  plan_handle *h = new plan_handle();
+  h->cfg = *cfg;
+  h->mp = method_params(*cfg);
+  const plan_config &c = h->cfg;
+  // ---- FP64 precompute, once per T and per (T, M)
+  std::vector<BasisTable> bts(c.n_T);
+  std::vector<Step1Table> s1(c.n_T);
+  std::vector<ProjTable> pj((size_t)c.n_T * c.n_M);
+  try {
+    const CostWeights cw{c.k_p, c.k_v, c.w_s, c.w_l, c.w_v};
+    for (int i = 0; i < c.n_T; ++i) {
+      build_basis(c.T_set[i], c.t_f, bts[i]);
+      build_step1(bts[i], cw, c.t_f, s1[i]);
+      for (int m = 0; m < c.n_M; ++m) build_proj(bts[i], c.M_set[m], c.rho, pj[(size_t)i * c.n_M + m]);
+    }
+  } catch (const std::exception &e) {
+    g_create_error = std::string("precompute failed: ") + e.what();
+    delete h;
+    return PLAN_E_INVALID;
+  }
+  // ---- device memory: caller's workspace or our own allocation
+  h->lay = compute_layout(c);
+  const size_t need = h->lay.total() + 4096;
+  if (c.device_workspace) {
+    if (c.workspace_bytes < need) {
+      g_create_error = "workspace too small: need " + std::to_string(need) + " bytes";
+      delete h;
+      return PLAN_E_NOMEM;
+    }
+    h->mem.base = (char *)c.device_workspace;
+    h->mem.cap = c.workspace_bytes;
+  } else {
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, need);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+      delete h;
+      return e == hipErrorOutOfMemory ? PLAN_E_NOMEM : PLAN_E_DEVICE;
+    }
+    h->mem.base = (char *)ptr;
+    h->mem.cap = need;
+    h->own_mem = true;
+  }
+  const Layout &L = h->lay;
+  const size_t S = (size_t)c.max_requests, N = (size_t)c.max_N;
+  h->basis = (float *)h->mem.take(L.basis);
+  h->step1 = (float *)h->mem.take(L.step1);
+  h->proj = (float *)h->mem.take(L.proj);
+  h->basis_off = (int32_t *)h->mem.take(L.offs);
+  h->basis_tpad = h->basis_off + c.n_T;
+  h->desc = (ReqDesc *)h->mem.take(L.desc);
+  h->dist = (DistState *)h->mem.take(L.dist);
+  h->result = (ResultRec *)h->mem.take(L.result);
+  h->slots = (int32_t *)h->mem.take(L.slots);
+  h->p = (float *)h->mem.take(L.p);
+  h->zs = (float *)h->mem.take(L.zs);
+  h->resid = (float *)h->mem.take(L.rc);
+  h->cost = h->resid + S * N;
+  h->blocks = (int2 *)h->mem.take(L.blocks);
+  h->sess = (double *)h->mem.take(L.sess);
+  h->xi_out = (double *)h->mem.take(L.xiout);
+  elite_sizes(c, c.max_N, h->max_ces, h->max_es);
+  if (c.trace) {
+    h->tr_p = (float *)h->mem.take(L.tr_p);
+    h->tr_r = (float *)h->mem.take(L.tr_rc);
+    h->tr_c = h->tr_r + S * c.upper_iters * N;
+    h->tr_ces = (int32_t *)h->mem.take(L.tr_idx);
+    h->tr_es = h->tr_ces + S * c.upper_iters * h->max_ces;
+    h->tr_mu = (double *)h->mem.take(L.tr_dist);
+    h->tr_sigma = h->tr_mu + S * c.upper_iters * 8;
+  }
+  if (!h->xi_out) {
+    g_create_error = "internal: workspace carve failed";
+    free_handle(h);
+    return PLAN_E_NOMEM;
+  }
+  h->sess_key.assign(max_sessions(c), 0);
+  h->sess_used.assign(max_sessions(c), 0);
+  h->sess_valid.assign(max_sessions(c), 0);
+  // ---- stream and pinned staging
+  hipError_t e = hipSuccess;
+  if (c.stream) {
+    h->stream = (hipStream_t)c.stream;
+  } else {
+    e = hipStreamCreate(&h->stream);
+    h->own_stream = e == hipSuccess;
+  }
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_desc, sizeof(ReqDesc) * S);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_blocks, sizeof(int2) * S * N);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_slots, sizeof(int32_t) * S);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_result, sizeof(ResultRec) * S);
+  // ---- upload tables
+  if (e == hipSuccess) {
+    std::vector<float> basis_all;
+    std::vector<int32_t> offs(2 * c.n_T);
+    for (int i = 0; i < c.n_T; ++i) {
+      offs[i] = (int32_t)basis_all.size();
+      offs[c.n_T + i] = bts[i].Tpad;
+      basis_all.insert(basis_all.end(), bts[i].table.begin(), bts[i].table.end());
+    }
+    std::vector<float> s1all, pjall;
+    for (auto &t : s1) s1all.insert(s1all.end(), t.table.begin(), t.table.end());
+    for (auto &t : pj) pjall.insert(pjall.end(), t.table.begin(), t.table.end());
+    e = hipMemcpyAsync(h->basis, basis_all.data(), basis_all.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->basis_off, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->step1, s1all.data(), s1all.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->proj, pjall.data(), pjall.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->sess, 0, L.sess, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  }
+  if (e != hipSuccess) {
+    g_create_error = std::string("device setup: ") + hipGetErrorString(e);
+    free_handle(h);
+    return PLAN_E_DEVICE;
+  }
+  *out = h;
+  return PLAN_OK;
+}
+
+void plan_destroy(plan_handle *h) { free_handle(h); }
+
+plan_status plan_stage(plan_handle *h, const plan_request *reqs, int32_t n) {
+  if (!h || (n > 0 && !reqs) || n < 0) return fail(h, PLAN_E_INVALID, "bad arguments");
+  if (n > h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more requests than max_requests");
+  h->t_stage = std::chrono::steady_clock::now();
+  plan_status st = stage_impl(h, reqs, n, 0);
+  if (st != PLAN_OK) return st;
+  return hipStreamSynchronize(h->stream) == hipSuccess ? PLAN_OK : fail(h, PLAN_E_DEVICE, "stage sync");
+}
+
+plan_status plan_launch(plan_handle *h) {
+  if (!h) return PLAN_E_INVALID;
+  return launch_impl(h);
+}
+
+plan_status plan_collect(plan_handle *h, plan_result *out) {
+  if (!h || !out) return fail(h, PLAN_E_INVALID, "bad arguments");
+  double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - h->t_stage).count();
+  return collect_impl(h, out, el);
+}
+
+plan_status plan_solve_batch(plan_handle *h, const plan_request *reqs, int32_t n, plan_result *out) {
+  if (!h || n < 0 || (n > 0 && (!reqs || !out))) return fail(h, PLAN_E_INVALID, "bad arguments");
+  plan_status worst = PLAN_OK;
+  for (int first = 0; first < n; first += h->cfg.max_requests) {
+    const int m = std::min(h->cfg.max_requests, n - first);
+    const auto t0 = std::chrono::steady_clock::now();
+    plan_status st = stage_impl(h, reqs + first, m, first);
+    if (st == PLAN_OK) st = launch_impl(h);
+    if (st != PLAN_OK) return st;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "solve");
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st = collect_impl(h, out + first, el);
+    worst = std::min(worst, st);
+  }
+  return worst;
+}
+
+plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const double *p, int32_t N,
+                             double *xi_bar, double *xi_star, double *resid, double *cost_upper) {
+  if (!h || !req || !p) return fail(h, PLAN_E_INVALID, "bad arguments");
+  plan_request r = *req;
+  r.N = N;
+  r.mu0 = r.sigma0 = nullptr;
+  r.session_id = 0;
+  ReqDesc &d = h->h_desc[0];
+  if (const char *why = check_request(h, r, d)) return fail(h, PLAN_E_INVALID, why);
+  if (!finite_all(p, 8 * N)) return fail(h, PLAN_E_INVALID, "non-finite p");
+  d.init_mode = kInitForced;
+  std::vector<float> pf((size_t)N * 8);
+  for (size_t i = 0; i < pf.size(); ++i) pf[i] = (float)p[i];
+  const int nw = (d.T + kWave - 1) / kWave, spb = 4 / nw;
+  const int nb = (d.N + spb - 1) / spb;
+  for (int b = 0; b < nb; ++b) h->h_blocks[b] = make_int2(0, b * spb);
+  HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->blocks, h->h_blocks, sizeof(int2) * nb, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->p, pf.data(), pf.size() * 4, hipMemcpyHostToDevice, h->stream));
+  LowerArgs la = lower_args(h);
+  la.xi_bar_out = h->xi_out;
+  la.xi_star_out = h->xi_out + (size_t)h->cfg.max_N * 22;
+  HIP_TRY(h, launch_lower(la, h->mp, nb, (size_t)d.M * d.T * sizeof(float2), h->stream));
+  std::vector<double> xo((size_t)N * 22 * 2);
+  std::vector<float> rc((size_t)N * 2);
+  HIP_TRY(h, hipMemcpyAsync(xo.data(), la.xi_bar_out, (size_t)N * 22 * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(xo.data() + (size_t)N * 22, la.xi_star_out, (size_t)N * 22 * 8,
+                            hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(rc.data(), h->resid, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(rc.data() + N, h->cost, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (xi_bar) std::memcpy(xi_bar, xo.data(), (size_t)N * 22 * 8);
+  if (xi_star) std::memcpy(xi_star, xo.data() + (size_t)N * 22, (size_t)N * 22 * 8);
+  for (int j = 0; j < N; ++j) {
+    if (resid) resid[j] = rc[j];
+    if (cost_upper) cost_upper[j] = rc[N + j];
+  }
+  h->staged = 0;  // slot 0 was overwritten
+  return PLAN_OK;
+}
+
+plan_status plan_get_trace(plan_handle *h, int32_t i, double *p, double *resid, double *cost_upper,
+                           int32_t *ces, int32_t *es, double *mu, double *sigma) {
+  if (!h) return PLAN_E_INVALID;
+  if (!h->cfg.trace) return fail(h, PLAN_E_UNSUPPORTED, "trace was not enabled in plan_config");
+  int slot = -1;
+  for (int s = 0; s < h->staged; ++s)
+    if (h->staged_req[s] == i) slot = s;
+  if (slot < 0) return fail(h, PLAN_E_INVALID, "request not in the last staged batch");
+  const ReqDesc &d = h->h_desc[slot];
+  const size_t L = h->cfg.upper_iters, Nmax = h->cfg.max_N, N = d.N;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (size_t l = 0; l < L; ++l) {
+    const size_t tb = ((size_t)slot * L + l) * Nmax;
+    if (p) {
+      std::vector<float> f(N * 8);
+      HIP_TRY(h, hipMemcpy(f.data(), h->tr_p + tb * 8, N * 8 * 4, hipMemcpyDeviceToHost));
+      for (size_t k = 0; k < N * 8; ++k) p[l * N * 8 + k] = f[k];
+    }
+    if (resid || cost_upper) {
+      std::vector<float> f(N);
+      if (resid) {
+        HIP_TRY(h, hipMemcpy(f.data(), h->tr_r + tb, N * 4, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < N; ++k) resid[l * N + k] = f[k];
+      }
+      if (cost_upper) {
+        HIP_TRY(h, hipMemcpy(f.data(), h->tr_c + tb, N * 4, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < N; ++k) cost_upper[l * N + k] = f[k];
+      }
+    }
+    const size_t ib = (size_t)slot * L + l;
+    if (ces)
+      HIP_TRY(h, hipMemcpy(ces + l * d.n_ces, h->tr_ces + ib * h->max_ces, d.n_ces * 4, hipMemcpyDeviceToHost));
+    if (es)
+      HIP_TRY(h, hipMemcpy(es + l * d.n_es, h->tr_es + ib * h->max_es, d.n_es * 4, hipMemcpyDeviceToHost));
+    if (mu) HIP_TRY(h, hipMemcpy(mu + l * 8, h->tr_mu + ib * 8, 64, hipMemcpyDeviceToHost));
+    if (sigma) HIP_TRY(h, hipMemcpy(sigma + l * 64, h->tr_sigma + ib * 64, 512, hipMemcpyDeviceToHost));
+  }
+  return PLAN_OK;
+}
+
+plan_status plan_profile(plan_handle *h, int32_t enable) {
+  if (!h) return PLAN_E_INVALID;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (auto &e : h->ev_pending) h->ev_free.push_back(e.second);
+  h->ev_pending.clear();
+  for (int k = 0; k < 3; ++k) {
+    h->prof_ms[k] = 0.0;
+    h->prof_count[k] = 0;
+  }
+  h->profiling = enable != 0;
+  return PLAN_OK;
+}
+
+plan_status plan_profile_read(plan_handle *h, double ms[3], int64_t count[3]) {
+  if (!h || !ms || !count) return fail(h, PLAN_E_INVALID, "bad arguments");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (auto &e : h->ev_pending) {
+    float t = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&t, e.second.first, e.second.second));
+    h->prof_ms[e.first] += t;
+    h->prof_count[e.first] += 1;
+    h->ev_free.push_back(e.second);
+  }
+  h->ev_pending.clear();
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = h->prof_ms[k];
+    count[k] = h->prof_count[k];
+  }
+  return PLAN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// plan_internal.h -- layouts shared by the host engine and the HIP kernels of
+// the batched bi-level planner (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/plan.h"
+
+namespace plan {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // lower kernel: 4 waves
+constexpr int kSelBlock = 1024;      // selection / update kernel
+constexpr int kZ = 16;               // free coefficients (8 x + 7 y) padded
+constexpr int kBasisCols = 37;       // columns of the per-T basis table
+constexpr int kStep1Floats = 16 * 8 + 16 * 4;
+constexpr int kProjFloats = 16 * 16 + 16;
+constexpr int kMaxCes = 1024;        // LDS bound of the second sort
+
+// Columns of the per-T basis table (each column holds Tpad floats):
+//   0..7   W[:, 3..10]     8..15 Wd[:, 3..10]     16..23 Wdd[:, 3..10]
+//   24     W9 + W10        25    Wd9 + Wd10       26     Wdd9 + Wdd10
+//   27..29 W[:, 0..2]      30..32 Wd[:, 0..2]     33..35 Wdd[:, 0..2]
+//   36     t_k
+enum BasisCol {
+  kColW = 0, kColWd = 8, kColWdd = 16, kColY7 = 24, kColFix = 27, kColT = 36
+};
+
+// How iteration 0 draws its samples.
+enum InitMode : int32_t {
+  kInitStructured = 0,  // structured initial sampler (lanes + uniform speeds)
+  kInitGiven = 1,       // N(mu0, Sigma0) supplied with the request
+  kInitSession = 2,     // N(mu, Sigma) stored for the session on the device
+  kInitForced = 3       // samples uploaded by the caller (lower-level only)
+};
+
+// Device-resident descriptor of one request slot.
+struct ReqDesc {
+  int32_t T, M, N, n_ces, n_es;
+  int32_t t_idx;     // index into the per-T tables
+  int32_t tm_idx;    // index into the per-(T, M) tables
+  int32_t init_mode; // InitMode
+  int32_t session;    // session store index read at iteration 0, or -1
+  int32_t session_wb; // session store index written after the last update, or -1
+  int32_t first_iter; // upper-iteration index of the first iteration (sample stream)
+  int32_t pad0;
+  uint64_t seed;
+  double ego[6];     // x0, y0, vx0, vy0, ax0, ay0
+  double kappa;
+  double mu0[8];
+  double sigma0[64];
+  double obs[PLAN_MAX_M][4];
+};
+
+// Sampling distribution of one slot (FP64).
+struct DistState {
+  double mu[8];
+  double sigma[64];
+  double chol[64];
+};
+
+// Result record of one slot (FP64).
+struct ResultRec {
+  int32_t status;
+  uint32_t flags;
+  int32_t best;
+  int32_t iterations;
+  double p[8];
+  double xi[22];
+  double cost_upper;
+  double residual;
+};
+
+// Scalars of the method (from plan_config), FP64 on the host, passed by value.
+struct MethodParams {
+  double t_f, rho, ell_a, ell_b;
+  double v_min, v_max, a_max, kappa_max, c_max, y_lb, y_ub, v_eps;
+  double eta, gamma, cov_jitter;
+  double lane_c[3];
+  double lane_sigma, vd_lo, vd_hi;
+  int32_t K, L;
+};
+
+// Arguments of the lower-level kernel.
+struct LowerArgs {
+  const ReqDesc *desc;
+  const int2 *blocks;        // (slot, first sample) per workgroup
+  const float *basis;        // concatenated per-T tables
+  const int32_t *basis_off;  // float offset of table t_idx
+  const int32_t *basis_tpad; // column stride of table t_idx
+  const float *step1;        // per-T: S (16x8) then R (16x4)
+  const float *proj;         // per-(T,M): A^-1 (16x16) then D (16)
+  const float *p;            // slot-strided [max_N][8]
+  float *zs;                 // slot-strided [max_N][16] free coefficients
+  float *resid;              // slot-strided [max_N]
+  float *cost;               // slot-strided [max_N]
+  double *xi_bar_out;        // optional [N][22] (slot 0 only)
+  double *xi_star_out;       // optional [N][22] (slot 0 only)
+  int32_t max_N;
+  int32_t obs_stride;        // floats of the LDS obstacle table (max M*T)
+};
+
+// Arguments of the selection / update kernel and the init kernel.
+struct SelArgs {
+  ReqDesc *desc;
+  const int32_t *slots;      // slot of each workgroup
+  float *p;
+  const float *zs;
+  const float *resid;
+  const float *cost;
+  DistState *dist;
+  ResultRec *result;
+  double *sess;              // session store [n_sess][72]: mu then Sigma
+  // optional trace (slot-strided by trace_stride_* per iteration)
+  float *tr_p;               // [slot][L][max_N][8]
+  float *tr_r;               // [slot][L][max_N]
+  float *tr_c;               // [slot][L][max_N]
+  int32_t *tr_ces;           // [slot][L][max_ces]
+  int32_t *tr_es;            // [slot][L][max_es]
+  double *tr_mu;             // [slot][L][8]
+  double *tr_sigma;          // [slot][L][64]
+  int32_t max_N, max_ces, max_es;
+};
+
+}  // namespace plan

@@ -1,0 +1,290 @@
+// precompute.cpp -- sample-independent matrices of the lower level, built
+// once per horizon length T (and obstacle count M) in FP64 on the host and
+// stored as FP32 tables for the kernels (Sec. III-C: the KKT inverse is
+// computed once, irrespective of the batch size).
+//
+//   basis   Bernstein polynomials of order 10 on tau = t / t_f and their first
+//           two time derivatives at t_k = k t_f / (T - 1) (eq. param).
+//   step1   affine map of the Step-1 QP of Alg. 1 restricted to the free
+//           coefficients: z_bar = S p' + R b', with p' = [y_d, v_d - vx0] and
+//           b' = (ax0, y0, vy0, ay0); x is taken relative to x0 + vx0 t.
+//   proj    inverse of A = N^T N + rho N^T (F^T F + G^T G) N (the xi-update
+//           of Alg. 2, eq. split_xy, in the free coordinates), block diagonal
+//           in x (8 x 8) and y (7 x 7), and D = diag(N^T N).
+#include "precompute.h"
+
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+namespace plan {
+
+namespace {
+
+constexpr int kDeg = 10;
+constexpr int kNC = 11;
+
+// Bernstein values of degree m at tau: b[0..m] (de Casteljau recurrence).
+void bernstein(int m, double tau, double *b) {
+  for (int i = 0; i <= m; ++i) b[i] = 0.0;
+  b[0] = 1.0;
+  for (int d = 1; d <= m; ++d) {
+    for (int i = d; i >= 1; --i) b[i] = (1.0 - tau) * b[i] + tau * b[i - 1];
+    b[0] = (1.0 - tau) * b[0];
+  }
+}
+
+// Rows of W, Wd, Wdd at one instant via the derivative recurrence
+// dB_i,n = n (B_i-1,n-1 - B_i,n-1).
+void basis_row(double tau, double t_f, double *W, double *Wd, double *Wdd) {
+  double b10[kNC], b9[kNC], b8[kNC];
+  bernstein(kDeg, tau, b10);
+  bernstein(kDeg - 1, tau, b9);
+  bernstein(kDeg - 2, tau, b8);
+  for (int i = 0; i <= kDeg; ++i) {
+    W[i] = b10[i];
+    double d1 = (i >= 1 ? b9[i - 1] : 0.0) - (i <= kDeg - 1 ? b9[i] : 0.0);
+    Wd[i] = kDeg * d1 / t_f;
+    double d2 = (i >= 2 ? b8[i - 2] : 0.0) - 2.0 * (i >= 1 && i - 1 <= kDeg - 2 ? b8[i - 1] : 0.0) +
+                (i <= kDeg - 2 ? b8[i] : 0.0);
+    Wdd[i] = kDeg * (kDeg - 1) * d2 / (t_f * t_f);
+  }
+}
+
+// In-place inverse of a symmetric positive definite n x n matrix (Cholesky).
+void spd_inverse(double *A, int n) {
+  std::vector<double> L(n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 0.0)) throw std::runtime_error("matrix not positive definite");
+    L[j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = s / L[j * n + j];
+    }
+  }
+  // inverse columns: solve L L^T x = e_c
+  std::vector<double> inv(n * n);
+  std::vector<double> y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * y[k];
+      y[i] = s / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * inv[k * n + c];
+      inv[i * n + c] = s / L[i * n + i];
+    }
+  }
+  std::memcpy(A, inv.data(), sizeof(double) * n * n);
+}
+
+// Free-coordinate selections: x free = c3..c10 (8); y free = c3..c8 and the
+// shared value of c9 = c10 (ydot(t_f) = 0).
+void null_x(double *Nx /* 11 x 8 */) {
+  std::memset(Nx, 0, sizeof(double) * kNC * 8);
+  for (int c = 0; c < 8; ++c) Nx[(3 + c) * 8 + c] = 1.0;
+}
+void null_y(double *Ny /* 11 x 7 */) {
+  std::memset(Ny, 0, sizeof(double) * kNC * 7);
+  for (int c = 0; c < 6; ++c) Ny[(3 + c) * 7 + c] = 1.0;
+  Ny[9 * 7 + 6] = 1.0;
+  Ny[10 * 7 + 6] = 1.0;
+}
+
+// v^T N for a row v of length 11.
+template <int NF>
+void project_row(const double *row, const double *Nm, double *out) {
+  for (int c = 0; c < NF; ++c) {
+    double s = 0.0;
+    for (int i = 0; i < kNC; ++i) s += row[i] * Nm[i * NF + c];
+    out[c] = s;
+  }
+}
+
+}  // namespace
+
+void build_basis(int T, double t_f, BasisTable &bt) {
+  bt.T = T;
+  bt.Tpad = (T + 63) / 64 * 64;
+  bt.W.assign(T * kNC, 0.0);
+  bt.Wd.assign(T * kNC, 0.0);
+  bt.Wdd.assign(T * kNC, 0.0);
+  for (int k = 0; k < T; ++k) {
+    double tau = T > 1 ? (double)k / (double)(T - 1) : 0.0;
+    basis_row(tau, t_f, &bt.W[k * kNC], &bt.Wd[k * kNC], &bt.Wdd[k * kNC]);
+  }
+  bt.table.assign((size_t)kBasisCols * bt.Tpad, 0.f);
+  auto col = [&](int c) { return &bt.table[(size_t)c * bt.Tpad]; };
+  for (int k = 0; k < T; ++k) {
+    const double *W = &bt.W[k * kNC], *Wd = &bt.Wd[k * kNC], *Wdd = &bt.Wdd[k * kNC];
+    for (int c = 0; c < 8; ++c) {
+      col(kColW + c)[k] = (float)W[3 + c];
+      col(kColWd + c)[k] = (float)Wd[3 + c];
+      col(kColWdd + c)[k] = (float)Wdd[3 + c];
+    }
+    col(kColY7 + 0)[k] = (float)(W[9] + W[10]);
+    col(kColY7 + 1)[k] = (float)(Wd[9] + Wd[10]);
+    col(kColY7 + 2)[k] = (float)(Wdd[9] + Wdd[10]);
+    for (int c = 0; c < 3; ++c) {
+      col(kColFix + c)[k] = (float)W[c];
+      col(kColFix + 3 + c)[k] = (float)Wd[c];
+      col(kColFix + 6 + c)[k] = (float)Wdd[c];
+    }
+    col(kColT)[k] = (float)(t_f * (double)k / (double)(T - 1));
+  }
+}
+
+// Step-1 QP (Alg. 1, Sec. II-C cost) reduced to the free coefficients:
+// minimise sum_k w (a_k^T c - beta_k)^2 over c = N z + c_fix.
+void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, Step1Table &st) {
+  const int T = bt.T;
+  double Nx[kNC * 8], Ny[kNC * 7];
+  null_x(Nx);
+  null_y(Ny);
+  const double n = kDeg;
+  // ---- x axis, relative to x0 + vx0 t: beta = k_p (v_d - vx0), c_fix = e2 ax0 t_f^2/90
+  double Hx[64] = {0}, Sx[8 * 4] = {0}, rx[8] = {0};
+  {
+    double cfix2 = t_f * t_f / (n * (n - 1.0));  // per unit ax0
+    for (int k = 0; k < T; ++k) {
+      const double *Wd = &bt.Wd[k * kNC], *Wdd = &bt.Wdd[k * kNC];
+      int seg = (4 * k) / T;
+      double a1[kNC], a2[kNC];
+      for (int i = 0; i < kNC; ++i) {
+        a1[i] = Wdd[i];                 // c_s: xddot
+        a2[i] = Wdd[i] + cw.k_p * Wd[i]; // c_v: xddot + k_p xdot
+      }
+      double n1[8], n2[8];
+      project_row<8>(a1, Nx, n1);
+      project_row<8>(a2, Nx, n2);
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) Hx[a * 8 + b] += 2.0 * (cw.w_s * n1[a] * n1[b] + cw.w_v * n2[a] * n2[b]);
+      for (int a = 0; a < 8; ++a) {
+        Sx[a * 4 + seg] += 2.0 * cw.w_v * cw.k_p * n2[a];
+        rx[a] -= 2.0 * (cw.w_s * n1[a] * a1[2] + cw.w_v * n2[a] * a2[2]) * cfix2;
+      }
+    }
+    spd_inverse(Hx, 8);
+  }
+  // ---- y axis: beta = k_p y_d, c_fix = E (y0, vy0, ay0)
+  double Hy[49] = {0}, Sy[7 * 4] = {0}, Ry[7 * 3] = {0};
+  {
+    double E[kNC * 3] = {0};
+    E[0 * 3 + 0] = 1.0;
+    E[1 * 3 + 0] = 1.0;
+    E[1 * 3 + 1] = t_f / n;
+    E[2 * 3 + 0] = 1.0;
+    E[2 * 3 + 1] = 2.0 * t_f / n;
+    E[2 * 3 + 2] = t_f * t_f / (n * (n - 1.0));
+    for (int k = 0; k < T; ++k) {
+      const double *W = &bt.W[k * kNC], *Wd = &bt.Wd[k * kNC], *Wdd = &bt.Wdd[k * kNC];
+      int seg = (4 * k) / T;
+      double a1[kNC], a2[kNC];
+      for (int i = 0; i < kNC; ++i) {
+        a1[i] = Wdd[i];                                   // c_s: yddot
+        a2[i] = Wdd[i] + cw.k_p * W[i] + cw.k_v * Wd[i];  // c_l
+      }
+      double n1[7], n2[7];
+      project_row<7>(a1, Ny, n1);
+      project_row<7>(a2, Ny, n2);
+      double e1[3] = {0}, e2[3] = {0};
+      for (int m = 0; m < 3; ++m)
+        for (int i = 0; i < kNC; ++i) {
+          e1[m] += a1[i] * E[i * 3 + m];
+          e2[m] += a2[i] * E[i * 3 + m];
+        }
+      for (int a = 0; a < 7; ++a)
+        for (int b = 0; b < 7; ++b) Hy[a * 7 + b] += 2.0 * (cw.w_s * n1[a] * n1[b] + cw.w_l * n2[a] * n2[b]);
+      for (int a = 0; a < 7; ++a) {
+        Sy[a * 4 + seg] += 2.0 * cw.w_l * cw.k_p * n2[a];
+        for (int m = 0; m < 3; ++m) Ry[a * 3 + m] -= 2.0 * (cw.w_s * n1[a] * e1[m] + cw.w_l * n2[a] * e2[m]);
+      }
+    }
+    spd_inverse(Hy, 7);
+  }
+  // S (16 x 8) on p' = [y_d(4), v_d - vx0 (4)], R (16 x 4) on b' = (ax0, y0, vy0, ay0)
+  st.S.assign(16 * 8, 0.0);
+  st.R.assign(16 * 4, 0.0);
+  for (int a = 0; a < 8; ++a) {
+    for (int m = 0; m < 4; ++m) {
+      double s = 0.0;
+      for (int b = 0; b < 8; ++b) s += Hx[a * 8 + b] * Sx[b * 4 + m];
+      st.S[a * 8 + 4 + m] = s;
+    }
+    double s = 0.0;
+    for (int b = 0; b < 8; ++b) s += Hx[a * 8 + b] * rx[b];
+    st.R[a * 4 + 0] = s;
+  }
+  for (int a = 0; a < 7; ++a) {
+    for (int m = 0; m < 4; ++m) {
+      double s = 0.0;
+      for (int b = 0; b < 7; ++b) s += Hy[a * 7 + b] * Sy[b * 4 + m];
+      st.S[(8 + a) * 8 + m] = s;
+    }
+    for (int m = 0; m < 3; ++m) {
+      double s = 0.0;
+      for (int b = 0; b < 7; ++b) s += Hy[a * 7 + b] * Ry[b * 3 + m];
+      st.R[(8 + a) * 4 + 1 + m] = s;
+    }
+  }
+  st.table.resize(kStep1Floats);
+  for (int i = 0; i < 16 * 8; ++i) st.table[i] = (float)st.S[i];
+  for (int i = 0; i < 16 * 4; ++i) st.table[16 * 8 + i] = (float)st.R[i];
+}
+
+void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt) {
+  const int T = bt.T;
+  double WtW[kNC * kNC] = {0}, DtD[kNC * kNC] = {0}, AtA[kNC * kNC] = {0};
+  for (int k = 0; k < T; ++k)
+    for (int i = 0; i < kNC; ++i)
+      for (int j = 0; j < kNC; ++j) {
+        WtW[i * kNC + j] += bt.W[k * kNC + i] * bt.W[k * kNC + j];
+        DtD[i * kNC + j] += bt.Wd[k * kNC + i] * bt.Wd[k * kNC + j];
+        AtA[i * kNC + j] += bt.Wdd[k * kNC + i] * bt.Wdd[k * kNC + j];
+      }
+  // H_x = M W^T W + Wd^T Wd + Wdd^T Wdd; H_y adds G^T G = 2 W^T W.
+  double Hx[kNC * kNC], Hy[kNC * kNC];
+  for (int i = 0; i < kNC * kNC; ++i) {
+    Hx[i] = M * WtW[i] + DtD[i] + AtA[i];
+    Hy[i] = (M + 2) * WtW[i] + DtD[i] + AtA[i];
+  }
+  double Nx[kNC * 8], Ny[kNC * 7];
+  null_x(Nx);
+  null_y(Ny);
+  auto reduce = [&](const double *H, const double *Nm, int nf, double *Aout, double *Dout) {
+    for (int a = 0; a < nf; ++a)
+      for (int b = 0; b < nf; ++b) {
+        double h = 0.0, nn = 0.0;
+        for (int i = 0; i < kNC; ++i)
+          for (int j = 0; j < kNC; ++j) h += Nm[i * nf + a] * H[i * kNC + j] * Nm[j * nf + b];
+        for (int i = 0; i < kNC; ++i) nn += Nm[i * nf + a] * Nm[i * nf + b];
+        Aout[a * nf + b] = nn + rho * h;
+        if (a == b) Dout[a] = nn;
+      }
+  };
+  double Ax[64], Ay[49], Dx[8], Dy[7];
+  reduce(Hx, Nx, 8, Ax, Dx);
+  reduce(Hy, Ny, 7, Ay, Dy);
+  spd_inverse(Ax, 8);
+  spd_inverse(Ay, 7);
+  pt.Ainv.assign(16 * 16, 0.0);
+  pt.D.assign(16, 0.0);
+  for (int a = 0; a < 8; ++a) {
+    for (int b = 0; b < 8; ++b) pt.Ainv[a * 16 + b] = Ax[a * 8 + b];
+    pt.D[a] = Dx[a];
+  }
+  for (int a = 0; a < 7; ++a) {
+    for (int b = 0; b < 7; ++b) pt.Ainv[(8 + a) * 16 + 8 + b] = Ay[a * 7 + b];
+    pt.D[8 + a] = Dy[a];
+  }
+  pt.table.resize(kProjFloats);
+  for (int i = 0; i < 256; ++i) pt.table[i] = (float)pt.Ainv[i];
+  for (int i = 0; i < 16; ++i) pt.table[256 + i] = (float)pt.D[i];
+}
+
+}  // namespace plan

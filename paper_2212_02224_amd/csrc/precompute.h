@@ -1,0 +1,34 @@
+// precompute.h -- host FP64 construction of the per-T and per-(T, M) tables.
+#pragma once
+
+#include <vector>
+
+#include "plan_internal.h"
+
+namespace plan {
+
+struct CostWeights {
+  double k_p, k_v, w_s, w_l, w_v;
+};
+
+struct BasisTable {
+  int T = 0, Tpad = 0;
+  std::vector<double> W, Wd, Wdd;  // T x 11 (FP64)
+  std::vector<float> table;        // kBasisCols x Tpad (FP32, device layout)
+};
+
+struct Step1Table {
+  std::vector<double> S, R;        // 16 x 8, 16 x 4 (FP64)
+  std::vector<float> table;        // kStep1Floats
+};
+
+struct ProjTable {
+  std::vector<double> Ainv, D;     // 16 x 16 block diagonal, 16
+  std::vector<float> table;        // kProjFloats
+};
+
+void build_basis(int T, double t_f, BasisTable &bt);
+void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, Step1Table &st);
+void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt);
+
+}  // namespace plan

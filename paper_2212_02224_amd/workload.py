@@ -1,0 +1,62 @@
+"""Seeded synthetic planning scenes (inputs only; none of the method's
+arithmetic lives here).
+
+The paper evaluates on highway-env scenes with IDM/MOBIL traffic (Sec. V);
+that simulator is not available, so these scenes stand in for them with the
+same structure: a straight multi-lane road, an ego vehicle in a lane, and
+neighbours moving along straight lines at constant speed in their lanes
+(Fig. learned_sampler), of which the planner sees the M nearest.
+
+    road        straight, lane centres {-3.5, 0, 3.5} m, bounds y in [-7, 7]
+    ego         x0 = 0, y0 = a lane centre, vx0 ~ U[10, 20] m/s, other terms 0
+    neighbours  lane centre, x ~ U[-20, 120] m, vx ~ U[8, 25] m/s, vy = 0;
+                rejected if closer than 1.5 (ellipse-normalised) to the ego or
+                than 1.0 to another neighbour at t = 0
+    seeds       scene seed = 1000 * config + request index; the request's
+                sample-stream key is scene seed XOR 0x9E3779B9
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+LANES = (-3.5, 0.0, 3.5)
+ELL_A, ELL_B = 4.5, 2.0
+
+
+@dataclass
+class Scene:
+    ego: np.ndarray        # (6,)  x0, y0, vx0, vy0, ax0, ay0
+    obstacles: np.ndarray  # (M, 4) x, y, vx, vy at t = 0
+    seed: int              # key of the request's sample stream
+
+
+def scene(config: int, index: int, M: int) -> Scene:
+    s = 1000 * int(config) + int(index)
+    rng = np.random.default_rng(s)
+    ego = np.array([0.0, rng.choice(LANES), rng.uniform(10.0, 20.0), 0.0, 0.0, 0.0])
+    obs = []
+    tries = 0
+    while len(obs) < M:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place neighbours")
+        o = np.array([rng.uniform(-20.0, 120.0), rng.choice(LANES), rng.uniform(8.0, 25.0), 0.0])
+        d_ego = np.hypot((o[0] - ego[0]) / ELL_A, (o[1] - ego[1]) / ELL_B)
+        if d_ego < 1.5:
+            continue
+        if any(np.hypot((o[0] - q[0]) / ELL_A, (o[1] - q[1]) / ELL_B) < 1.0 for q in obs):
+            continue
+        obs.append(o)
+    obs = np.array(obs, dtype=np.float64).reshape(M, 4)
+    return Scene(ego, obs, s ^ 0x9E3779B9)
+
+
+# Workload configurations (sizes of the planning problem).
+CONFIGS = {
+    1: dict(name="small-N64-T50-M4", N=64, T=50, M=4, L=3, K=10),
+    2: dict(name="plan-N1000-T100-M10", N=1000, T=100, M=10, L=5, K=20),
+    4: dict(name="served-poisson-256", N=(256, 512, 1000, 2048), T=(50, 100), M=(4, 10, 20), L=5, K=20),
+    5: dict(name="served-1024x-N4096-T100-M20", N=4096, T=100, M=20, L=5, K=20),
+}
