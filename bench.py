@@ -68,6 +68,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy 512 MiB device-to-device three times (a "
+                         "kernel of known traffic that calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): requests are independent, "
@@ -137,6 +140,12 @@ def main() -> int:
         "kernel_ms_per_step": {k: ms[k] / args.steps for k in ms},
         "plan": {"best_index": res.best_index, "cost_upper": res.cost_upper, "residual": res.residual},
     }
+    if args.copy_probe:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(scene, c, threads)
