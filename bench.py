@@ -62,12 +62,79 @@ def cpu_baseline(scene, c, threads: int):
                       f"FP64, OpenMP over samples ({dt:.2f} s)"}
 
 
+def served_stream(pl, workload, n_req: int, seed: int = 4):
+    """The served workload: n_req requests with N in {256, 512, 1000, 2048},
+    M in {4, 10, 20}, T in {50, 100} (seeded), on synthetic scenes."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        N = int(rng.choice([256, 512, 1000, 2048]))
+        M = int(rng.choice([4, 10, 20]))
+        T = int(rng.choice([50, 100]))
+        s = workload.scene(4, i, M)
+        reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
+    return reqs
+
+
+def run_served(pl, h, reqs, arrivals):
+    """Submit each request at its arrival time (seconds after start), drive
+    plan_progress until all finish; returns (latencies, makespan)."""
+    import numpy as np
+    order = np.argsort(arrivals, kind="stable")
+    pending = {}
+    lat = np.zeros(len(reqs))
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(order) or pending:
+        now = time.perf_counter() - t0
+        while k < len(order) and arrivals[order[k]] <= now:
+            i = int(order[k])
+            pending[pl.plan_submit(h, reqs[i])] = i
+            k += 1
+        if not pending:
+            continue
+        pl.plan_progress(h)
+        for t in list(pending):
+            r = pl.plan_poll(h, t)
+            if r is not None:
+                if r.status != 0:
+                    raise RuntimeError(f"served request failed: {pl.plan_last_error(h)}")
+                lat[pending.pop(t)] = r.latency_s
+    return lat, time.perf_counter() - t0
+
+
+def served_bench(pl, workload, torch, n_req=256, slots=64):
+    """Saturated rate, then Poisson arrivals at 0.7 of it: p50/p99 latency."""
+    import numpy as np
+    L, K = 5, 20
+    cfg = pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=K, upper_iters=L, max_N=2048,
+                              max_requests=slots)
+    ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
+    h = pl.plan_create(cfg, workspace=ws, stream=torch.cuda.current_stream().cuda_stream)
+    reqs = served_stream(pl, workload, n_req)
+    solves = sum(r.N for r in reqs) * L
+    run_served(pl, h, reqs[:8], np.zeros(8))  # warm-up
+    _, sat_span = run_served(pl, h, reqs, np.zeros(n_req))
+    rate_sat = n_req / sat_span
+    lam = 0.7 * rate_sat
+    arrivals = np.cumsum(np.random.default_rng(11).exponential(1.0 / lam, n_req))
+    lat, span = run_served(pl, h, reqs, arrivals)
+    return {"requests": n_req, "slots": slots, "L": L, "K": K,
+            "mix": "N in {256,512,1000,2048}, M in {4,10,20}, T in {50,100}",
+            "saturated_requests_per_s": rate_sat, "saturated_solves_per_s": solves / sat_span,
+            "arrival_rate_per_s": lam, "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)), "solves_per_s": solves / span,
+            "makespan_s": span}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson) measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 512 MiB device-to-device three times (a "
                          "kernel of known traffic that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -146,6 +213,8 @@ def main() -> int:
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if not args.no_served:
+        out["served"] = served_bench(pl, workload, torch)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(scene, c, threads)

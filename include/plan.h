@@ -77,6 +77,10 @@ typedef enum plan_precision {
  *   t_f             horizon [s].
  *   max_N           largest sample count of a request (<= PLAN_MAX_N).
  *   max_requests    request slots resident on the device at once.
+ *   sample_budget   rows of per-sample device memory (samples, coefficients,
+ *                   residual, cost: 104 bytes each) shared by the resident
+ *                   requests; a request takes N contiguous rows. With
+ *                   max_requests this is the HBM budget of admission.
  *   proj_iters      K, iterations of Alg. 2 (its maxiter).
  *   upper_iters     L, iterations of Alg. 1 (its N).
  *   frac_ces/es     n = max(q, round(frac_ces N)), q = max(1, round(frac_es N))
@@ -117,6 +121,7 @@ typedef struct plan_config {
   double lane_sigma, vd_lo, vd_hi;
   int32_t precision;
   int32_t trace; /* nonzero: keep per-iteration elite sets and mu, Sigma */
+  int64_t sample_budget; /* sample rows resident at once (0: max_requests * max_N) */
   void *device_workspace;
   size_t workspace_bytes;
   void *stream;
@@ -221,19 +226,39 @@ plan_status plan_lower_solve(plan_handle *h, const plan_request *req,
 
 /* Per-iteration record of the last plan_solve_batch / plan_collect for
  * staged request i (needs cfg.trace): samples p (L x N x 8), residuals and
- * costs (L x N), ConstraintEliteSet (L x n) and EliteSet (L x q) indices,
- * mu (L x 8) and Sigma (L x 64) after each update. Any pointer may be NULL. */
+ * costs (L x N), ConstraintEliteSet (L x n) and EliteSet (L x q) sample
+ * indices (each list in increasing sample index), mu (L x 8) and Sigma
+ * (L x 64) after each update. Any pointer may be NULL. */
 plan_status plan_get_trace(plan_handle *h, int32_t i, double *p, double *resid,
                            double *cost_upper, int32_t *ces, int32_t *es,
                            double *mu, double *sigma);
 
+/*
+ * Served mode: continuous batching at the granularity of one upper iteration
+ * of Alg. 1. plan_submit validates and queues a request (copying everything
+ * it points to) and returns a ticket. Each plan_progress call admits queued
+ * requests, first come first served, while a request slot and N contiguous
+ * sample rows of the budget are free; runs one upper iteration for every
+ * resident request at once (whatever their sizes and iteration indices, in
+ * the same kernel launches); and retires the requests that finished their L
+ * iterations. plan_poll returns PLAN_E_BUSY until the ticket's request is
+ * done, then its result (latency_s: submit to completion) and forgets the
+ * ticket. A request's arithmetic does not depend on what else is resident,
+ * so its result equals the one of plan_solve_batch bit for bit.
+ * *n_active / *n_queued (nullable) receive the resident and waiting counts.
+ * plan_submit fails with PLAN_E_INVALID for a bad request.
+ */
+plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticket);
+plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued);
+plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out);
+
 /* Kernel timing by HIP events recorded on the library's stream around every
  * launch of plan_launch / plan_solve_batch. enable != 0 starts recording (and
  * clears the totals); plan_profile_read waits for the stream and returns the
- * summed milliseconds and launch counts per kernel: [0] init, [1] lower level
- * (Steps 1-2 + residual), [2] selection / update. */
+ * summed milliseconds and launch counts per kernel: [0] lower level
+ * (sampling, Steps 1-2, residual/cost), [1] selection / update. */
 plan_status plan_profile(plan_handle *h, int32_t enable);
-plan_status plan_profile_read(plan_handle *h, double ms[3], int64_t count[3]);
+plan_status plan_profile_read(plan_handle *h, double ms[2], int64_t count[2]);
 
 #ifdef __cplusplus
 }

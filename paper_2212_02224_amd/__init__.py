@@ -9,5 +9,6 @@ from .binding import (PLAN_E_BUSY, PLAN_E_DEVICE, PLAN_E_INVALID, PLAN_E_NOMEM, 
                       PlanError, Request, Result, elite_sizes, exported_symbols, load,
                       plan_collect, plan_config_init, plan_create, plan_destroy,
                       plan_get_trace, plan_last_error, plan_launch, plan_lower_solve,
+                      plan_poll, plan_progress, plan_submit,
                       plan_profile, plan_profile_read, plan_solve_batch, plan_stage,
                       plan_workspace_bytes)

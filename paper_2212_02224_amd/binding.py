@@ -46,6 +46,7 @@ class plan_config(C.Structure):
         ("lane_c", C.c_double * 3),
         ("lane_sigma", C.c_double), ("vd_lo", C.c_double), ("vd_hi", C.c_double),
         ("precision", C.c_int32), ("trace", C.c_int32),
+        ("sample_budget", C.c_int64),
         ("device_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
@@ -108,10 +109,14 @@ def load():
     lib.plan_lower_solve.argtypes = [H, Req, _PD, C.c_int32, _PD, _PD, _PD, _PD]
     lib.plan_get_trace.argtypes = [H, C.c_int32, _PD, _PD, _PD, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), _PD, _PD]
+    lib.plan_submit.argtypes = [H, Req, C.POINTER(C.c_uint64)]
+    lib.plan_progress.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.plan_poll.argtypes = [H, C.c_uint64, Res]
     lib.plan_profile.argtypes = [H, C.c_int32]
     lib.plan_profile_read.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in ("plan_create", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
-                 "plan_lower_solve", "plan_get_trace", "plan_profile", "plan_profile_read"):
+                 "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
+                 "plan_profile", "plan_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -120,7 +125,8 @@ def load():
 def exported_symbols() -> list[str]:
     return ["plan_config_init", "plan_workspace_bytes", "plan_create", "plan_destroy",
             "plan_last_error", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
-            "plan_lower_solve", "plan_get_trace", "plan_profile", "plan_profile_read"]
+            "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
+            "plan_profile", "plan_profile_read"]
 
 
 def _check(status: int, handle=None) -> int:
@@ -316,16 +322,42 @@ def plan_get_trace(h: Handle, i: int, N: int, n: int, q: int) -> dict:
     return out
 
 
+def plan_submit(h: Handle, req: Request) -> int:
+    """Queue a request for the served mode; returns its ticket."""
+    m = _Marshalled([req])
+    t = C.c_uint64()
+    _check(load().plan_submit(h.ptr, m.arr, C.byref(t)), h.ptr)
+    return int(t.value)
+
+
+def plan_progress(h: Handle) -> tuple[int, int]:
+    """Admit, run one upper iteration of everything resident, retire.
+    Returns (resident, queued) counts."""
+    a, q = C.c_int32(), C.c_int32()
+    _check(load().plan_progress(h.ptr, C.byref(a), C.byref(q)), h.ptr)
+    return int(a.value), int(q.value)
+
+
+def plan_poll(h: Handle, ticket: int) -> Result | None:
+    """The result of a finished ticket, or None while it is queued/resident."""
+    out = plan_result()
+    st = load().plan_poll(h.ptr, C.c_uint64(int(ticket)), C.byref(out))
+    if st == PLAN_E_BUSY:
+        return None
+    _check(st, h.ptr)
+    return _result(out)
+
+
 def plan_profile(h: Handle, enable: bool = True) -> None:
     _check(load().plan_profile(h.ptr, 1 if enable else 0), h.ptr)
 
 
 def plan_profile_read(h: Handle):
-    """Returns ({'init','lower','select'}: total ms, same: launch count)."""
-    ms = (C.c_double * 3)()
-    cnt = (C.c_int64 * 3)()
+    """Returns ({'lower','select'}: total ms, same: launch count)."""
+    ms = (C.c_double * 2)()
+    cnt = (C.c_int64 * 2)()
     _check(load().plan_profile_read(h.ptr, ms, cnt), h.ptr)
-    names = ("init", "lower", "select")
+    names = ("lower", "select")
     return {k: ms[i] for i, k in enumerate(names)}, {k: cnt[i] for i, k in enumerate(names)}
 
 

@@ -1,11 +1,15 @@
 // capi.cpp -- the C ABI of include/plan.h: validation, device memory layout,
-// request staging and the launch sequence of Alg. 1 on a HIP stream.
+// request staging, the launch sequence of Alg. 1 on a HIP stream, and the
+// served mode (continuous batching).
 //
-// Launch sequence of one batch of resident requests (all on one stream):
-//   init_kernel                         iteration-0 distribution and draw
-//   for l in 0..L-1:
-//     lower_kernel                      Steps 1-2 of Alg. 1 + residual/cost
-//     select_update_kernel(l)           elite sets, update, next draw
+// One upper iteration of every resident request is two launches:
+//   lower_kernel          draw of the iteration, Steps 1-2 of Alg. 1,
+//                         residual/cost, for all samples of all requests
+//   select_update_kernel  elite sets and the update of mu, Sigma, one
+//                         workgroup per request
+// Batch mode runs L such pairs for a staged batch; served mode runs one pair
+// per plan_progress call for whatever is resident, each request at its own
+// iteration (kept on the device in its descriptor).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,6 +17,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -21,13 +27,12 @@
 #include "precompute.h"
 
 namespace plan {
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds,
-                        hipStream_t st);
-hipError_t launch_init(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st);
-hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, int l, hipStream_t st);
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st);
+hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st);
 }  // namespace plan
 
 using namespace plan;
+using Clock = std::chrono::steady_clock;
 
 namespace {
 
@@ -48,6 +53,19 @@ bool finite_all(const double *v, int n) {
   return true;
 }
 
+int64_t budget_rows(const plan_config &c) {
+  return c.sample_budget > 0 ? c.sample_budget : (int64_t)c.max_requests * c.max_N;
+}
+
+// Dynamic LDS of the lower kernel: two neighbours per float4, per instant.
+size_t lds_bytes(int M, int T) { return (size_t)((M + 1) / 2) * T * sizeof(float4); }
+
+// Workgroups of one request: ceil(T/64) waves per sample, 4 waves per group.
+int blocks_for(int N, int T) {
+  const int spb = 4 / ((T + kWave - 1) / kWave);
+  return (N + spb - 1) / spb;
+}
+
 struct DevBuf {
   char *base = nullptr;
   size_t used = 0, cap = 0;
@@ -62,13 +80,13 @@ struct DevBuf {
 // Device bytes of every region, in allocation order.
 struct Layout {
   size_t basis = 0, step1 = 0, proj = 0, offs = 0;
-  size_t desc = 0, dist = 0, result = 0, slots = 0;
-  size_t p = 0, zs = 0, rc = 0, blocks = 0, sess = 0, xiout = 0;
+  size_t desc = 0, dist = 0, result = 0, act = 0;
+  size_t p = 0, zs = 0, rc = 0, sess = 0, xiout = 0;
   size_t tr_p = 0, tr_rc = 0, tr_idx = 0, tr_dist = 0;
   size_t total() const {
     size_t s = 0;
-    for (size_t b : {basis, step1, proj, offs, desc, dist, result, slots, p, zs, rc, blocks, sess,
-                     xiout, tr_p, tr_rc, tr_idx, tr_dist})
+    for (size_t b : {basis, step1, proj, offs, desc, dist, result, act, p, zs, rc, sess, xiout, tr_p, tr_rc,
+                     tr_idx, tr_dist})
       s += (b + 255) & ~(size_t)255;
     return s;
   }
@@ -78,7 +96,7 @@ int max_sessions(const plan_config &c) { return std::max(64, 2 * c.max_requests)
 
 Layout compute_layout(const plan_config &c) {
   Layout L;
-  size_t S = (size_t)c.max_requests, N = (size_t)c.max_N;
+  const size_t S = (size_t)c.max_requests, N = (size_t)c.max_N, R = (size_t)budget_rows(c);
   for (int i = 0; i < c.n_T; ++i) L.basis += (size_t)kBasisCols * ((c.T_set[i] + 63) / 64 * 64) * 4;
   L.step1 = (size_t)c.n_T * kStep1Floats * 4;
   L.proj = (size_t)c.n_T * c.n_M * kProjFloats * 4;
@@ -86,17 +104,16 @@ Layout compute_layout(const plan_config &c) {
   L.desc = S * sizeof(ReqDesc);
   L.dist = S * sizeof(DistState);
   L.result = S * sizeof(ResultRec);
-  L.slots = S * 4;
-  L.p = S * N * 8 * 4;
-  L.zs = S * N * kZ * 4;
-  L.rc = S * N * 2 * 4;
-  L.blocks = S * N * sizeof(int2);
+  L.act = (2 * S + 1) * 4;
+  L.p = R * 8 * 4;
+  L.zs = R * kZ * 4;
+  L.rc = R * 2 * 4;
   L.sess = (size_t)max_sessions(c) * 72 * 8;
   L.xiout = N * 22 * 2 * 8;
   if (c.trace) {
     int n, q;
     elite_sizes(c, c.max_N, n, q);
-    size_t Lit = (size_t)c.upper_iters;
+    const size_t Lit = (size_t)c.upper_iters;
     L.tr_p = S * Lit * N * 8 * 4;
     L.tr_rc = S * Lit * N * 2 * 4;
     L.tr_idx = S * Lit * (size_t)(n + q) * 4;
@@ -113,6 +130,8 @@ const char *validate_config(const plan_config &c) {
     if (c.M_set[i] < 0 || c.M_set[i] > PLAN_MAX_M) return "M must be in [0, PLAN_MAX_M]";
   if (c.max_N < 1 || c.max_N > PLAN_MAX_N) return "max_N must be in [1, PLAN_MAX_N]";
   if (c.max_requests < 1 || c.max_requests > 65536) return "max_requests must be in [1, 65536]";
+  if (c.sample_budget < 0 || (c.sample_budget > 0 && c.sample_budget < c.max_N))
+    return "sample_budget must be 0 or at least max_N";
   if (c.proj_iters < 1 || c.proj_iters > 10000) return "proj_iters must be >= 1";
   if (c.upper_iters < 1 || c.upper_iters > PLAN_MAX_L) return "upper_iters must be in [1, PLAN_MAX_L]";
   if (!(c.t_f > 0) || !(c.rho > 0) || !(c.gamma > 0) || !(c.eta >= 0 && c.eta <= 1))
@@ -126,9 +145,28 @@ const char *validate_config(const plan_config &c) {
   int n, q;
   elite_sizes(c, c.max_N, n, q);
   if (n > kMaxCes) return "ConstraintEliteSet larger than 1024 samples is not supported";
+  if (q > kMaxEs) return "EliteSet larger than 256 samples is not supported";
   if (c.precision != PLAN_PREC_FP32) return "unsupported precision";
   return nullptr;
 }
+
+// A queued request of the served mode, owning copies of its arrays.
+struct Pending {
+  uint64_t ticket = 0;
+  plan_request req{};
+  std::vector<double> obs, mu0, sigma0;
+  Clock::time_point submit;
+};
+
+struct Resident {
+  uint64_t ticket = 0;
+  int slot = -1;
+  int64_t row_off = 0;
+  int N = 0, T = 0;
+  int iters = 0;
+  int session_wb = -1;
+  Clock::time_point submit;
+};
 
 }  // namespace
 
@@ -141,16 +179,16 @@ struct plan_handle {
   bool own_mem = false;
   DevBuf mem;
   Layout lay;
+  int64_t rows = 0;
   // tables
   float *basis = nullptr, *step1 = nullptr, *proj = nullptr;
   int32_t *basis_off = nullptr, *basis_tpad = nullptr;
-  // slots
+  // slots and the row pool
   ReqDesc *desc = nullptr;
   DistState *dist = nullptr;
   ResultRec *result = nullptr;
-  int32_t *slots = nullptr;
+  int32_t *act_slots = nullptr, *blk_prefix = nullptr;
   float *p = nullptr, *zs = nullptr, *resid = nullptr, *cost = nullptr;
-  int2 *blocks = nullptr;
   double *sess = nullptr;
   double *xi_out = nullptr;
   float *tr_p = nullptr, *tr_r = nullptr, *tr_c = nullptr;
@@ -159,18 +197,24 @@ struct plan_handle {
   int max_ces = 0, max_es = 0;
   // host staging (pinned)
   ReqDesc *h_desc = nullptr;
-  int2 *h_blocks = nullptr;
-  int32_t *h_slots = nullptr;
+  int32_t *h_act = nullptr;  // act_slots then blk_prefix
   ResultRec *h_result = nullptr;
-  // staged batch
-  int staged = 0;                  // requests staged (slots 0..staged-1)
+  DistState *h_dist = nullptr;
+  // batch mode: staged requests in slots 0..staged-1
+  int staged = 0;
   int nblocks = 0;
   size_t lds = 0;
-  std::vector<int> staged_req;     // original request index per slot
-  std::vector<int> staged_status;  // per original request in the last stage
+  std::vector<int> staged_req;
+  std::vector<int> staged_status;
   int staged_total = 0;
-  std::vector<uint64_t> staged_session;
-  std::chrono::steady_clock::time_point t_stage;
+  Clock::time_point t_stage;
+  // served mode
+  std::map<int64_t, int64_t> free_rows;  // begin -> end of free row ranges
+  std::vector<char> slot_busy;
+  std::deque<Pending> queue;
+  std::vector<Resident> resident;
+  std::unordered_map<uint64_t, plan_result> done;
+  uint64_t next_ticket = 1;
   // sessions
   std::unordered_map<uint64_t, int> sess_index;
   std::vector<uint64_t> sess_key;
@@ -181,8 +225,8 @@ struct plan_handle {
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-  double prof_ms[3] = {0, 0, 0};
-  int64_t prof_count[3] = {0, 0, 0};
+  double prof_ms[2] = {0, 0};
+  int64_t prof_count[2] = {0, 0};
 };
 
 namespace {
@@ -239,19 +283,21 @@ int find_M(const plan_config &c, int M) {
   return -1;
 }
 
-// Validate one request; fill its descriptor (init_mode resolved by caller).
+// Validate one request; fill its descriptor (warm start and rows are set by
+// the caller).
 const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &d) {
   const plan_config &c = h->cfg;
   if (r.N < 1 || r.N > c.max_N) return "N out of range";
-  int ti = find_T(c, r.T), mi = find_M(c, r.M);
+  const int ti = find_T(c, r.T), mi = find_M(c, r.M);
   if (ti < 0) return "T not in T_set";
   if (mi < 0) return "M not in M_set";
-  if ((size_t)r.M * r.T * sizeof(float2) > 60 * 1024) return "M * T too large for the LDS table";
+  if (lds_bytes(r.M, r.T) > 60 * 1024) return "M * T too large for the LDS table";
   if (!finite_all(r.ego, 6) || !std::isfinite(r.kappa_road)) return "non-finite ego state";
   if (r.M > 0 && r.obstacles == nullptr) return "obstacles missing";
   if (r.M > 0 && !finite_all(r.obstacles, 4 * r.M)) return "non-finite obstacle";
   if ((r.mu0 == nullptr) != (r.sigma0 == nullptr)) return "mu0 and sigma0 must be given together";
   if (r.mu0 && (!finite_all(r.mu0, 8) || !finite_all(r.sigma0, 64))) return "non-finite mu0/sigma0";
+  if (r.first_iter < 0 || r.first_iter > (1 << 20)) return "first_iter out of range";
   std::memset(&d, 0, sizeof(d));
   d.T = r.T;
   d.M = r.M;
@@ -261,9 +307,9 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   d.tm_idx = ti * c.n_M + mi;
   d.session = -1;
   d.session_wb = -1;
-  d.seed = r.seed;
-  if (r.first_iter < 0 || r.first_iter > (1 << 20)) return "first_iter out of range";
   d.first_iter = r.first_iter;
+  d.cur_iter = 0;
+  d.seed = r.seed;
   std::memcpy(d.ego, r.ego, sizeof(d.ego));
   d.kappa = r.kappa_road;
   for (int i = 0; i < r.M; ++i)
@@ -284,7 +330,7 @@ int session_slot(plan_handle *h, uint64_t key) {
     h->sess_used[it->second] = ++h->sess_clock;
     return it->second;
   }
-  int ns = (int)h->sess_key.size();
+  const int ns = (int)h->sess_key.size();
   int victim = 0;
   for (int i = 1; i < ns; ++i)
     if (h->sess_used[i] < h->sess_used[victim]) victim = i;
@@ -296,10 +342,22 @@ int session_slot(plan_handle *h, uint64_t key) {
   return victim;
 }
 
-SelArgs sel_args(plan_handle *h) {
+// Warm start from the session store when the request brings none.
+void resolve_session(plan_handle *h, uint64_t key, ReqDesc &d, bool write_back) {
+  if (key == 0) return;
+  const int s = session_slot(h, key);
+  if (d.init_mode == kInitStructured && h->sess_valid[s]) {
+    d.init_mode = kInitSession;
+    d.session = s;
+  }
+  if (write_back) d.session_wb = s;
+}
+
+SelArgs sel_args(plan_handle *h, int l_uniform) {
   SelArgs a;
   a.desc = h->desc;
-  a.slots = h->slots;
+  a.slots = h->act_slots;
+  a.l_uniform = l_uniform;
   a.p = h->p;
   a.zs = h->zs;
   a.resid = h->resid;
@@ -320,76 +378,30 @@ SelArgs sel_args(plan_handle *h) {
   return a;
 }
 
-LowerArgs lower_args(plan_handle *h) {
+LowerArgs lower_args(plan_handle *h, int n_act, int l_uniform) {
   LowerArgs a;
   a.desc = h->desc;
-  a.blocks = h->blocks;
+  a.act_slots = h->act_slots;
+  a.blk_prefix = h->blk_prefix;
+  a.n_act = n_act;
+  a.l_uniform = l_uniform;
   a.basis = h->basis;
   a.basis_off = h->basis_off;
   a.basis_tpad = h->basis_tpad;
   a.step1 = h->step1;
   a.proj = h->proj;
   a.p = h->p;
+  a.dist = h->dist;
+  a.sess = h->sess;
   a.zs = h->zs;
   a.resid = h->resid;
   a.cost = h->cost;
   a.xi_bar_out = nullptr;
   a.xi_star_out = nullptr;
-  a.max_N = h->cfg.max_N;
-  a.obs_stride = 0;
   return a;
 }
 
-
-
-// Stage requests into slots 0..k-1: host descriptors and the workgroup table,
-// then one H2D copy each. Invalid requests are reported and skipped.
-plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int first) {
-  h->staged = 0;
-  h->nblocks = 0;
-  h->lds = 0;
-  h->staged_req.clear();
-  h->staged_session.clear();
-  h->staged_status.assign(n, PLAN_OK);
-  h->staged_total = n;
-  std::unordered_map<uint64_t, int> last_of_session;
-  for (int i = 0; i < n; ++i)
-    if (reqs[i].session_id != 0) last_of_session[reqs[i].session_id] = i;
-  for (int i = 0; i < n; ++i) {
-    if (h->staged >= h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more requests than max_requests");
-    ReqDesc &d = h->h_desc[h->staged];
-    if (const char *why = check_request(h, reqs[i], d)) {
-      h->staged_status[i] = PLAN_E_INVALID;
-      h->err = "request " + std::to_string(first + i) + ": " + why;
-      continue;
-    }
-    const uint64_t sk = reqs[i].session_id;
-    if (sk != 0) {
-      int s = session_slot(h, sk);
-      if (d.init_mode == kInitStructured && h->sess_valid[s]) {
-        d.init_mode = kInitSession;  // device-resident warm start
-        d.session = s;
-      }
-      if (last_of_session[sk] == i) d.session_wb = s;
-    }
-    const int slot = h->staged++;
-    h->staged_req.push_back(i);
-    h->staged_session.push_back(sk);
-    const int nw = (d.T + kWave - 1) / kWave, spb = 4 / nw;
-    const int nb = (d.N + spb - 1) / spb;
-    for (int b = 0; b < nb; ++b) h->h_blocks[h->nblocks + b] = make_int2(slot, b * spb);
-    h->nblocks += nb;
-    h->lds = std::max(h->lds, (size_t)d.M * d.T * sizeof(float2));
-    h->h_slots[slot] = slot;
-  }
-  if (h->staged == 0) return PLAN_OK;
-  HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc) * h->staged, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->blocks, h->h_blocks, sizeof(int2) * h->nblocks, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->slots, h->h_slots, sizeof(int32_t) * h->staged, hipMemcpyHostToDevice, h->stream));
-  return PLAN_OK;
-}
-
-// Event pair around one launch when profiling (kind: 0 init, 1 lower, 2 select).
+// Event pair around one launch when profiling (kind: 0 lower, 1 select).
 hipError_t prof_begin(plan_handle *h, std::pair<hipEvent_t, hipEvent_t> &ev) {
   if (h->ev_free.empty()) {
     hipEvent_t a, b;
@@ -418,26 +430,90 @@ plan_status timed(plan_handle *h, int kind, F &&launch, const char *what) {
   return PLAN_OK;
 }
 
+// One upper iteration of n_act resident slots (the act arrays are on the
+// device): lower_kernel then select_update_kernel.
+plan_status launch_iteration(plan_handle *h, int n_act, int nblocks, size_t lds, int l_uniform) {
+  const LowerArgs la = lower_args(h, n_act, l_uniform);
+  const SelArgs sa = sel_args(h, l_uniform);
+  plan_status st = timed(h, 0, [&] { return launch_lower(la, h->mp, nblocks, lds, h->stream); }, "lower_kernel");
+  if (st == PLAN_OK)
+    st = timed(h, 1, [&] { return launch_select(sa, h->mp, n_act, h->stream); }, "select_update_kernel");
+  return st;
+}
+
+// Batch mode: stage requests into slots 0..k-1 with consecutive rows.
+plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int first) {
+  if (!h->resident.empty() || !h->queue.empty())
+    return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them before batch calls");
+  h->staged = 0;
+  h->nblocks = 0;
+  h->lds = 0;
+  h->staged_req.clear();
+  h->staged_status.assign(n, PLAN_OK);
+  h->staged_total = n;
+  std::unordered_map<uint64_t, int> last_of_session;
+  for (int i = 0; i < n; ++i)
+    if (reqs[i].session_id != 0) last_of_session[reqs[i].session_id] = i;
+  int64_t row = 0;
+  int32_t *act = h->h_act, *prefix = h->h_act + h->cfg.max_requests;
+  for (int i = 0; i < n; ++i) {
+    if (h->staged >= h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more requests than max_requests");
+    ReqDesc &d = h->h_desc[h->staged];
+    if (const char *why = check_request(h, reqs[i], d)) {
+      h->staged_status[i] = PLAN_E_INVALID;
+      h->err = "request " + std::to_string(first + i) + ": " + why;
+      continue;
+    }
+    if (row + d.N > h->rows) return fail(h, PLAN_E_NOMEM, "batch exceeds the sample budget");
+    const uint64_t sk = reqs[i].session_id;
+    resolve_session(h, sk, d, sk != 0 && last_of_session[sk] == i);
+    d.row_off = row;
+    row += d.N;
+    const int slot = h->staged++;
+    h->staged_req.push_back(i);
+    act[slot] = slot;
+    prefix[slot] = h->nblocks;
+    h->nblocks += blocks_for(d.N, d.T);
+    h->lds = std::max(h->lds, lds_bytes(d.M, d.T));
+  }
+  prefix[h->staged] = h->nblocks;
+  if (h->staged == 0) return PLAN_OK;
+  HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc) * h->staged, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->act_slots, act, sizeof(int32_t) * h->staged, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->blk_prefix, prefix, sizeof(int32_t) * (h->staged + 1), hipMemcpyHostToDevice,
+                            h->stream));
+  return PLAN_OK;
+}
+
 plan_status launch_impl(plan_handle *h) {
   if (h->staged == 0) return PLAN_OK;
-  const SelArgs sa = sel_args(h);
-  const LowerArgs la = lower_args(h);
-  plan_status st = timed(h, 0, [&] { return launch_init(sa, h->mp, h->staged, h->stream); }, "init_kernel");
-  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) {
-    st = timed(h, 1, [&] { return launch_lower(la, h->mp, h->nblocks, h->lds, h->stream); }, "lower_kernel");
-    if (st == PLAN_OK)
-      st = timed(h, 2, [&] { return launch_select(sa, h->mp, h->staged, l, h->stream); }, "select_update_kernel");
-  }
+  plan_status st = PLAN_OK;
+  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l)
+    st = launch_iteration(h, h->staged, h->nblocks, h->lds, l);
   return st;
+}
+
+void fill_result(plan_result &o, const ResultRec &R, const DistState &ds, double latency) {
+  std::memset(&o, 0, sizeof(o));
+  o.status = R.status;
+  o.flags = R.flags;
+  o.best_index = R.best;
+  o.iterations = R.iterations;
+  std::memcpy(o.p_best, R.p, sizeof(o.p_best));
+  std::memcpy(o.xi_best, R.xi, sizeof(o.xi_best));
+  o.cost_upper = R.cost_upper;
+  o.residual = R.residual;
+  std::memcpy(o.mu, ds.mu, sizeof(o.mu));
+  std::memcpy(o.sigma, ds.sigma, sizeof(o.sigma));
+  o.latency_s = latency;
 }
 
 // Wait for the staged batch and copy results into out[0..staged_total).
 plan_status collect_impl(plan_handle *h, plan_result *out, double elapsed) {
-  std::vector<DistState> ds(h->staged);
   if (h->staged > 0) {
     HIP_TRY(h, hipMemcpyAsync(h->h_result, h->result, sizeof(ResultRec) * h->staged, hipMemcpyDeviceToHost,
                               h->stream));
-    HIP_TRY(h, hipMemcpyAsync(ds.data(), h->dist, sizeof(DistState) * h->staged, hipMemcpyDeviceToHost,
+    HIP_TRY(h, hipMemcpyAsync(h->h_dist, h->dist, sizeof(DistState) * h->staged, hipMemcpyDeviceToHost,
                               h->stream));
   }
   HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -450,25 +526,43 @@ plan_status collect_impl(plan_handle *h, plan_result *out, double elapsed) {
   }
   for (int s = 0; s < h->staged; ++s) {
     plan_result &o = out[h->staged_req[s]];
-    const ResultRec &R = h->h_result[s];
-    o.status = R.status;
-    o.flags = R.flags;
-    o.best_index = R.best;
-    o.iterations = R.iterations;
-    std::memcpy(o.p_best, R.p, sizeof(o.p_best));
-    std::memcpy(o.xi_best, R.xi, sizeof(o.xi_best));
-    o.cost_upper = R.cost_upper;
-    o.residual = R.residual;
-    std::memcpy(o.mu, ds[s].mu, sizeof(o.mu));
-    std::memcpy(o.sigma, ds[s].sigma, sizeof(o.sigma));
-    o.latency_s = elapsed;
-    if (R.status != 0) {
-      worst = std::min(worst, (plan_status)R.status);
-    } else if (h->h_desc[s].session_wb >= 0) {
-      h->sess_valid[h->h_desc[s].session_wb] = 1;
-    }
+    fill_result(o, h->h_result[s], h->h_dist[s], elapsed);
+    if (o.status != 0) worst = std::min(worst, (plan_status)o.status);
+    else if (h->h_desc[s].session_wb >= 0) h->sess_valid[h->h_desc[s].session_wb] = 1;
   }
   return worst;
+}
+
+// ---- served mode: first-fit allocation of contiguous sample rows
+
+bool take_rows(plan_handle *h, int N, int64_t &off) {
+  for (auto it = h->free_rows.begin(); it != h->free_rows.end(); ++it) {
+    if (it->second - it->first >= N) {
+      off = it->first;
+      const int64_t end = it->second;
+      h->free_rows.erase(it);
+      if (off + N < end) h->free_rows[off + N] = end;
+      return true;
+    }
+  }
+  return false;
+}
+
+void give_rows(plan_handle *h, int64_t off, int N) {
+  int64_t b = off, e = off + N;
+  auto next = h->free_rows.lower_bound(b);
+  if (next != h->free_rows.end() && next->first == e) {
+    e = next->second;
+    next = h->free_rows.erase(next);
+  }
+  if (next != h->free_rows.begin()) {
+    auto prev = std::prev(next);
+    if (prev->second == b) {
+      b = prev->first;
+      h->free_rows.erase(prev);
+    }
+  }
+  h->free_rows[b] = e;
 }
 
 void free_handle(plan_handle *h) {
@@ -485,9 +579,9 @@ void free_handle(plan_handle *h) {
   if (h->own_mem && h->mem.base) hipFree(h->mem.base);
   if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
   if (h->h_desc) hipHostFree(h->h_desc);
-  if (h->h_blocks) hipHostFree(h->h_blocks);
-  if (h->h_slots) hipHostFree(h->h_slots);
+  if (h->h_act) hipHostFree(h->h_act);
   if (h->h_result) hipHostFree(h->h_result);
+  if (h->h_dist) hipHostFree(h->h_dist);
   delete h;
 }
 
@@ -557,6 +651,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   plan_handle *h = new plan_handle();
   h->cfg = *cfg;
   h->mp = method_params(*cfg);
+  h->rows = budget_rows(*cfg);
   const plan_config &c = h->cfg;
   // ---- FP64 precompute, once per T and per (T, M)
   std::vector<BasisTable> bts(c.n_T);
@@ -598,7 +693,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     h->own_mem = true;
   }
   const Layout &L = h->lay;
-  const size_t S = (size_t)c.max_requests, N = (size_t)c.max_N;
+  const size_t S = (size_t)c.max_requests, R = (size_t)h->rows;
   h->basis = (float *)h->mem.take(L.basis);
   h->step1 = (float *)h->mem.take(L.step1);
   h->proj = (float *)h->mem.take(L.proj);
@@ -607,25 +702,25 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->desc = (ReqDesc *)h->mem.take(L.desc);
   h->dist = (DistState *)h->mem.take(L.dist);
   h->result = (ResultRec *)h->mem.take(L.result);
-  h->slots = (int32_t *)h->mem.take(L.slots);
+  h->act_slots = (int32_t *)h->mem.take(L.act);
+  h->blk_prefix = h->act_slots + S;
   h->p = (float *)h->mem.take(L.p);
   h->zs = (float *)h->mem.take(L.zs);
   h->resid = (float *)h->mem.take(L.rc);
-  h->cost = h->resid + S * N;
-  h->blocks = (int2 *)h->mem.take(L.blocks);
+  h->cost = h->resid + R;
   h->sess = (double *)h->mem.take(L.sess);
   h->xi_out = (double *)h->mem.take(L.xiout);
   elite_sizes(c, c.max_N, h->max_ces, h->max_es);
   if (c.trace) {
     h->tr_p = (float *)h->mem.take(L.tr_p);
     h->tr_r = (float *)h->mem.take(L.tr_rc);
-    h->tr_c = h->tr_r + S * c.upper_iters * N;
+    h->tr_c = h->tr_r + S * c.upper_iters * c.max_N;
     h->tr_ces = (int32_t *)h->mem.take(L.tr_idx);
     h->tr_es = h->tr_ces + S * c.upper_iters * h->max_ces;
     h->tr_mu = (double *)h->mem.take(L.tr_dist);
     h->tr_sigma = h->tr_mu + S * c.upper_iters * 8;
   }
-  if (!h->xi_out) {
+  if (!h->xi_out || (c.trace && !h->tr_mu)) {
     g_create_error = "internal: workspace carve failed";
     free_handle(h);
     return PLAN_E_NOMEM;
@@ -633,6 +728,8 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->sess_key.assign(max_sessions(c), 0);
   h->sess_used.assign(max_sessions(c), 0);
   h->sess_valid.assign(max_sessions(c), 0);
+  h->slot_busy.assign(S, 0);
+  h->free_rows[0] = h->rows;
   // ---- stream and pinned staging
   hipError_t e = hipSuccess;
   if (c.stream) {
@@ -642,9 +739,9 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     h->own_stream = e == hipSuccess;
   }
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_desc, sizeof(ReqDesc) * S);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_blocks, sizeof(int2) * S * N);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_slots, sizeof(int32_t) * S);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_act, sizeof(int32_t) * (2 * S + 1));
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_result, sizeof(ResultRec) * S);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_dist, sizeof(DistState) * S);
   // ---- upload tables
   if (e == hipSuccess) {
     std::vector<float> basis_all;
@@ -681,7 +778,7 @@ void plan_destroy(plan_handle *h) { free_handle(h); }
 plan_status plan_stage(plan_handle *h, const plan_request *reqs, int32_t n) {
   if (!h || (n > 0 && !reqs) || n < 0) return fail(h, PLAN_E_INVALID, "bad arguments");
   if (n > h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more requests than max_requests");
-  h->t_stage = std::chrono::steady_clock::now();
+  h->t_stage = Clock::now();
   plan_status st = stage_impl(h, reqs, n, 0);
   if (st != PLAN_OK) return st;
   return hipStreamSynchronize(h->stream) == hipSuccess ? PLAN_OK : fail(h, PLAN_E_DEVICE, "stage sync");
@@ -694,24 +791,35 @@ plan_status plan_launch(plan_handle *h) {
 
 plan_status plan_collect(plan_handle *h, plan_result *out) {
   if (!h || !out) return fail(h, PLAN_E_INVALID, "bad arguments");
-  double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - h->t_stage).count();
+  const double el = std::chrono::duration<double>(Clock::now() - h->t_stage).count();
   return collect_impl(h, out, el);
 }
 
 plan_status plan_solve_batch(plan_handle *h, const plan_request *reqs, int32_t n, plan_result *out) {
   if (!h || n < 0 || (n > 0 && (!reqs || !out))) return fail(h, PLAN_E_INVALID, "bad arguments");
   plan_status worst = PLAN_OK;
-  for (int first = 0; first < n; first += h->cfg.max_requests) {
-    const int m = std::min(h->cfg.max_requests, n - first);
-    const auto t0 = std::chrono::steady_clock::now();
+  int first = 0;
+  while (first < n) {
+    // a group: at most max_requests requests whose samples fit the budget
+    int m = 0;
+    int64_t rows = 0;
+    while (first + m < n && m < h->cfg.max_requests) {
+      const int Nr = reqs[first + m].N;
+      const bool counted = Nr >= 1 && Nr <= h->cfg.max_N;
+      if (m > 0 && counted && rows + Nr > h->rows) break;
+      if (counted) rows += Nr;
+      ++m;
+    }
+    const auto t0 = Clock::now();
     plan_status st = stage_impl(h, reqs + first, m, first);
     if (st == PLAN_OK) st = launch_impl(h);
     if (st != PLAN_OK) return st;
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "solve");
-    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const double el = std::chrono::duration<double>(Clock::now() - t0).count();
     st = collect_impl(h, out + first, el);
     worst = std::min(worst, st);
+    first += m;
   }
   return worst;
 }
@@ -719,6 +827,8 @@ plan_status plan_solve_batch(plan_handle *h, const plan_request *reqs, int32_t n
 plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const double *p, int32_t N,
                              double *xi_bar, double *xi_star, double *resid, double *cost_upper) {
   if (!h || !req || !p) return fail(h, PLAN_E_INVALID, "bad arguments");
+  if (!h->resident.empty() || !h->queue.empty())
+    return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them before batch calls");
   plan_request r = *req;
   r.N = N;
   r.mu0 = r.sigma0 = nullptr;
@@ -727,18 +837,22 @@ plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const doub
   if (const char *why = check_request(h, r, d)) return fail(h, PLAN_E_INVALID, why);
   if (!finite_all(p, 8 * N)) return fail(h, PLAN_E_INVALID, "non-finite p");
   d.init_mode = kInitForced;
+  d.row_off = 0;
   std::vector<float> pf((size_t)N * 8);
   for (size_t i = 0; i < pf.size(); ++i) pf[i] = (float)p[i];
-  const int nw = (d.T + kWave - 1) / kWave, spb = 4 / nw;
-  const int nb = (d.N + spb - 1) / spb;
-  for (int b = 0; b < nb; ++b) h->h_blocks[b] = make_int2(0, b * spb);
+  const int nb = blocks_for(d.N, d.T);
+  const int S = h->cfg.max_requests;
+  h->h_act[0] = 0;
+  h->h_act[S] = 0;
+  h->h_act[S + 1] = nb;
   HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc), hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->blocks, h->h_blocks, sizeof(int2) * nb, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->act_slots, h->h_act, sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->blk_prefix, h->h_act + S, 2 * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, hipMemcpyAsync(h->p, pf.data(), pf.size() * 4, hipMemcpyHostToDevice, h->stream));
-  LowerArgs la = lower_args(h);
+  LowerArgs la = lower_args(h, 1, 0);
   la.xi_bar_out = h->xi_out;
   la.xi_star_out = h->xi_out + (size_t)h->cfg.max_N * 22;
-  HIP_TRY(h, launch_lower(la, h->mp, nb, (size_t)d.M * d.T * sizeof(float2), h->stream));
+  HIP_TRY(h, launch_lower(la, h->mp, nb, lds_bytes(d.M, d.T), h->stream));
   std::vector<double> xo((size_t)N * 22 * 2);
   std::vector<float> rc((size_t)N * 2);
   HIP_TRY(h, hipMemcpyAsync(xo.data(), la.xi_bar_out, (size_t)N * 22 * 8, hipMemcpyDeviceToHost, h->stream));
@@ -789,12 +903,139 @@ plan_status plan_get_trace(plan_handle *h, int32_t i, double *p, double *resid, 
     const size_t ib = (size_t)slot * L + l;
     if (ces)
       HIP_TRY(h, hipMemcpy(ces + l * d.n_ces, h->tr_ces + ib * h->max_ces, d.n_ces * 4, hipMemcpyDeviceToHost));
-    if (es)
-      HIP_TRY(h, hipMemcpy(es + l * d.n_es, h->tr_es + ib * h->max_es, d.n_es * 4, hipMemcpyDeviceToHost));
+    if (es) HIP_TRY(h, hipMemcpy(es + l * d.n_es, h->tr_es + ib * h->max_es, d.n_es * 4, hipMemcpyDeviceToHost));
     if (mu) HIP_TRY(h, hipMemcpy(mu + l * 8, h->tr_mu + ib * 8, 64, hipMemcpyDeviceToHost));
     if (sigma) HIP_TRY(h, hipMemcpy(sigma + l * 64, h->tr_sigma + ib * 64, 512, hipMemcpyDeviceToHost));
   }
   return PLAN_OK;
+}
+
+// ---- served mode
+
+plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticket) {
+  if (!h || !req || !ticket) return fail(h, PLAN_E_INVALID, "bad arguments");
+  ReqDesc tmp;
+  if (const char *why = check_request(h, *req, tmp)) return fail(h, PLAN_E_INVALID, why);
+  if (req->N > h->rows) return fail(h, PLAN_E_NOMEM, "request larger than the sample budget");
+  Pending pd;
+  pd.ticket = h->next_ticket++;
+  pd.req = *req;
+  if (req->M > 0) pd.obs.assign(req->obstacles, req->obstacles + 4 * req->M);
+  if (req->mu0) {
+    pd.mu0.assign(req->mu0, req->mu0 + 8);
+    pd.sigma0.assign(req->sigma0, req->sigma0 + 64);
+  }
+  pd.submit = Clock::now();
+  *ticket = pd.ticket;
+  h->queue.push_back(std::move(pd));
+  return PLAN_OK;
+}
+
+plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) {
+  if (!h) return PLAN_E_INVALID;
+  h->staged = 0;  // batch slots are reused
+  const int S = h->cfg.max_requests;
+  // Admission: first come first served while a slot and the rows are free.
+  std::vector<int> admitted;
+  while (!h->queue.empty()) {
+    Pending &pd = h->queue.front();
+    int slot = -1;
+    for (int s = 0; s < S; ++s)
+      if (!h->slot_busy[s]) {
+        slot = s;
+        break;
+      }
+    int64_t off = 0;
+    if (slot < 0 || !take_rows(h, pd.req.N, off)) break;
+    plan_request r = pd.req;
+    r.obstacles = pd.obs.empty() ? nullptr : pd.obs.data();
+    r.mu0 = pd.mu0.empty() ? nullptr : pd.mu0.data();
+    r.sigma0 = pd.sigma0.empty() ? nullptr : pd.sigma0.data();
+    ReqDesc &d = h->h_desc[slot];
+    check_request(h, r, d);  // validated at submit
+    resolve_session(h, r.session_id, d, r.session_id != 0);
+    d.row_off = off;
+    d.cur_iter = 0;
+    h->slot_busy[slot] = 1;
+    Resident rs;
+    rs.ticket = pd.ticket;
+    rs.slot = slot;
+    rs.row_off = off;
+    rs.N = r.N;
+    rs.T = r.T;
+    rs.session_wb = d.session_wb;
+    rs.submit = pd.submit;
+    h->resident.push_back(rs);
+    admitted.push_back(slot);
+    h->queue.pop_front();
+  }
+  for (int slot : admitted)
+    HIP_TRY(h, hipMemcpyAsync(h->desc + slot, h->h_desc + slot, sizeof(ReqDesc), hipMemcpyHostToDevice,
+                              h->stream));
+  const int n_act = (int)h->resident.size();
+  if (n_act > 0) {
+    // One upper iteration for every resident request.
+    int32_t *act = h->h_act, *prefix = h->h_act + S;
+    int nblocks = 0;
+    size_t lds = 0;
+    for (int i = 0; i < n_act; ++i) {
+      const Resident &rs = h->resident[i];
+      act[i] = rs.slot;
+      prefix[i] = nblocks;
+      nblocks += blocks_for(rs.N, rs.T);
+      const ReqDesc &d = h->h_desc[rs.slot];
+      lds = std::max(lds, lds_bytes(d.M, d.T));
+    }
+    prefix[n_act] = nblocks;
+    HIP_TRY(h, hipMemcpyAsync(h->act_slots, act, sizeof(int32_t) * n_act, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->blk_prefix, prefix, sizeof(int32_t) * (n_act + 1), hipMemcpyHostToDevice,
+                              h->stream));
+    plan_status st = launch_iteration(h, n_act, nblocks, lds, -1);
+    if (st != PLAN_OK) return st;
+    std::vector<int> finished;
+    for (int i = 0; i < n_act; ++i) {
+      Resident &rs = h->resident[i];
+      if (++rs.iters == h->cfg.upper_iters) {
+        finished.push_back(i);
+        HIP_TRY(h, hipMemcpyAsync(h->h_result + rs.slot, h->result + rs.slot, sizeof(ResultRec),
+                                  hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(h->h_dist + rs.slot, h->dist + rs.slot, sizeof(DistState),
+                                  hipMemcpyDeviceToHost, h->stream));
+      }
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const auto now = Clock::now();
+    for (int k = (int)finished.size() - 1; k >= 0; --k) {
+      const int i = finished[k];
+      const Resident rs = h->resident[i];
+      plan_result o;
+      fill_result(o, h->h_result[rs.slot], h->h_dist[rs.slot],
+                  std::chrono::duration<double>(now - rs.submit).count());
+      if (o.status == 0 && rs.session_wb >= 0) h->sess_valid[rs.session_wb] = 1;
+      h->done[rs.ticket] = o;
+      h->slot_busy[rs.slot] = 0;
+      give_rows(h, rs.row_off, rs.N);
+      h->resident.erase(h->resident.begin() + i);
+    }
+  }
+  if (n_active) *n_active = (int32_t)h->resident.size();
+  if (n_queued) *n_queued = (int32_t)h->queue.size();
+  return PLAN_OK;
+}
+
+plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out) {
+  if (!h || !out) return fail(h, PLAN_E_INVALID, "bad arguments");
+  auto it = h->done.find(ticket);
+  if (it != h->done.end()) {
+    *out = it->second;
+    h->done.erase(it);
+    return PLAN_OK;
+  }
+  for (const auto &rs : h->resident)
+    if (rs.ticket == ticket) return PLAN_E_BUSY;
+  for (const auto &pd : h->queue)
+    if (pd.ticket == ticket) return PLAN_E_BUSY;
+  return fail(h, PLAN_E_INVALID, "unknown ticket");
 }
 
 plan_status plan_profile(plan_handle *h, int32_t enable) {
@@ -802,7 +1043,7 @@ plan_status plan_profile(plan_handle *h, int32_t enable) {
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   for (auto &e : h->ev_pending) h->ev_free.push_back(e.second);
   h->ev_pending.clear();
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 2; ++k) {
     h->prof_ms[k] = 0.0;
     h->prof_count[k] = 0;
   }
@@ -810,7 +1051,7 @@ plan_status plan_profile(plan_handle *h, int32_t enable) {
   return PLAN_OK;
 }
 
-plan_status plan_profile_read(plan_handle *h, double ms[3], int64_t count[3]) {
+plan_status plan_profile_read(plan_handle *h, double ms[2], int64_t count[2]) {
   if (!h || !ms || !count) return fail(h, PLAN_E_INVALID, "bad arguments");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   for (auto &e : h->ev_pending) {
@@ -821,7 +1062,7 @@ plan_status plan_profile_read(plan_handle *h, double ms[3], int64_t count[3]) {
     h->ev_free.push_back(e.second);
   }
   h->ev_pending.clear();
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 2; ++k) {
     ms[k] = h->prof_ms[k];
     count[k] = h->prof_count[k];
   }

@@ -1,13 +1,14 @@
 // kernels.hip -- CDNA4 (gfx950) kernels of the batched bi-level planner.
 //
-//   lower_kernel          Alg. 1 Steps 1-2 and the residual for every sample
-//                         of every resident request: the Step-1 QP through
-//                         its precomputed affine map (Sec. III-C, eq. over_3),
-//                         K iterations of Alg. 2, then r_j and c_u,j.
-//   init_kernel           sampling distribution of iteration 0 and its draw.
-//   select_update_kernel  ConstraintEliteSet / EliteSet (Alg. 1), the update
-//                         of eqs. mean_update, cov_update, s_formula (FP64),
-//                         the Cholesky factor and the next iteration's draw.
+//   lower_kernel          for every sample of every resident request: the draw
+//                         p_j ~ N(mu, Sigma) of Alg. 1 (Philox4x32-10 +
+//                         Box-Muller), the Step-1 QP through its precomputed
+//                         affine map (Sec. III-C, eq. over_3), K iterations of
+//                         Alg. 2, then r_j and c_u,j.
+//   select_update_kernel  ConstraintEliteSet / EliteSet (Alg. 1) by radix
+//                         selection, the update of eqs. mean_update,
+//                         cov_update, s_formula (FP64) and the Cholesky factor
+//                         used by the next draw.
 //
 // Lower-level algebra (mathematically identical to Alg. 2; the oracle does it
 // the literal way). With the boundary conditions of eqs.
@@ -48,43 +49,200 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ float bcast(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
+__device__ __forceinline__ uint32_t bcastu(uint32_t v, int src) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
 
-__device__ __forceinline__ float xorf(float v, int m) { return __shfl_xor(v, m, 64); }
+// Cross-lane moves of gfx950: v_permlane32_swap exchanges the upper 32 lanes
+// of a with the lower 32 lanes of b; v_permlane16_swap exchanges rows 1 and 3
+// of a with rows 0 and 2 of b (a row is 16 lanes). DPP row_mirror reads lane
+// 15 - i of the row, row_half_mirror lane 7 - i of the half row, quad_perm
+// permutes within groups of 4.
+__device__ __forceinline__ void swap32(float &a, float &b) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float &a, float &b) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadSwap2 = 0x4e;  // quad_perm [2,3,0,1]
+constexpr int kDppQuadSwap1 = 0xb1;  // quad_perm [1,0,3,2]
 
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += xorf(v, m);
+  float a = v, b = v;
+  swap32(a, b);  // a + b = own + (lane ^ 32)
+  v = a + b;
+  a = v;
+  b = v;
+  swap16(a, b);  // + (lane ^ 16)
+  v = a + b;
+  v += dpp<kDppRowMirror>(v);
+  v += dpp<kDppRowHalfMirror>(v);
+  v += dpp<kDppQuadSwap2>(v);
+  v += dpp<kDppQuadSwap1>(v);
   return v;
 }
 
-// Sum over the 64 lanes of 16 per-lane values; lane l returns value l >> 2.
+// Sum over the 64 lanes of 16 per-lane values; every lane l returns value
+// l >> 2. Each step halves the values a lane holds by pairing it with a lane
+// that differs in one more index bit (lane bits 5, 4, 3, 2), then the last
+// two steps finish the sum inside groups of 4 lanes.
 __device__ __forceinline__ float reduce16(const float (&v)[16], int lane) {
-  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
   float a[8], b[4], c[2];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    float keep = h5 ? v[i + 8] : v[i];
-    float send = h5 ? v[i] : v[i + 8];
-    a[i] = keep + xorf(send, 32);
+    float x = v[i], y = v[i + 8];
+    swap32(x, y);  // lanes < 32: (v[i], partner v[i]); lanes >= 32: (partner v[i+8], v[i+8])
+    a[i] = x + y;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    float keep = h4 ? a[i + 4] : a[i];
-    float send = h4 ? a[i] : a[i + 4];
-    b[i] = keep + xorf(send, 16);
+    float x = a[i], y = a[i + 4];
+    swap16(x, y);
+    b[i] = x + y;
   }
+  const bool h3 = lane & 8, h2 = lane & 4;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     float keep = h3 ? b[i + 2] : b[i];
     float send = h3 ? b[i] : b[i + 2];
-    c[i] = keep + xorf(send, 8);
+    c[i] = keep + dpp<kDppRowMirror>(send);  // partner 15 - i: other bit 3, same row
   }
   float keep = h2 ? c[1] : c[0];
   float send = h2 ? c[0] : c[1];
-  float d = keep + xorf(send, 4);
-  d += xorf(d, 2);
-  d += xorf(d, 1);
+  float d = keep + dpp<kDppRowHalfMirror>(send);  // partner 7 - i: other bit 2, same bit 3
+  d += dpp<kDppQuadSwap2>(d);
+  d += dpp<kDppQuadSwap1>(d);
   return d;
+}
+
+// ---------------------------------------------------------------------------
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the request
+// seed; counter (sample, upper iteration, block, 0). Box-Muller turns pairs of
+// uniforms in (0, 1] into normals.
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * c[0];
+    uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+    uint32_t lo1 = 0xCD9E8D57u * c[2];
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    uint32_t n0 = hi1 ^ c[1] ^ k0;
+    uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ void rng_block(uint64_t seed, int j, int l, int blk, uint32_t w[4]) {
+  w[0] = (uint32_t)j;
+  w[1] = (uint32_t)l;
+  w[2] = (uint32_t)blk;
+  w[3] = 0u;
+  philox4x32_10(w, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ float u01(uint32_t x) {
+  return (float)((x >> 8) + 1u) * (1.0f / 16777216.0f);
+}
+
+__device__ __forceinline__ void normals2(uint32_t a, uint32_t b, float &n0, float &n1) {
+  float rad = sqrtf(-2.0f * logf(u01(a)));
+  float s, c;
+  sincospif(2.0f * u01(b), &s, &c);
+  n0 = rad * c;
+  n1 = rad * s;
+}
+
+// Lower Cholesky factor of A + jitter I (8x8, FP64). Returns false if not
+// positive definite.
+__device__ bool chol8(const double *A, double jitter, double *Lo) {
+  for (int i = 0; i < 64; ++i) Lo[i] = 0.0;
+  for (int jc = 0; jc < 8; ++jc) {
+    double d = A[jc * 8 + jc] + jitter;
+    for (int k = 0; k < jc; ++k) d -= Lo[jc * 8 + k] * Lo[jc * 8 + k];
+    if (!(d > 0.0)) return false;
+    double l = sqrt(d);
+    Lo[jc * 8 + jc] = l;
+    for (int i = jc + 1; i < 8; ++i) {
+      double s = A[i * 8 + jc];
+      for (int k = 0; k < jc; ++k) s -= Lo[i * 8 + k] * Lo[jc * 8 + k];
+      Lo[i * 8 + jc] = s / l;
+    }
+  }
+  return true;
+}
+
+// Exact moments of the structured initial sampler.
+__device__ void structured_moments(const MethodParams &P, double *mu, double *sg) {
+  double mc = (P.lane_c[0] + P.lane_c[1] + P.lane_c[2]) / 3.0;
+  double vc = 0.0;
+  for (int i = 0; i < 3; ++i) vc += (P.lane_c[i] - mc) * (P.lane_c[i] - mc);
+  vc /= 3.0;
+  double vm = 0.5 * (P.vd_lo + P.vd_hi);
+  double vv = (P.vd_hi - P.vd_lo) * (P.vd_hi - P.vd_lo) / 12.0;
+  for (int i = 0; i < 64; ++i) sg[i] = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    mu[a] = mc;
+    mu[4 + a] = vm;
+    for (int b = 0; b < 4; ++b) sg[a * 8 + b] = vc + (a == b ? P.lane_sigma * P.lane_sigma : 0.0);
+    sg[(4 + a) * 8 + 4 + a] = vv;
+  }
+}
+
+// Sample j of upper iteration l, drawn by one wave: lanes 0-2 each run one
+// Philox block, lanes 0-3 one Box-Muller pair; the eight values are returned
+// uniform across the wave. mu/chol point to LDS (Gaussian draws only).
+__device__ void wave_draw(const MethodParams &P, uint64_t seed, int j, int l, bool structured,
+                          const double *mu, const double *chol, int lane, float (&p)[8]) {
+  uint32_t w[4];
+  rng_block(seed, j, l, lane < 3 ? lane : 2, w);
+  // Box-Muller pair m (lane m < 4) uses words 2(m & 1), 2(m & 1) + 1 of block m >> 1.
+  const int src = (lane & 3) >> 1;
+  uint32_t w0 = __shfl(w[0], src, 64), w1 = __shfl(w[1], src, 64);
+  uint32_t w2 = __shfl(w[2], src, 64), w3 = __shfl(w[3], src, 64);
+  const bool odd = lane & 1;
+  float n0, n1;
+  normals2(odd ? w2 : w0, odd ? w3 : w1, n0, n1);
+  float z[8];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    z[2 * m] = bcast(n0, m);
+    z[2 * m + 1] = bcast(n1, m);
+  }
+  if (structured) {
+    const uint32_t sel = bcastu(w[0], 2);
+    const int ln = (int)(((uint64_t)sel * 3u) >> 32);
+    const double lc = P.lane_c[ln];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      p[m] = (float)(lc + P.lane_sigma * (double)z[m]);
+      const uint32_t wv = bcastu(w[m], 1);
+      const double u = (double)((wv >> 8) + 1u) * (1.0 / 16777216.0);
+      p[4 + m] = (float)(P.vd_lo + (P.vd_hi - P.vd_lo) * u);
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      double s = mu[a];
+#pragma unroll
+      for (int b = 0; b <= a; ++b) s += chol[a * 8 + b] * (double)z[b];
+      p[a] = (float)s;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -94,12 +252,12 @@ struct Lane {
   // basis rows of this lane's instant (free columns)
   float bx[8], bdx[8], bddx[8];
   float by7, bdy7, bddy7;
-  // fixed part of the trajectory (relative x frame)
+  // fixed part of the trajectory (relative x frame, without vx0)
   float xf, xdf, xddf, yf, ydf, yddf;
 };
 
 struct Scal {
-  float vx0, rho, ia2, ib2, ell_a;
+  float vx0, rho, ia, ib, ell_a, ell_b;
   float v_min, v_max, a_max, kmax, inv_kmax, c_max, kappa_abs, y_lb, y_ub, v_eps;
 };
 
@@ -133,77 +291,76 @@ __device__ __forceinline__ State6 eval_traj(const Lane &L, const float (&zs)[15]
   return s;
 }
 
+// Neighbour corrections at this lane's instant, in ellipse-scaled units:
+// sum_i (max(1, 1/r_i) - 1) (dx_i / a, dy_i / b), r_i the normalised
+// distance (closed form of step split_alpha_o with the clip of clip_d_o);
+// at the centre (r = 0) alpha = 0 and d = 1 give (1, 0). The table holds two
+// neighbours per float4 entry, pre-divided by (a, b); loads run one entry
+// ahead of the arithmetic.
+__device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, int npair, int T, int t,
+                                               float xs, float ys, float &ax, float &ay) {
+  ax = 0.f;
+  ay = 0.f;
+  if (npair == 0) return;
+  float4 cur = obs[t];
+  for (int c = 0; c < npair; ++c) {
+    float4 nxt = obs[(c + 1 < npair ? c + 1 : c) * T + t];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float dx = xs - (h ? cur.z : cur.x), dy = ys - (h ? cur.w : cur.y);
+      const float q = fmaf(dx, dx, dy * dy);
+      if (q < 1.f) {
+        const float f = (q > 0.f ? frsq(q) : 1.f) - 1.f;
+        ax = fmaf(f, dx, ax + (q > 0.f ? 0.f : 1.f));
+        ay = fmaf(f, dy, ay);
+      }
+    }
+    cur = nxt;
+  }
+}
+
 // One target pass (steps split_alpha_o .. update_slack of Alg. 2) at this
 // lane's instant, accumulated into the lane's share of N^T g.
 __device__ __forceinline__ void target_pass(const Lane &L, const Scal &S, const float (&zs)[15],
-                                            const float2 *__restrict__ obs, int M, int T,
-                                            int t, bool tv, float &da_prev, float (&g)[16]) {
+                                            const float4 *__restrict__ obs, int npair, int T, int t,
+                                            bool tv, float &da_prev, float (&g)[16]) {
   State6 s = eval_traj(L, zs, S.vx0);
-  // neighbours: target minus trajectory, summed over i
-  float dox = 0.f, doy = 0.f;
-  for (int i = 0; i < M; ++i) {
-    float2 o = obs[i * T + t];
-    float dx = s.x - o.x, dy = s.y - o.y;
-    float q = fmaf(dx * dx, S.ia2, dy * dy * S.ib2);
-    if (q < 1.f) {
-      if (q > 0.f) {
-        float f = frsq(q) - 1.f;
-        dox = fmaf(f, dx, dox);
-        doy = fmaf(f, dy, doy);
-      } else {
-        dox += S.ell_a;  // centre: alpha = 0, d = 1
-      }
-    }
-  }
+  float ax, ay;
+  neighbour_pass(obs, npair, T, t, s.x * S.ia, s.y * S.ib, ax, ay);
+  float dox = ax * S.ell_a, doy = ay * S.ell_b;
   // velocity / acceleration polar variables and their clips
-  float v2 = fmaf(s.xd, s.xd, s.yd * s.yd);
-  float a2 = fmaf(s.xdd, s.xdd, s.ydd * s.ydd);
-  float rv = v2 > 0.f ? frsq(v2) : 0.f;
-  float ra = a2 > 0.f ? frsq(a2) : 0.f;
-  float vn = v2 * rv, an = a2 * ra;
-  float cv = v2 > 0.f ? s.xd * rv : 1.f, sv = s.yd * rv;
-  float ca = a2 > 0.f ? s.xdd * ra : 1.f, sa = s.ydd * ra;
-  float sig = fabsf(sa * cv - ca * sv);
-  float vlo = fmaxf(S.v_min, fsqrt(da_prev * sig * S.inv_kmax));
+  const float v2 = fmaf(s.xd, s.xd, s.yd * s.yd);
+  const float a2 = fmaf(s.xdd, s.xdd, s.ydd * s.ydd);
+  const bool vz = !(v2 > 0.f), az = !(a2 > 0.f);
+  const float rv = vz ? 0.f : frsq(v2);
+  const float ra = az ? 0.f : frsq(a2);
+  const float vn = v2 * rv, an = a2 * ra;
+  // |sin(alpha_a - alpha_v)|: cross product of the unit vectors (atan2(0, 0)
+  // = 0 maps a zero vector to (1, 0))
+  const float ex = vz ? 1.f : s.xd, rv1 = vz ? 1.f : rv;
+  const float fx = az ? 1.f : s.xdd, ra1 = az ? 1.f : ra;
+  const float sig = fabsf(fmaf(s.ydd, ex, -fx * s.yd)) * (rv1 * ra1);
+  const float vlo = fmaxf(S.v_min, fsqrt(da_prev * sig * S.inv_kmax));
   float vhi = S.v_max;
   if (S.kappa_abs > 0.f) {
-    float den = S.kappa_abs * cv * cv;
+    const float cv = ex * rv1;
+    const float den = S.kappa_abs * cv * cv;
     if (den > 0.f) vhi = fminf(vhi, fsqrt(S.c_max * frcp(den)));
   }
-  float dv = fminf(fmaxf(vn, vlo), vhi);
-  float ahi = S.a_max;
-  if (sig > 0.f) ahi = fminf(ahi, dv * dv * S.kmax * frcp(sig));
-  float dan = fminf(fmaxf(an, 0.f), ahi);
-  float dvx, dvy, dax, day;
-  if (v2 > 0.f) {
-    float k = (dv - vn) * rv;
-    dvx = k * s.xd;
-    dvy = k * s.yd;
-  } else {
-    dvx = dv;
-    dvy = 0.f;
-  }
-  if (a2 > 0.f) {
-    float k = (dan - an) * ra;
-    dax = k * s.xdd;
-    day = k * s.ydd;
-  } else {
-    dax = dan;
-    day = 0.f;
-  }
+  const float dv = fminf(fmaxf(vn, vlo), vhi);
+  const float ahi = sig > 0.f ? fminf(S.a_max, dv * dv * S.kmax * frcp(sig)) : S.a_max;
+  const float dan = fminf(an, ahi);
+  const float kv = (dv - vn) * rv, ka = (dan - an) * ra;
+  float dvx = vz ? dv : kv * s.xd, dvy = kv * s.yd;
+  float dax = az ? dan : ka * s.xdd, day = ka * s.ydd;
   if (tv) da_prev = dan;
   // lane bounds: e - s - G xi = clip(y, y_lb, y_ub) - y
-  float dl = fminf(fmaxf(s.y, S.y_lb), S.y_ub) - s.y;
-  float wy = doy + dl;
-  if (!tv) {
-    dox = wy = dvx = dvy = dax = day = 0.f;
-  }
+  float wy = doy + (fminf(fmaxf(s.y, S.y_lb), S.y_ub) - s.y);
+  if (!tv) dox = wy = dvx = dvy = dax = day = 0.f;
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
-    g[c] = fmaf(L.bx[c], dox, fmaf(L.bdx[c], dvx, L.bddx[c] * dax));
+  for (int c = 0; c < 8; ++c) g[c] = fmaf(L.bx[c], dox, fmaf(L.bdx[c], dvx, L.bddx[c] * dax));
 #pragma unroll
-  for (int c = 0; c < 6; ++c)
-    g[8 + c] = fmaf(L.bx[c], wy, fmaf(L.bdx[c], dvy, L.bddx[c] * day));
+  for (int c = 0; c < 6; ++c) g[8 + c] = fmaf(L.bx[c], wy, fmaf(L.bdx[c], dvy, L.bddx[c] * day));
   g[14] = fmaf(L.by7, wy, fmaf(L.bdy7, dvy, L.bddy7 * day));
   g[15] = 0.f;
 }
@@ -211,36 +368,58 @@ __device__ __forceinline__ void target_pass(const Lane &L, const Scal &S, const 
 // Residual r (sum of max(0, g) over Table ineq_list) and upper cost c_u at
 // this lane's instant.
 __device__ __forceinline__ void residual_pass(const Lane &L, const Scal &S, const float (&zs)[15],
-                                              const float2 *__restrict__ obs, int M, int T, int t,
+                                              const float4 *__restrict__ obs, int npair, int T, int t,
                                               bool tv, float &res, float &cost) {
   State6 s = eval_traj(L, zs, S.vx0);
+  const float xs = s.x * S.ia, ys = s.y * S.ib;
   float r = 0.f;
-  for (int i = 0; i < M; ++i) {
-    float2 o = obs[i * T + t];
-    float dx = s.x - o.x, dy = s.y - o.y;
-    float q = fmaf(dx * dx, S.ia2, dy * dy * S.ib2);
-    r += fmaxf(0.f, 1.f - q);
+  for (int c = 0; c < npair; ++c) {
+    const float4 o = obs[c * T + t];
+    float dx = xs - o.x, dy = ys - o.y;
+    r += fmaxf(0.f, 1.f - fmaf(dx, dx, dy * dy));
+    dx = xs - o.z;
+    dy = ys - o.w;
+    r += fmaxf(0.f, 1.f - fmaf(dx, dx, dy * dy));
   }
-  float vn = fsqrt(fmaf(s.xd, s.xd, s.yd * s.yd));
-  float an = fsqrt(fmaf(s.xdd, s.xdd, s.ydd * s.ydd));
+  const float vn = fsqrt(fmaf(s.xd, s.xd, s.yd * s.yd));
+  const float an = fsqrt(fmaf(s.xdd, s.xdd, s.ydd * s.ydd));
   r += fmaxf(0.f, vn - S.v_max) + fmaxf(0.f, S.v_min - vn) + fmaxf(0.f, an - S.a_max);
-  float vd = fmaxf(vn, S.v_eps);
-  float curv = fabsf(s.ydd * s.xd - s.xdd * s.yd) * frcp(vd * vd * vd);
+  const float vd = fmaxf(vn, S.v_eps);
+  const float curv = fabsf(s.ydd * s.xd - s.xdd * s.yd) * frcp(vd * vd * vd);
   r += fmaxf(0.f, curv - S.kmax);
   r += fmaxf(0.f, fabsf(s.xd * s.xd * S.kappa_abs) - S.c_max);
   r += fmaxf(0.f, s.y - S.y_ub) + fmaxf(0.f, S.y_lb - s.y);
-  float e = vn - S.v_max;
+  const float e = vn - S.v_max;
   res = tv ? r : 0.f;
   cost = tv ? e * e : 0.f;
 }
 
-__global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
-  extern __shared__ float2 s_obs[];
-  __shared__ float s_red[2][4][16];
+// Workgroup -> (slot, first sample): binary search of the workgroup index in
+// the prefix counts of the launch's active slots (uniform scalar loads).
+__device__ __forceinline__ int2 block_slot(const LowerArgs &A) {
+  int lo = 0, hi = A.n_act - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.blk_prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int slot = A.act_slots[lo];
+  const int T = A.desc[slot].T;
+  const int spb = 4 / ((T + kWave - 1) / kWave);
+  return make_int2(slot, (b - A.blk_prefix[lo]) * spb);
+}
 
-  const int2 bi = A.blocks[blockIdx.x];
+__global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
+  extern __shared__ float4 s_obs[];
+  __shared__ float s_red[2][4][16];
+  __shared__ double s_mu[8], s_chol[64];
+
+  const int2 bi = block_slot(A);
   const ReqDesc &D = A.desc[bi.x];
+  const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
   const int T = D.T, M = D.M, N = D.N;
+  const int npair = (M + 1) >> 1;
   const int NW = (T + kWave - 1) / kWave;
   const int spb = 4 / NW;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -251,29 +430,60 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   const int t = wi * kWave + lane;
   const bool tv = active && t < T;
   const int tt = t < T ? t : T - 1;
-  const size_t slot_off = (size_t)bi.x * A.max_N;
+  const size_t slot_off = (size_t)D.row_off;
 
   const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
   const double ax0 = D.ego[4], ay0 = D.ego[5];
+  const double ia = 1.0 / P.ell_a, ib = 1.0 / P.ell_b;
 
-  const float *Bt = A.basis + A.basis_off[D.t_idx];
-  const int Tp = A.basis_tpad[D.t_idx];
-
-  // Neighbour positions relative to the reference line, per instant.
-  for (int idx = threadIdx.x; idx < M * T; idx += kBlock) {
-    int i = idx / T, k = idx - i * T;
-    double tk = (double)P.t_f * (double)k / (double)(T - 1);
-    double ox = (D.obs[i][0] - x0) + (D.obs[i][2] - vx0) * tk;
-    double oy = D.obs[i][1] + D.obs[i][3] * tk;
-    s_obs[idx] = make_float2((float)ox, (float)oy);
+  // Neighbour positions relative to the reference line, divided by the
+  // ellipse axes, two neighbours per entry (an odd last one is paired with a
+  // point far away).
+  for (int idx = threadIdx.x; idx < npair * T; idx += kBlock) {
+    const int c = idx / T, k = idx - c * T;
+    const double tk = P.t_f * (double)k / (double)(T - 1);
+    float v[4];
+    for (int h = 0; h < 2; ++h) {
+      const int i = 2 * c + h;
+      if (i < M) {
+        v[2 * h] = (float)(((D.obs[i][0] - x0) + (D.obs[i][2] - vx0) * tk) * ia);
+        v[2 * h + 1] = (float)((D.obs[i][1] + D.obs[i][3] * tk) * ib);
+      } else {
+        v[2 * h] = 1e18f;
+        v[2 * h + 1] = 1e18f;
+      }
+    }
+    s_obs[idx] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+  // Distribution of this iteration (Gaussian draws only).
+  const bool forced = D.init_mode == kInitForced;
+  const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
+  if (!forced && !structured) {
+    if (l == 0) {
+      if (threadIdx.x == 0) {
+        const double *m0 = D.mu0, *s0 = D.sigma0;
+        if (D.init_mode == kInitSession) {
+          m0 = A.sess + (size_t)D.session * 72;
+          s0 = m0 + 8;
+        }
+        for (int a = 0; a < 8; ++a) s_mu[a] = m0[a];
+        if (!chol8(s0, P.cov_jitter, s_chol))
+          for (int i = 0; i < 64; ++i) s_chol[i] = 0.0;  // reported by the update
+      }
+    } else if (threadIdx.x < 72) {
+      const DistState &Sd = A.dist[bi.x];
+      if (threadIdx.x < 8) s_mu[threadIdx.x] = Sd.mu[threadIdx.x];
+      else s_chol[threadIdx.x - 8] = Sd.chol[threadIdx.x - 8];
+    }
   }
 
   Scal S;
   S.vx0 = (float)vx0;
   S.rho = (float)P.rho;
-  S.ia2 = (float)(1.0 / (P.ell_a * P.ell_a));
-  S.ib2 = (float)(1.0 / (P.ell_b * P.ell_b));
+  S.ia = (float)ia;
+  S.ib = (float)ib;
   S.ell_a = (float)P.ell_a;
+  S.ell_b = (float)P.ell_b;
   S.v_min = (float)P.v_min;
   S.v_max = (float)P.v_max;
   S.a_max = (float)P.a_max;
@@ -286,6 +496,8 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   S.v_eps = (float)P.v_eps;
 
   // Basis rows of this lane's instant and the fixed part of the trajectory.
+  const float *Bt = A.basis + A.basis_off[D.t_idx];
+  const int Tp = A.basis_tpad[D.t_idx];
   Lane L;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -316,12 +528,33 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     L.ydf = fmaf(Wd0, fy0, fmaf(Wd1, fy1, Wd2 * fy2));
     L.yddf = fmaf(Wdd0, fy0, fmaf(Wdd1, fy1, Wdd2 * fy2));
   }
+  const int v = lane >> 2;
+  float arow[16];
+  float Dv;
+  {
+    const float *Pj = A.proj + (size_t)D.tm_idx * kProjFloats;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) arow[c] = Pj[v * 16 + c];
+    Dv = Pj[256 + v];
+  }
+  __syncthreads();  // neighbour table and distribution ready
+
+  // Sample p_j (Alg. 1: draw from N(mu, Sigma); iteration 0 may use the
+  // structured initial sampler), or the caller's samples.
+  float pin[8];
+  if (forced) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) pin[m] = active ? A.p[(slot_off + j) * 8 + m] : 0.f;
+  } else {
+    wave_draw(P, D.seed, j, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
+    if (active && wi == 0 && lane == 0) {
+      float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
+      dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
+      dst[1] = make_float4(pin[4], pin[5], pin[6], pin[7]);
+    }
+  }
 
   // Step 1 (eq. over_3 through its affine map): z_bar = S p' + R b'.
-  const int v = lane >> 2;
-  float pin[8];
-#pragma unroll
-  for (int m = 0; m < 8; ++m) pin[m] = active ? A.p[(slot_off + j) * 8 + m] : 0.f;
   float zb;
   {
     const float *S1 = A.step1 + (size_t)D.t_idx * kStep1Floats;
@@ -339,15 +572,6 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 #pragma unroll
     for (int m = 0; m < 4; ++m) zb = fmaf(R1[v * 4 + m], bb[m], zb);
   }
-  float arow[16];
-  float Dv;
-  {
-    const float *Pj = A.proj + (size_t)D.tm_idx * kProjFloats;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) arow[c] = Pj[v * 16 + c];
-    Dv = Pj[256 + v];
-  }
-  __syncthreads();  // obstacle table ready
 
   float z = zb, mu = 0.f;
   float zs[15];
@@ -361,7 +585,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     da_prev = fminf(fsqrt(fmaf(s.xdd, s.xdd, s.ydd * s.ydd)), S.a_max);
   }
 
-  const float2 *obs = s_obs;
+  const float4 *obs = s_obs;
   int buf = 0;
   auto reduce_sample = [&](const float (&g)[16]) -> float {
     float r = reduce16(g, lane);
@@ -377,13 +601,13 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   };
 
   float g[16];
-  target_pass(L, S, zs, obs, M, T, tt, tv, da_prev, g);
+  target_pass(L, S, zs, obs, npair, T, tt, tv, da_prev, g);
   float Gv = reduce_sample(g);
 
   const int K = P.K;
   for (int k = 1; k <= K; ++k) {
     // xi-update (eq. split_xy) in the free coordinates
-    float rhs = fmaf(Dv, zb - z, fmaf(S.rho, Gv, mu));
+    const float rhs = fmaf(Dv, zb - z, fmaf(S.rho, Gv, mu));
     float rs[15];
 #pragma unroll
     for (int c = 0; c < 15; ++c) rs[c] = bcast(rhs, 4 * c);
@@ -394,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 #pragma unroll
     for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
     if (k < K) {
-      target_pass(L, S, zs, obs, M, T, tt, tv, da_prev, g);
+      target_pass(L, S, zs, obs, npair, T, tt, tv, da_prev, g);
       Gv = reduce_sample(g);
       mu = fmaf(0.5f * S.rho, Gv, mu);  // eq. update_lagrange
     }
@@ -402,7 +626,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 
   // Residual and upper cost of xi* = xi^K.
   float rr, cc;
-  residual_pass(L, S, zs, obs, M, T, tt, tv, rr, cc);
+  residual_pass(L, S, zs, obs, npair, T, tt, tv, rr, cc);
   rr = wave_sum(rr);
   cc = wave_sum(cc);
   if (NW > 1) {
@@ -458,144 +682,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 }
 
 // ---------------------------------------------------------------------------
-// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the request
-// seed; counter (sample, iteration, block, 0). Box-Muller turns pairs of
-// uniforms in (0, 1] into normals.
-
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    uint32_t lo0 = 0xD2511F53u * c[0];
-    uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
-    uint32_t lo1 = 0xCD9E8D57u * c[2];
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
-    uint32_t n0 = hi1 ^ c[1] ^ k0;
-    uint32_t n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
-__device__ __forceinline__ void rng_block(uint64_t seed, int j, int l, int blk, uint32_t w[4]) {
-  w[0] = (uint32_t)j;
-  w[1] = (uint32_t)l;
-  w[2] = (uint32_t)blk;
-  w[3] = 0u;
-  philox4x32_10(w, (uint32_t)seed, (uint32_t)(seed >> 32));
-}
-
-__device__ __forceinline__ float u01(uint32_t x) {
-  return (float)((x >> 8) + 1u) * (1.0f / 16777216.0f);
-}
-
-__device__ __forceinline__ void normals2(uint32_t a, uint32_t b, float &n0, float &n1) {
-  float rad = sqrtf(-2.0f * logf(u01(a)));
-  float s, c;
-  sincospif(2.0f * u01(b), &s, &c);
-  n0 = rad * c;
-  n1 = rad * s;
-}
-
-// Draw sample j of upper iteration l into p (8 floats).
-__device__ void draw_sample(const MethodParams &P, const ReqDesc &D, const DistState &Sd, int j,
-                            int l, bool structured, float *p) {
-  uint32_t w[12];
-  rng_block(D.seed, j, l, 0, w);
-  rng_block(D.seed, j, l, 1, w + 4);
-  if (structured) {
-    rng_block(D.seed, j, l, 2, w + 8);
-    float n[4];
-    normals2(w[0], w[1], n[0], n[1]);
-    normals2(w[2], w[3], n[2], n[3]);
-    int lane = (int)(((uint64_t)w[8] * 3u) >> 32);
-    double lc = P.lane_c[lane];
-    for (int m = 0; m < 4; ++m) {
-      p[m] = (float)(lc + P.lane_sigma * (double)n[m]);
-      double u = (double)((w[4 + m] >> 8) + 1u) * (1.0 / 16777216.0);
-      p[4 + m] = (float)(P.vd_lo + (P.vd_hi - P.vd_lo) * u);
-    }
-  } else {
-    float zf[8];
-    for (int m = 0; m < 8; m += 2) normals2(w[m], w[m + 1], zf[m], zf[m + 1]);
-    for (int a = 0; a < 8; ++a) {
-      double s = Sd.mu[a];
-      for (int b = 0; b <= a; ++b) s += Sd.chol[a * 8 + b] * (double)zf[b];
-      p[a] = (float)s;
-    }
-  }
-}
-
-// Lower Cholesky factor of A + jitter I (8x8, FP64). Returns false if not
-// positive definite.
-__device__ bool chol8(const double *A, double jitter, double *Lo) {
-  for (int i = 0; i < 64; ++i) Lo[i] = 0.0;
-  for (int jc = 0; jc < 8; ++jc) {
-    double d = A[jc * 8 + jc] + jitter;
-    for (int k = 0; k < jc; ++k) d -= Lo[jc * 8 + k] * Lo[jc * 8 + k];
-    if (!(d > 0.0)) return false;
-    double l = sqrt(d);
-    Lo[jc * 8 + jc] = l;
-    for (int i = jc + 1; i < 8; ++i) {
-      double s = A[i * 8 + jc];
-      for (int k = 0; k < jc; ++k) s -= Lo[i * 8 + k] * Lo[jc * 8 + k];
-      Lo[i * 8 + jc] = s / l;
-    }
-  }
-  return true;
-}
-
-// Iteration-0 distribution and draw: one workgroup per request.
-__global__ void __launch_bounds__(kSelBlock) init_kernel(SelArgs A, MethodParams P) {
-  const int slot = A.slots[blockIdx.x];
-  ReqDesc &D = A.desc[slot];
-  DistState &Sd = A.dist[slot];
-  __shared__ int s_ok;
-  if (D.init_mode == kInitForced) return;
-  if (threadIdx.x == 0) {
-    double *mu = Sd.mu, *sg = Sd.sigma;
-    if (D.init_mode == kInitStructured) {
-      // exact moments of the structured sampler
-      double mc = (P.lane_c[0] + P.lane_c[1] + P.lane_c[2]) / 3.0;
-      double vc = 0.0;
-      for (int i = 0; i < 3; ++i) vc += (P.lane_c[i] - mc) * (P.lane_c[i] - mc);
-      vc /= 3.0;
-      double vm = 0.5 * (P.vd_lo + P.vd_hi);
-      double vv = (P.vd_hi - P.vd_lo) * (P.vd_hi - P.vd_lo) / 12.0;
-      for (int i = 0; i < 64; ++i) sg[i] = 0.0;
-      for (int a = 0; a < 4; ++a) {
-        mu[a] = mc;
-        mu[4 + a] = vm;
-        for (int b = 0; b < 4; ++b) sg[a * 8 + b] = vc + (a == b ? P.lane_sigma * P.lane_sigma : 0.0);
-        sg[(4 + a) * 8 + 4 + a] = vv;
-      }
-      s_ok = 1;
-    } else {
-      const double *m0 = D.mu0, *s0 = D.sigma0;
-      if (D.init_mode == kInitSession) {
-        m0 = A.sess + (size_t)D.session * 72;
-        s0 = m0 + 8;
-      }
-      for (int a = 0; a < 8; ++a) mu[a] = m0[a];
-      for (int i = 0; i < 64; ++i) sg[i] = s0[i];
-      s_ok = chol8(sg, P.cov_jitter, Sd.chol) ? 1 : 0;
-    }
-    ResultRec &R = A.result[slot];
-    R.status = s_ok ? 0 : PLAN_E_INVALID;
-    R.iterations = 0;
-  }
-  __syncthreads();
-  if (!s_ok) return;
-  const bool structured = D.init_mode == kInitStructured;
-  for (int j = threadIdx.x; j < D.N; j += kSelBlock)
-    draw_sample(P, D, Sd, j, D.first_iter, structured, A.p + ((size_t)slot * A.max_N + j) * 8);
-}
-
-// ---------------------------------------------------------------------------
-// Selection and update.
+// Selection and update: one 1024-thread workgroup per request.
 
 __device__ __forceinline__ uint32_t order_key(float f) {
   uint32_t b = __float_as_uint(f);
@@ -603,124 +690,224 @@ __device__ __forceinline__ uint32_t order_key(float f) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-__device__ void bitonic_sort(uint64_t *s, int n) {
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int i = threadIdx.x; i < n; i += kSelBlock) {
-        int ixj = i ^ jj;
-        if (ixj > i) {
-          uint64_t a = s[i], b = s[ixj];
-          bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            s[i] = b;
-            s[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
+// Exclusive prefix sum over the block of one value per thread; returns the
+// thread's offset and writes the total to *total. Uses s_tmp[16] and two
+// barriers.
+__device__ uint32_t block_exscan(uint32_t x, uint32_t *s_tmp, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
   }
+  if (lane == 63) s_tmp[wave] = incl;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (int w = 0; w < kSelBlock / 64; ++w) {
+    uint32_t t = s_tmp[w];
+    if (w < wave) base += t;
+    tot += t;
+  }
+  *total = tot;
+  __syncthreads();
+  return base + incl - x;
 }
 
-__device__ __forceinline__ int pow2ceil(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
+// Select the `want` smallest (key, position) pairs of s_key[0..cnt) (ties to
+// the lower position) and write their positions, in increasing order, to
+// s_out[0..want). Radix select on the 32-bit keys, 8 bits per pass, then one
+// scan ranks the members equal to the threshold by position. cnt <= 4096.
+__device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t *s_out,
+                             uint32_t *s_hist, uint32_t *s_tmp) {
+  const int tid = threadIdx.x;
+  uint32_t prefix = 0, mask = 0;
+  int remaining = want;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += kSelBlock) s_hist[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < cnt; i += kSelBlock) {
+      const uint32_t k = s_key[i];
+      if ((k & mask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      uint32_t h[4], sum = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        h[u] = s_hist[4 * tid + u];
+        sum += h[u];
+      }
+      uint32_t incl = sum;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(incl, d, 64);
+        if (tid >= d) incl += y;
+      }
+      uint32_t before = incl - sum;
+      for (int u = 0; u < 4; ++u) {
+        if (before < (uint32_t)remaining && (uint32_t)remaining <= before + h[u]) {
+          s_tmp[16] = 4 * tid + u;
+          s_tmp[17] = before;
+        }
+        before += h[u];
+      }
+    }
+    __syncthreads();
+    const uint32_t b = s_tmp[16];
+    remaining -= (int)s_tmp[17];
+    prefix |= b << shift;
+    mask |= 0xFFu << shift;
+    __syncthreads();
+  }
+  // Positions are split into contiguous chunks, one per thread, so both scans
+  // run in position order.
+  const int chunk = (cnt + kSelBlock - 1) / kSelBlock;
+  const int p0 = tid * chunk, p1 = min(cnt, p0 + chunk);
+  uint32_t eq = 0;
+  for (int i = p0; i < p1; ++i) eq += s_key[i] == prefix;
+  uint32_t tot;
+  uint32_t eq_before = block_exscan(eq, s_tmp, &tot);
+  uint32_t sel = 0;
+  for (int i = p0; i < p1; ++i) {
+    const uint32_t k = s_key[i];
+    if (k < prefix) ++sel;
+    else if (k == prefix) sel += (eq_before++ < (uint32_t)remaining);
+  }
+  eq_before -= eq;
+  uint32_t pos = block_exscan(sel, s_tmp, &tot);
+  for (int i = p0; i < p1; ++i) {
+    const uint32_t k = s_key[i];
+    bool take = k < prefix;
+    if (k == prefix) take = eq_before++ < (uint32_t)remaining;
+    if (take) s_out[pos++] = (uint32_t)i;
+  }
+  __syncthreads();
 }
 
-__global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, MethodParams P, int l) {
-  __shared__ uint64_t s_key[PLAN_MAX_N];
-  __shared__ double s_w[kMaxCes];
-  __shared__ double s_mu[8];
+__global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, MethodParams P) {
+  __shared__ uint32_t s_key[PLAN_MAX_N];
+  __shared__ uint32_t s_ces[kMaxCes];
+  __shared__ uint32_t s_key2[kMaxCes];
+  __shared__ uint32_t s_es[kMaxCes];
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_tmp[32];
+  __shared__ double s_w[kMaxEs];
+  __shared__ double s_p[kMaxEs][8];
+  __shared__ double s_mu[8], s_mun[8], s_sig[64];
   __shared__ double s_sum;
+  __shared__ unsigned long long s_best;
+
   const int slot = A.slots[blockIdx.x];
-  const ReqDesc &D = A.desc[slot];
+  ReqDesc &D = A.desc[slot];
   DistState &Sd = A.dist[slot];
   ResultRec &R = A.result[slot];
-  if (R.status != 0) return;
+  const int tid = threadIdx.x;
+  const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
   const int N = D.N, n = D.n_ces, q = D.n_es;
-  const size_t base = (size_t)slot * A.max_N;
+  const size_t base = (size_t)D.row_off;
   const float *r = A.resid + base, *cu = A.cost + base;
   const float *p = A.p + base * 8;
   const bool last = (l == P.L - 1);
 
-  // ConstraintEliteSet: the n smallest (r_j, j).
-  const int P1 = pow2ceil(N);
-  for (int i = threadIdx.x; i < P1; i += kSelBlock)
-    s_key[i] = i < N ? ((uint64_t)order_key(r[i]) << 32) | (uint32_t)i : ~0ull;
-  __syncthreads();
-  bitonic_sort(s_key, P1);
-  // EliteSet: the q smallest (c_u + r, j) over the ConstraintEliteSet.
-  const int P2 = pow2ceil(n);
-  uint64_t k2[4];
-  int cnt = 0;
-  for (int i = threadIdx.x; i < P2; i += kSelBlock, ++cnt) {
-    if (i < n) {
-      uint32_t idx = (uint32_t)(s_key[i] & 0xFFFFFFFFu);
-      if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)idx;
-      float c = cu[idx] + r[idx];
-      k2[cnt] = ((uint64_t)order_key(c) << 32) | idx;
-    } else {
-      k2[cnt] = ~0ull;
+  // Distribution before this update: the prior at iteration 0.
+  if (l == 0) {
+    if (tid == 0) {
+      int ok = 1;
+      if (D.init_mode == kInitStructured) {
+        structured_moments(P, s_mu, s_sig);
+      } else {
+        const double *m0 = D.mu0, *s0 = D.sigma0;
+        if (D.init_mode == kInitSession) {
+          m0 = A.sess + (size_t)D.session * 72;
+          s0 = m0 + 8;
+        }
+        for (int a = 0; a < 8; ++a) s_mu[a] = m0[a];
+        for (int i = 0; i < 64; ++i) s_sig[i] = s0[i];
+        double Lt[64];
+        ok = chol8(s_sig, P.cov_jitter, Lt) ? 1 : 0;
+      }
+      R.status = ok ? 0 : PLAN_E_INVALID;
+      R.iterations = 0;
     }
+  } else if (tid < 72) {
+    if (tid < 8) s_mu[tid] = Sd.mu[tid];
+    else s_sig[tid - 8] = Sd.sigma[tid - 8];
   }
+  if (tid == 0) s_best = ~0ull;
   __syncthreads();
-  cnt = 0;
-  for (int i = threadIdx.x; i < P2; i += kSelBlock, ++cnt) s_key[i] = k2[cnt];
-  __syncthreads();
-  bitonic_sort(s_key, P2);
+  if (R.status != 0) return;
 
-  // Weights s_j = exp(-(c_j - c_min) / gamma) over the EliteSet (FP64).
-  const uint32_t i0 = (uint32_t)(s_key[0] & 0xFFFFFFFFu);
-  const double cmin = (double)(cu[i0] + r[i0]);
-  for (int i = threadIdx.x; i < q; i += kSelBlock) {
-    uint32_t idx = (uint32_t)(s_key[i] & 0xFFFFFFFFu);
-    double c = (double)(cu[idx] + r[idx]);
-    s_w[i] = exp(-(c - cmin) / P.gamma);
-    if (A.tr_es) A.tr_es[((size_t)slot * P.L + l) * A.max_es + i] = (int32_t)idx;
+  // ConstraintEliteSet: the n smallest (r_j, j).
+  for (int i = tid; i < N; i += kSelBlock) s_key[i] = order_key(r[i]);
+  __syncthreads();
+  block_select(s_key, N, n, s_ces, s_hist, s_tmp);
+  // EliteSet: the q smallest (c_u + r, j) over the ConstraintEliteSet, whose
+  // members are listed in increasing sample index.
+  for (int i = tid; i < n; i += kSelBlock) {
+    const uint32_t j = s_ces[i];
+    s_key2[i] = order_key(cu[j] + r[j]);
+    if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)j;
   }
   __syncthreads();
-  if (threadIdx.x < 8) {
-    const int a = threadIdx.x;
+  block_select(s_key2, n, q, s_es, s_hist, s_tmp);
+  for (int i = tid; i < q; i += kSelBlock) {
+    const uint32_t pos = s_es[i];
+    atomicMin(&s_best, ((unsigned long long)s_key2[pos] << 32) | s_ces[pos]);
+  }
+  __syncthreads();
+  const uint32_t jbest = (uint32_t)(s_best & 0xFFFFFFFFull);
+
+  // Weights s_j = exp(-(c_j - c_min) / gamma) and the elite rows, in FP64.
+  const double cmin = (double)(cu[jbest] + r[jbest]);
+  for (int i = tid; i < q; i += kSelBlock) {
+    const uint32_t j = s_ces[s_es[i]];
+    s_w[i] = exp(-((double)(cu[j] + r[j]) - cmin) / P.gamma);
+    if (A.tr_es) A.tr_es[((size_t)slot * P.L + l) * A.max_es + i] = (int32_t)j;
+  }
+  for (int e = tid; e < q * 8; e += kSelBlock) {
+    const int i = e >> 3, a = e & 7;
+    s_p[i][a] = (double)p[(size_t)s_ces[s_es[i]] * 8 + a];
+  }
+  __syncthreads();
+  // eq. mean_update (8 threads) with the weight total
+  if (tid < 8) {
     double m = 0.0, ssum = 0.0;
     for (int i = 0; i < q; ++i) {
-      uint32_t idx = (uint32_t)(s_key[i] & 0xFFFFFFFFu);
-      m += s_w[i] * (double)p[(size_t)idx * 8 + a];
+      m += s_w[i] * s_p[i][tid];
       ssum += s_w[i];
     }
-    s_mu[a] = (1.0 - P.eta) * Sd.mu[a] + P.eta * m / ssum;
-    if (a == 0) s_sum = ssum;
+    s_mun[tid] = (1.0 - P.eta) * s_mu[tid] + P.eta * m / ssum;
+    if (tid == 0) s_sum = ssum;
   }
   __syncthreads();
+  // eq. cov_update around the new mean (64 threads), then symmetrise.
   double snew = 0.0;
-  if (threadIdx.x < 64) {
-    const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
+  if (tid < 64) {
+    const int a = tid >> 3, b = tid & 7;
+    const double ma = s_mun[a], mb = s_mun[b];
     double c = 0.0;
-    for (int i = 0; i < q; ++i) {
-      uint32_t idx = (uint32_t)(s_key[i] & 0xFFFFFFFFu);
-      c += s_w[i] * ((double)p[(size_t)idx * 8 + a] - s_mu[a]) * ((double)p[(size_t)idx * 8 + b] - s_mu[b]);
-    }
-    snew = (1.0 - P.eta) * Sd.sigma[a * 8 + b] + P.eta * c / s_sum;
+    for (int i = 0; i < q; ++i) c += s_w[i] * (s_p[i][a] - ma) * (s_p[i][b] - mb);
+    snew = (1.0 - P.eta) * s_sig[a * 8 + b] + P.eta * c / s_sum;
   }
   __syncthreads();
-  if (threadIdx.x < 64) Sd.sigma[threadIdx.x] = snew;
-  if (threadIdx.x < 8) Sd.mu[threadIdx.x] = s_mu[threadIdx.x];
+  if (tid < 64) s_sig[tid] = snew;
+  if (tid < 8) Sd.mu[tid] = s_mun[tid];
   __syncthreads();
-  __shared__ int s_ok;
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double sym[64];
     for (int a = 0; a < 8; ++a)
-      for (int b = 0; b < 8; ++b) sym[a * 8 + b] = 0.5 * (Sd.sigma[a * 8 + b] + Sd.sigma[b * 8 + a]);
+      for (int b = 0; b < 8; ++b) sym[a * 8 + b] = 0.5 * (s_sig[a * 8 + b] + s_sig[b * 8 + a]);
     for (int i = 0; i < 64; ++i) Sd.sigma[i] = sym[i];
-    s_ok = chol8(sym, P.cov_jitter, Sd.chol) ? 1 : 0;
+    const bool ok = chol8(sym, P.cov_jitter, Sd.chol);
     if (A.tr_mu) {
-      for (int a = 0; a < 8; ++a) A.tr_mu[((size_t)slot * P.L + l) * 8 + a] = Sd.mu[a];
+      for (int a = 0; a < 8; ++a) A.tr_mu[((size_t)slot * P.L + l) * 8 + a] = s_mun[a];
       for (int i = 0; i < 64; ++i) A.tr_sigma[((size_t)slot * P.L + l) * 64 + i] = sym[i];
     }
     R.iterations = l + 1;
     if (last) {
-      // Return: lowest c_u + r in the final EliteSet.
-      const uint32_t b = i0;
+      // Return: lowest c_u + r in the final EliteSet (ties: lower index).
+      const uint32_t b = jbest;
       R.best = (int32_t)b;
       for (int a = 0; a < 8; ++a) R.p[a] = (double)p[(size_t)b * 8 + a];
       const float *zb = A.zs + (base + b) * kZ;
@@ -742,44 +929,34 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       if (D.init_mode == kInitSession || D.init_mode == kInitGiven) R.flags |= PLAN_F_WARM;
       if (D.session_wb >= 0) {
         double *st = A.sess + (size_t)D.session_wb * 72;
-        for (int a = 0; a < 8; ++a) st[a] = Sd.mu[a];
+        for (int a = 0; a < 8; ++a) st[a] = s_mun[a];
         for (int i = 0; i < 64; ++i) st[8 + i] = sym[i];
       }
     }
-    if (!s_ok) R.status = PLAN_E_INVALID;
+    if (!ok) R.status = PLAN_E_INVALID;
+    if (A.l_uniform < 0) D.cur_iter = l + 1;
   }
   // Trace of this iteration's samples, residuals and costs.
   if (A.tr_p) {
     const size_t tb = ((size_t)slot * P.L + l) * A.max_N;
-    for (int i = threadIdx.x; i < N; i += kSelBlock) {
+    for (int i = tid; i < N; i += kSelBlock) {
       for (int a = 0; a < 8; ++a) A.tr_p[(tb + i) * 8 + a] = p[(size_t)i * 8 + a];
       A.tr_r[tb + i] = r[i];
       A.tr_c[tb + i] = cu[i];
     }
   }
-  __syncthreads();
-  if (last || !s_ok) return;
-  // Draw the samples of iteration l + 1 from N(mu, Sigma).
-  float *pw = A.p + base * 8;
-  for (int j = threadIdx.x; j < N; j += kSelBlock)
-    draw_sample(P, D, Sd, j, D.first_iter + l + 1, false, pw + (size_t)j * 8);
 }
 
 }  // namespace plan
 
 // Launch wrappers (C++ linkage, used by the engine).
 namespace plan {
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds,
-                        hipStream_t st) {
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), lds, st, a, p);
   return hipGetLastError();
 }
-hipError_t launch_init(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st) {
-  hipLaunchKernelGGL(init_kernel, dim3(nreq), dim3(kSelBlock), 0, st, a, p);
-  return hipGetLastError();
-}
-hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, int l, hipStream_t st) {
-  hipLaunchKernelGGL(select_update_kernel, dim3(nreq), dim3(kSelBlock), 0, st, a, p, l);
+hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st) {
+  hipLaunchKernelGGL(select_update_kernel, dim3(nreq), dim3(kSelBlock), 0, st, a, p);
   return hipGetLastError();
 }
 }  // namespace plan

@@ -16,7 +16,9 @@ constexpr int kZ = 16;               // free coefficients (8 x + 7 y) padded
 constexpr int kBasisCols = 37;       // columns of the per-T basis table
 constexpr int kStep1Floats = 16 * 8 + 16 * 4;
 constexpr int kProjFloats = 16 * 16 + 16;
-constexpr int kMaxCes = 1024;        // LDS bound of the second sort
+constexpr int kMaxCes = 1024;        // LDS bound of the ConstraintEliteSet
+constexpr int kMaxEs = 256;          // LDS bound of the EliteSet
+constexpr int kBaCols = 45;          // columns of the per-(T, M) B A^-1 table
 
 // Columns of the per-T basis table (each column holds Tpad floats):
 //   0..7   W[:, 3..10]     8..15 Wd[:, 3..10]     16..23 Wdd[:, 3..10]
@@ -26,6 +28,13 @@ constexpr int kMaxCes = 1024;        // LDS bound of the second sort
 enum BasisCol {
   kColW = 0, kColWd = 8, kColWdd = 16, kColY7 = 24, kColFix = 27, kColT = 36
 };
+
+// Columns of the per-(T, M) table BA = B A^-1 (each Tpad floats): for the
+// x axis 8 columns per derivative order (W, Wd, Wdd), then for the y axis 7
+// per order: 0..7 W_x, 8..15 Wd_x, 16..23 Wdd_x, 24..30 W_y, 31..37 Wd_y,
+// 38..44 Wdd_y. Row t maps a right-hand side of the xi-update to the change
+// of the trajectory at t.
+enum BaCol { kBaWx = 0, kBaWdx = 8, kBaWddx = 16, kBaWy = 24, kBaWdy = 31, kBaWddy = 38 };
 
 // How iteration 0 draws its samples.
 enum InitMode : int32_t {
@@ -44,7 +53,8 @@ struct ReqDesc {
   int32_t session;    // session store index read at iteration 0, or -1
   int32_t session_wb; // session store index written after the last update, or -1
   int32_t first_iter; // upper-iteration index of the first iteration (sample stream)
-  int32_t pad0;
+  int32_t cur_iter;   // next upper iteration of this request (served mode)
+  int64_t row_off;    // first row of this request in the sample-row pool
   uint64_t seed;
   double ego[6];     // x0, y0, vx0, vy0, ax0, ay0
   double kappa;
@@ -85,26 +95,30 @@ struct MethodParams {
 // Arguments of the lower-level kernel.
 struct LowerArgs {
   const ReqDesc *desc;
-  const int2 *blocks;        // (slot, first sample) per workgroup
+  const int32_t *act_slots;  // slots of this launch
+  const int32_t *blk_prefix; // workgroups before each active slot (n_act + 1)
+  int32_t n_act;
+  int32_t l_uniform;         // upper iteration of every slot, or -1: desc.cur_iter
   const float *basis;        // concatenated per-T tables
   const int32_t *basis_off;  // float offset of table t_idx
   const int32_t *basis_tpad; // column stride of table t_idx
   const float *step1;        // per-T: S (16x8) then R (16x4)
   const float *proj;         // per-(T,M): A^-1 (16x16) then D (16)
-  const float *p;            // slot-strided [max_N][8]
-  float *zs;                 // slot-strided [max_N][16] free coefficients
-  float *resid;              // slot-strided [max_N]
-  float *cost;               // slot-strided [max_N]
-  double *xi_bar_out;        // optional [N][22] (slot 0 only)
-  double *xi_star_out;       // optional [N][22] (slot 0 only)
-  int32_t max_N;
-  int32_t obs_stride;        // floats of the LDS obstacle table (max M*T)
+  float *p;                  // row pool [rows][8] (written unless forced)
+  const DistState *dist;     // slot distribution (iterations >= 1)
+  const double *sess;        // session store (iteration 0 of a warm start)
+  float *zs;                 // row pool [rows][16] free coefficients
+  float *resid;              // row pool [rows]
+  float *cost;               // row pool [rows]
+  double *xi_bar_out;        // optional [N][22] (single request only)
+  double *xi_star_out;       // optional [N][22] (single request only)
 };
 
 // Arguments of the selection / update kernel and the init kernel.
 struct SelArgs {
   ReqDesc *desc;
   const int32_t *slots;      // slot of each workgroup
+  int32_t l_uniform;         // upper iteration of every slot, or -1: desc.cur_iter
   float *p;
   const float *zs;
   const float *resid;
@@ -112,7 +126,7 @@ struct SelArgs {
   DistState *dist;
   ResultRec *result;
   double *sess;              // session store [n_sess][72]: mu then Sigma
-  // optional trace (slot-strided by trace_stride_* per iteration)
+  // optional trace (per slot and iteration; max_N rows per slot)
   float *tr_p;               // [slot][L][max_N][8]
   float *tr_r;               // [slot][L][max_N]
   float *tr_c;               // [slot][L][max_N]

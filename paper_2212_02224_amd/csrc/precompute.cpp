@@ -285,6 +285,29 @@ void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt) {
   pt.table.resize(kProjFloats);
   for (int i = 0; i < 256; ++i) pt.table[i] = (float)pt.Ainv[i];
   for (int i = 0; i < 16; ++i) pt.table[256 + i] = (float)pt.D[i];
+  // BA = (basis rows of the free coefficients) x A^-1, per derivative order.
+  // x(t) changes by sum_d BA_x[t][d] rhs_d when z changes by A^-1 rhs.
+  pt.ba.assign((size_t)kBaCols * bt.Tpad, 0.f);
+  const std::vector<double> *rows[3] = {&bt.W, &bt.Wd, &bt.Wdd};
+  for (int k = 0; k < T; ++k) {
+    for (int o = 0; o < 3; ++o) {
+      const double *B = &(*rows[o])[k * kNC];
+      double bx[8], by[7];
+      for (int c = 0; c < 8; ++c) bx[c] = B[3 + c];
+      for (int c = 0; c < 6; ++c) by[c] = B[3 + c];
+      by[6] = B[9] + B[10];
+      for (int d = 0; d < 8; ++d) {
+        double s = 0.0;
+        for (int c = 0; c < 8; ++c) s += bx[c] * Ax[c * 8 + d];
+        pt.ba[(size_t)(kBaWx + 8 * o + d) * bt.Tpad + k] = (float)s;
+      }
+      for (int d = 0; d < 7; ++d) {
+        double s = 0.0;
+        for (int c = 0; c < 7; ++c) s += by[c] * Ay[c * 7 + d];
+        pt.ba[(size_t)(kBaWy + 7 * o + d) * bt.Tpad + k] = (float)s;
+      }
+    }
+  }
 }
 
 }  // namespace plan

@@ -25,6 +25,7 @@ struct Step1Table {
 struct ProjTable {
   std::vector<double> Ainv, D;     // 16 x 16 block diagonal, 16
   std::vector<float> table;        // kProjFloats
+  std::vector<float> ba;           // kBaCols x Tpad: basis rows times A^-1 (device layout)
 };
 
 void build_basis(int T, double t_f, BasisTable &bt);

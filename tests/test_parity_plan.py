@@ -147,7 +147,9 @@ def test_full_plan_consistency_and_determinism(orc, pl):
         # ConstraintEliteSet holds the n lowest residuals of the GPU's own r
         kth = np.sort(ga["r"][l])[n - 1]
         assert np.all(ga["r"][l][ga["ces"][l]] <= kth)
-    assert a.best_index == ga["es"][L - 1][0]
+    es = ga["es"][L - 1]
+    c_es = (ga["cu"][L - 1][es] + ga["r"][L - 1][es]).astype(np.float32)
+    assert a.best_index == es[np.lexsort((es, c_es))[0]]
     assert np.isclose(a.cost_upper, ga["cu"][L - 1][a.best_index])
     cfg1 = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=1, max_N=N,
                                max_requests=1, trace=1)

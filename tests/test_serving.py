@@ -1,0 +1,128 @@
+"""GPU tests of the served mode (continuous batching, include/plan.h):
+requests submitted at different times join the resident set at the next
+upper iteration, share the kernel launches with whatever is resident, are
+admitted by slot and sample-row budget, and return exactly the result they
+have when solved alone."""
+import numpy as np
+import pytest
+
+from paper_2212_02224_amd import workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pl():
+    import paper_2212_02224_amd as pl
+    pl.load()
+    return pl
+
+
+MIX = [(64, 50, 4), (300, 100, 10), (17, 100, 20), (512, 50, 10), (1, 100, 4), (250, 100, 20),
+       (128, 50, 20), (700, 100, 4)]
+
+
+def reqs_of(pl, cfgid=4):
+    out = []
+    for i, (N, T, M) in enumerate(MIX):
+        s = workload.scene(cfgid, 100 + i, M)
+        out.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
+    return out
+
+
+def cfg_of(pl, **over):
+    kw = dict(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=8, upper_iters=3, max_N=1024, max_requests=8)
+    kw.update(over)
+    return pl.plan_config_init(**kw)
+
+
+def alone_results(pl, reqs):
+    h = pl.plan_create(cfg_of(pl))
+    return [pl.plan_solve_batch(h, [r])[0] for r in reqs]
+
+
+def drain(pl, h, tickets, max_ticks=200):
+    got = {}
+    for _ in range(max_ticks):
+        act, q = pl.plan_progress(h)
+        for t in tickets:
+            if t not in got:
+                r = pl.plan_poll(h, t)
+                if r is not None:
+                    got[t] = r
+        if len(got) == len(tickets):
+            return got, act, q
+    raise AssertionError("requests did not finish")
+
+
+def same(a, b):
+    return (a.status == b.status == 0 and a.best_index == b.best_index and np.array_equal(a.xi_best, b.xi_best)
+            and np.array_equal(a.mu, b.mu) and np.array_equal(a.sigma, b.sigma))
+
+
+def test_served_all_at_once_equals_alone(pl):
+    reqs = reqs_of(pl)
+    ref = alone_results(pl, reqs)
+    h = pl.plan_create(cfg_of(pl))
+    tickets = [pl.plan_submit(h, r) for r in reqs]
+    got, _, _ = drain(pl, h, tickets)
+    for i, t in enumerate(tickets):
+        assert same(got[t], ref[i]), i
+        assert got[t].latency_s > 0
+
+
+def test_served_staggered_arrivals_equal_alone(pl):
+    reqs = reqs_of(pl)
+    ref = alone_results(pl, reqs)
+    h = pl.plan_create(cfg_of(pl))
+    tickets = []
+    for i, r in enumerate(reqs):
+        tickets.append(pl.plan_submit(h, r))
+        if i % 3 == 2:
+            pl.plan_progress(h)  # earlier requests are mid-flight when the next ones arrive
+    got, act, q = drain(pl, h, tickets)
+    assert act == 0 and q == 0
+    for i, t in enumerate(tickets):
+        assert same(got[t], ref[i]), i
+
+
+def test_served_admission_respects_sample_budget(pl):
+    reqs = reqs_of(pl)
+    ref = alone_results(pl, reqs)
+    budget = 800
+    h = pl.plan_create(cfg_of(pl, sample_budget=budget, max_requests=3))
+    tickets = [pl.plan_submit(h, r) for r in reqs]
+    done, ticks = {}, 0
+    while len(done) < len(tickets):
+        act, q = pl.plan_progress(h)
+        ticks += 1
+        assert act <= 3
+        for t in tickets:
+            if t not in done:
+                r = pl.plan_poll(h, t)
+                if r is not None:
+                    done[t] = r
+        assert ticks < 400
+    for i, t in enumerate(tickets):
+        assert same(done[t], ref[i]), i
+    # a request larger than the budget is refused at submit
+    big = pl.Request(N=1000, T=50, ego=reqs[0].ego, obstacles=reqs[0].obstacles, seed=1)
+    with pytest.raises(pl.PlanError) as e:
+        pl.plan_submit(h, big)
+    assert e.value.status == pl.PLAN_E_NOMEM
+
+
+def test_served_rejects_bad_requests_and_mixing(pl):
+    reqs = reqs_of(pl)
+    h = pl.plan_create(cfg_of(pl))
+    bad = pl.Request(N=10, T=70, ego=reqs[0].ego, obstacles=reqs[0].obstacles, seed=1)
+    with pytest.raises(pl.PlanError) as e:
+        pl.plan_submit(h, bad)
+    assert e.value.status == pl.PLAN_E_INVALID
+    t = pl.plan_submit(h, reqs[0])
+    assert pl.plan_poll(h, t) is None
+    with pytest.raises(pl.PlanError) as e:
+        pl.plan_solve_batch(h, [reqs[1]])
+    assert e.value.status == pl.PLAN_E_BUSY
+    drain(pl, h, [t])
+    assert pl.plan_solve_batch(h, [reqs[1]])[0].status == 0
