@@ -27,8 +27,10 @@
 #include "precompute.h"
 
 namespace plan {
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st);
-hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st);
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st,
+                        hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1);
 }  // namespace plan
 
 using namespace plan;
@@ -130,8 +132,7 @@ const char *validate_config(const plan_config &c) {
     if (c.M_set[i] < 0 || c.M_set[i] > PLAN_MAX_M) return "M must be in [0, PLAN_MAX_M]";
   if (c.max_N < 1 || c.max_N > PLAN_MAX_N) return "max_N must be in [1, PLAN_MAX_N]";
   if (c.max_requests < 1 || c.max_requests > 65536) return "max_requests must be in [1, 65536]";
-  if (c.sample_budget < 0 || (c.sample_budget > 0 && c.sample_budget < c.max_N))
-    return "sample_budget must be 0 or at least max_N";
+  if (c.sample_budget < 0) return "sample_budget must be >= 0";
   if (c.proj_iters < 1 || c.proj_iters > 10000) return "proj_iters must be >= 1";
   if (c.upper_iters < 1 || c.upper_iters > PLAN_MAX_L) return "upper_iters must be in [1, PLAN_MAX_L]";
   if (!(c.t_f > 0) || !(c.rho > 0) || !(c.gamma > 0) || !(c.eta >= 0 && c.eta <= 1))
@@ -401,8 +402,9 @@ LowerArgs lower_args(plan_handle *h, int n_act, int l_uniform) {
   return a;
 }
 
-// Event pair around one launch when profiling (kind: 0 lower, 1 select).
-hipError_t prof_begin(plan_handle *h, std::pair<hipEvent_t, hipEvent_t> &ev) {
+// Event pair for one launch when profiling (kind: 0 lower, 1 select); the
+// dispatch records both events.
+hipError_t prof_pair(plan_handle *h, int kind, std::pair<hipEvent_t, hipEvent_t> &ev) {
   if (h->ev_free.empty()) {
     hipEvent_t a, b;
     hipError_t e = hipEventCreate(&a);
@@ -412,21 +414,16 @@ hipError_t prof_begin(plan_handle *h, std::pair<hipEvent_t, hipEvent_t> &ev) {
   }
   ev = h->ev_free.back();
   h->ev_free.pop_back();
-  return hipEventRecord(ev.first, h->stream);
-}
-
-hipError_t prof_end(plan_handle *h, int kind, std::pair<hipEvent_t, hipEvent_t> ev) {
   h->ev_pending.push_back({kind, ev});
-  return hipEventRecord(ev.second, h->stream);
+  return hipSuccess;
 }
 
 template <class F>
 plan_status timed(plan_handle *h, int kind, F &&launch, const char *what) {
-  std::pair<hipEvent_t, hipEvent_t> ev;
-  if (h->profiling) HIP_TRY(h, prof_begin(h, ev));
-  hipError_t e = launch();
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (h->profiling) HIP_TRY(h, prof_pair(h, kind, ev));
+  hipError_t e = launch(ev.first, ev.second);
   if (e != hipSuccess) return hip_fail(h, e, what);
-  if (h->profiling) HIP_TRY(h, prof_end(h, kind, ev));
   return PLAN_OK;
 }
 
@@ -435,9 +432,13 @@ plan_status timed(plan_handle *h, int kind, F &&launch, const char *what) {
 plan_status launch_iteration(plan_handle *h, int n_act, int nblocks, size_t lds, int l_uniform) {
   const LowerArgs la = lower_args(h, n_act, l_uniform);
   const SelArgs sa = sel_args(h, l_uniform);
-  plan_status st = timed(h, 0, [&] { return launch_lower(la, h->mp, nblocks, lds, h->stream); }, "lower_kernel");
+  plan_status st = timed(
+      h, 0, [&](hipEvent_t a, hipEvent_t b) { return launch_lower(la, h->mp, nblocks, lds, h->stream, a, b); },
+      "lower_kernel");
   if (st == PLAN_OK)
-    st = timed(h, 1, [&] { return launch_select(sa, h->mp, n_act, h->stream); }, "select_update_kernel");
+    st = timed(
+        h, 1, [&](hipEvent_t a, hipEvent_t b) { return launch_select(sa, h->mp, n_act, h->stream, a, b); },
+        "select_update_kernel");
   return st;
 }
 
@@ -852,7 +853,7 @@ plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const doub
   LowerArgs la = lower_args(h, 1, 0);
   la.xi_bar_out = h->xi_out;
   la.xi_star_out = h->xi_out + (size_t)h->cfg.max_N * 22;
-  HIP_TRY(h, launch_lower(la, h->mp, nb, lds_bytes(d.M, d.T), h->stream));
+  HIP_TRY(h, launch_lower(la, h->mp, nb, lds_bytes(d.M, d.T), h->stream, nullptr, nullptr));
   std::vector<double> xo((size_t)N * 22 * 2);
   std::vector<float> rc((size_t)N * 2);
   HIP_TRY(h, hipMemcpyAsync(xo.data(), la.xi_bar_out, (size_t)N * 22 * 8, hipMemcpyDeviceToHost, h->stream));

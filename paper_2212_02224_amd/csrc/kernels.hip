@@ -33,6 +33,7 @@
 // time of N^T g are formed by a transpose-reduction across the wave (17
 // shuffles), the small A^-1 product by broadcasting through scalar
 // registers.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -175,12 +176,12 @@ __device__ bool chol8(const double *A, double jitter, double *Lo) {
     double d = A[jc * 8 + jc] + jitter;
     for (int k = 0; k < jc; ++k) d -= Lo[jc * 8 + k] * Lo[jc * 8 + k];
     if (!(d > 0.0)) return false;
-    double l = sqrt(d);
+    const double l = sqrt(d), il = 1.0 / l;
     Lo[jc * 8 + jc] = l;
     for (int i = jc + 1; i < 8; ++i) {
       double s = A[i * 8 + jc];
       for (int k = 0; k < jc; ++k) s -= Lo[i * 8 + k] * Lo[jc * 8 + k];
-      Lo[i * 8 + jc] = s / l;
+      Lo[i * 8 + jc] = s * il;
     }
   }
   return true;
@@ -870,71 +871,99 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
     s_p[i][a] = (double)p[(size_t)s_ces[s_es[i]] * 8 + a];
   }
   __syncthreads();
-  // eq. mean_update (8 threads) with the weight total
+  // eq. mean_update: 64 threads, 8 partial sums per component in a fixed
+  // order, then combined.
+  __shared__ double s_part[8][64 + 8];
+  if (tid < 64) {
+    const int a = tid & 7, part = tid >> 3;
+    double m = 0.0, ssum = 0.0;
+    for (int i = part; i < q; i += 8) {
+      m += s_w[i] * s_p[i][a];
+      ssum += s_w[i];
+    }
+    s_part[part][a] = m;
+    s_part[part][64 + a] = ssum;
+  }
+  __syncthreads();
   if (tid < 8) {
     double m = 0.0, ssum = 0.0;
-    for (int i = 0; i < q; ++i) {
-      m += s_w[i] * s_p[i][tid];
-      ssum += s_w[i];
+    for (int part = 0; part < 8; ++part) {
+      m += s_part[part][tid];
+      ssum += s_part[part][64 + tid];
     }
     s_mun[tid] = (1.0 - P.eta) * s_mu[tid] + P.eta * m / ssum;
     if (tid == 0) s_sum = ssum;
   }
   __syncthreads();
-  // eq. cov_update around the new mean (64 threads), then symmetrise.
-  double snew = 0.0;
-  if (tid < 64) {
-    const int a = tid >> 3, b = tid & 7;
+  // eq. cov_update around the new mean: 512 threads, 8 partial sums per
+  // entry (products commute, so the matrix comes out exactly symmetric).
+  if (tid < 512) {
+    const int e = tid & 63, part = tid >> 6;
+    const int a = e >> 3, b = e & 7;
     const double ma = s_mun[a], mb = s_mun[b];
     double c = 0.0;
-    for (int i = 0; i < q; ++i) c += s_w[i] * (s_p[i][a] - ma) * (s_p[i][b] - mb);
-    snew = (1.0 - P.eta) * s_sig[a * 8 + b] + P.eta * c / s_sum;
+    for (int i = part; i < q; i += 8) c += s_w[i] * (s_p[i][a] - ma) * (s_p[i][b] - mb);
+    s_part[part][e] = c;
   }
   __syncthreads();
-  if (tid < 64) s_sig[tid] = snew;
-  if (tid < 8) Sd.mu[tid] = s_mun[tid];
+  if (tid < 64) {
+    double c = 0.0;
+    for (int part = 0; part < 8; ++part) c += s_part[part][tid];
+    s_sig[tid] = (1.0 - P.eta) * s_sig[tid] + P.eta * c / s_sum;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int a = tid >> 3, b = tid & 7;
+    const double sym = 0.5 * (s_sig[a * 8 + b] + s_sig[b * 8 + a]);
+    s_part[0][tid] = sym;
+    Sd.sigma[tid] = sym;
+    if (A.tr_sigma) A.tr_sigma[((size_t)slot * P.L + l) * 64 + tid] = sym;
+    if (tid < 8) {
+      Sd.mu[tid] = s_mun[tid];
+      if (A.tr_mu) A.tr_mu[((size_t)slot * P.L + l) * 8 + tid] = s_mun[tid];
+    }
+    if (D.session_wb >= 0 && last) {
+      double *st = A.sess + (size_t)D.session_wb * 72;
+      st[8 + tid] = sym;
+      if (tid < 8) st[tid] = s_mun[tid];
+    }
+  }
   __syncthreads();
   if (tid == 0) {
     double sym[64];
-    for (int a = 0; a < 8; ++a)
-      for (int b = 0; b < 8; ++b) sym[a * 8 + b] = 0.5 * (s_sig[a * 8 + b] + s_sig[b * 8 + a]);
-    for (int i = 0; i < 64; ++i) Sd.sigma[i] = sym[i];
+    for (int i = 0; i < 64; ++i) sym[i] = s_part[0][i];
     const bool ok = chol8(sym, P.cov_jitter, Sd.chol);
-    if (A.tr_mu) {
-      for (int a = 0; a < 8; ++a) A.tr_mu[((size_t)slot * P.L + l) * 8 + a] = s_mun[a];
-      for (int i = 0; i < 64; ++i) A.tr_sigma[((size_t)slot * P.L + l) * 64 + i] = sym[i];
-    }
     R.iterations = l + 1;
-    if (last) {
-      // Return: lowest c_u + r in the final EliteSet (ties: lower index).
-      const uint32_t b = jbest;
-      R.best = (int32_t)b;
-      for (int a = 0; a < 8; ++a) R.p[a] = (double)p[(size_t)b * 8 + a];
-      const float *zb = A.zs + (base + b) * kZ;
-      const double n10 = 10.0, tf = P.t_f;
-      const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
-      const double ax0 = D.ego[4], ay0 = D.ego[5];
+    if (!ok) R.status = PLAN_E_INVALID;
+    if (A.l_uniform < 0) D.cur_iter = l + 1;
+  }
+  if (last && tid < 64) {
+    // Return: lowest c_u + r in the final EliteSet (ties: lower index).
+    const uint32_t b = jbest;
+    const double n10 = 10.0, tf = P.t_f;
+    const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
+    const double ax0 = D.ego[4], ay0 = D.ego[5];
+    const float *zb = A.zs + (base + b) * kZ;
+    if (tid < 8) R.p[tid] = (double)p[(size_t)b * 8 + tid];
+    if (tid < 8) R.xi[3 + tid] = (double)zb[tid] + x0 + vx0 * tf * (double)(3 + tid) / n10;
+    if (tid >= 8 && tid < 14) R.xi[14 + (tid - 8)] = (double)zb[tid];
+    if (tid == 14) R.xi[20] = R.xi[21] = (double)zb[14];
+    if (tid == 15) {
       R.xi[0] = x0;
       R.xi[1] = x0 + vx0 * tf / n10;
       R.xi[2] = x0 + 2.0 * vx0 * tf / n10 + ax0 * tf * tf / (n10 * (n10 - 1.0));
-      for (int c = 0; c < 8; ++c) R.xi[3 + c] = (double)zb[c] + x0 + vx0 * tf * (double)(3 + c) / n10;
       R.xi[11] = y0;
       R.xi[12] = y0 + vy0 * tf / n10;
       R.xi[13] = y0 + 2.0 * vy0 * tf / n10 + ay0 * tf * tf / (n10 * (n10 - 1.0));
-      for (int c = 0; c < 6; ++c) R.xi[14 + c] = (double)zb[8 + c];
-      R.xi[20] = R.xi[21] = (double)zb[14];
+    }
+    if (tid == 16) {
+      R.best = (int32_t)b;
       R.cost_upper = (double)cu[b];
       R.residual = (double)r[b];
-      R.flags = (r[b] > 0.f) ? PLAN_F_INFEASIBLE : 0u;
-      if (D.init_mode == kInitSession || D.init_mode == kInitGiven) R.flags |= PLAN_F_WARM;
-      if (D.session_wb >= 0) {
-        double *st = A.sess + (size_t)D.session_wb * 72;
-        for (int a = 0; a < 8; ++a) st[a] = s_mun[a];
-        for (int i = 0; i < 64; ++i) st[8 + i] = sym[i];
-      }
+      uint32_t fl = (r[b] > 0.f) ? PLAN_F_INFEASIBLE : 0u;
+      if (D.init_mode == kInitSession || D.init_mode == kInitGiven) fl |= PLAN_F_WARM;
+      R.flags = fl;
     }
-    if (!ok) R.status = PLAN_E_INVALID;
-    if (A.l_uniform < 0) D.cur_iter = l + 1;
   }
   // Trace of this iteration's samples, residuals and costs.
   if (A.tr_p) {
@@ -951,12 +980,22 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
 
 // Launch wrappers (C++ linkage, used by the engine).
 namespace plan {
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), lds, st, a, p);
+// With start/stop events the dispatch itself records them (no separate
+// marker packets between kernels).
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st,
+                        hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), (uint32_t)lds, st, ev0, ev1, 0, a, p);
+  else
+    hipLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), lds, st, a, p);
   return hipGetLastError();
 }
-hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st) {
-  hipLaunchKernelGGL(select_update_kernel, dim3(nreq), dim3(kSelBlock), 0, st, a, p);
+hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL(select_update_kernel, dim3(nreq), dim3(kSelBlock), 0, st, ev0, ev1, 0, a, p);
+  else
+    hipLaunchKernelGGL(select_update_kernel, dim3(nreq), dim3(kSelBlock), 0, st, a, p);
   return hipGetLastError();
 }
 }  // namespace plan
