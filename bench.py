@@ -13,7 +13,16 @@ Metric: lower-level QP solves per second = N * L / plan time.
 Prints one JSON line (see the keys below), including the roofline of the
 dominant kernel (lower_kernel, timed with HIP events on the library's stream
 over the timed region) and the FP64 oracle timed on host cores on the same
-scene.
+scene. Beside the headline (FP32) the line carries
+  mixed     the same plan with the lower level on the matrix cores
+            (PLAN_PREC_FP16_SPLIT),
+            and its position difference to the FP32 lower level on 256
+            inputs (the error of both against the FP64 oracle is stated
+            by the parity tests),
+  served    the served stream of 256 requests (saturated rate, then Poisson
+            arrivals at 0.7 of it; p50/p99 latency) in both precisions,
+  scale     1024 concurrent requests of N = 4096, T = 100, M = 20 in both
+            precisions.
 """
 from __future__ import annotations
 
@@ -104,12 +113,12 @@ def run_served(pl, h, reqs, arrivals):
     return lat, time.perf_counter() - t0
 
 
-def served_bench(pl, workload, torch, n_req=256, slots=64):
+def served_bench(pl, workload, torch, precision=0, n_req=256, slots=64):
     """Saturated rate, then Poisson arrivals at 0.7 of it: p50/p99 latency."""
     import numpy as np
     L, K = 5, 20
     cfg = pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=K, upper_iters=L, max_N=2048,
-                              max_requests=slots)
+                              max_requests=slots, precision=precision)
     ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
     h = pl.plan_create(cfg, workspace=ws, stream=torch.cuda.current_stream().cuda_stream)
     reqs = served_stream(pl, workload, n_req)
@@ -128,6 +137,79 @@ def served_bench(pl, workload, torch, n_req=256, slots=64):
             "makespan_s": span}
 
 
+def scale_bench(pl, workload, torch, precision=0, n_req=1024, N=4096, T=100, M=20):
+    """n_req concurrent requests of one size, all admitted at once (the
+    sample budget holds them all); makespan, solves/s, p50/p99 latency."""
+    import numpy as np
+    L, K = 5, 20
+    cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=n_req,
+                              precision=precision)
+    ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
+    h = pl.plan_create(cfg, workspace=ws, stream=torch.cuda.current_stream().cuda_stream)
+    reqs = []
+    for i in range(n_req):
+        s = workload.scene(5, i, M)
+        reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
+    run_served(pl, h, reqs[:4], np.zeros(4))  # warm-up
+    lat, span = run_served(pl, h, reqs, np.zeros(n_req))
+    return {"requests": n_req, "N": N, "T": T, "M": M, "L": L, "K": K, "solves_per_s": n_req * N * L / span,
+            "makespan_s": span, "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_latency_ms": 1e3 * float(np.percentile(lat, 99))}
+
+
+def precision_gap(pl, workload, c, n_samples=256):
+    """Lower level of both precisions on the same n_samples behavioural
+    inputs of the headline scene (seeded: lane offsets +- N(0, 0.3^2), speeds
+    U[5, 25]): largest position difference between the two trajectories. The
+    Bernstein basis is nonnegative and sums to one, so each axis differs by at
+    most the largest coefficient difference; the bound is reported."""
+    import numpy as np
+    rng = np.random.default_rng(2024)
+    s = workload.scene(CFG_ID, 0, c["M"])
+    lane = rng.choice([-3.5, 0.0, 3.5], size=(n_samples, 1))
+    p = np.hstack([lane + 0.3 * rng.standard_normal((n_samples, 4)), rng.uniform(5.0, 25.0, (n_samples, 4))])
+    xs = {}
+    for prec in (0, 1):
+        cfg = pl.plan_config_init(T_set=[c["T"]], M_set=[c["M"]], proj_iters=c["K"], max_N=n_samples,
+                                  max_requests=1, precision=prec)
+        h = pl.plan_create(cfg)
+        req = pl.Request(N=n_samples, T=c["T"], ego=s.ego, obstacles=s.obstacles, seed=s.seed)
+        xs[prec] = pl.plan_lower_solve(h, req, p)[1]
+    d = np.abs(xs[1] - xs[0])
+    bound = np.sqrt(d[:, :11].max(axis=1) ** 2 + d[:, 11:].max(axis=1) ** 2)
+    return {"samples": n_samples, "unit": "m", "max": float(bound.max()), "p99": float(np.percentile(bound, 99)),
+            "definition": "bound on max over t of |position(fp16_split) - position(f32)|"}
+
+
+def time_plan(pl, torch, c, scene, precision, steps, warmup):
+    """One staged plan launched warmup + steps times; returns (elapsed s,
+    kernel ms dict, launch counts, result)."""
+    N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
+    cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=1,
+                              precision=precision)
+    ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    h = pl.plan_create(cfg, workspace=ws, stream=stream.cuda_stream)
+    req = pl.Request(N=N, T=T, ego=scene.ego, obstacles=scene.obstacles, seed=scene.seed)
+    pl.plan_stage(h, [req])  # inputs into HBM before the timed region
+    for _ in range(warmup):
+        pl.plan_launch(h)
+    torch.cuda.synchronize()
+    pl.plan_profile(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pl.plan_launch(h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, cnt = pl.plan_profile_read(h)
+    pl.plan_profile(h, False)
+    res = pl.plan_collect(h)[0]
+    if res.status != 0:
+        raise RuntimeError(f"plan failed: {pl.plan_last_error(h)}")
+    return t1 - t0, ms, cnt, res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +217,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson) measurement")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP16-split plan and the accuracy check")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 1024-request measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 512 MiB device-to-device three times (a "
                          "kernel of known traffic that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -154,32 +238,10 @@ def main() -> int:
         return 1
     c = workload.CONFIGS[CFG_ID]
     N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
-    cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=1)
-    ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
-    stream = torch.cuda.current_stream()
-    h = pl.plan_create(cfg, workspace=ws, stream=stream.cuda_stream)
     scene = workload.scene(CFG_ID, 0, M)
-    req = pl.Request(N=N, T=T, ego=scene.ego, obstacles=scene.obstacles, seed=scene.seed)
-    pl.plan_stage(h, [req])  # inputs into HBM before the timed region
-
-    for _ in range(args.warmup):
-        pl.plan_launch(h)
-    torch.cuda.synchronize()
-    pl.plan_profile(h, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pl.plan_launch(h)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms, cnt = pl.plan_profile_read(h)
-    pl.plan_profile(h, False)
-    res = pl.plan_collect(h)[0]
-    if res.status != 0:
-        print(f"plan failed: {pl.plan_last_error(h)}", file=sys.stderr)
-        return 1
-
-    elapsed = t1 - t0
+    print(f"[bench] plan {c['name']} fp32: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
+          flush=True)
+    elapsed, ms, cnt, res = time_plan(pl, torch, c, scene, 0, args.steps, args.warmup)
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * L * args.steps / elapsed
     lower_avg_ms = ms["lower"] / max(1, cnt["lower"])
@@ -207,6 +269,16 @@ def main() -> int:
         "kernel_ms_per_step": {k: ms[k] / args.steps for k in ms},
         "plan": {"best_index": res.best_index, "cost_upper": res.cost_upper, "residual": res.residual},
     }
+    if not args.no_mixed:
+        print("[bench] plan fp16_split", file=sys.stderr, flush=True)
+        el2, ms2, cnt2, res2 = time_plan(pl, torch, c, scene, 1, args.steps, args.warmup)
+        avg2 = ms2["lower"] / max(1, cnt2["lower"])
+        out["mixed"] = {"precision": "fp16_split", "value": N * L * args.steps / el2, "unit": "QP-solves/s",
+                        "ms_per_step": 1e3 * el2 / args.steps, "kernel": "lower_mfma_kernel",
+                        "lower_avg_ms": avg2, "achieved_alg_tflops": flop / (avg2 * 1e-3) / 1e12,
+                        "kernel_ms_per_step": {k: ms2[k] / args.steps for k in ms2},
+                        "plan": {"best_index": res2.best_index, "cost_upper": res2.cost_upper}}
+        out["mixed"]["gap_to_f32"] = precision_gap(pl, workload, c)
     if args.copy_probe:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
@@ -214,7 +286,15 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
     if not args.no_served:
-        out["served"] = served_bench(pl, workload, torch)
+        out["served"] = {}
+        for name, prec in (("f32", 0), ("fp16_split", 1)):
+            print(f"[bench] served stream {name}", file=sys.stderr, flush=True)
+            out["served"][name] = served_bench(pl, workload, torch, prec)
+    if not args.no_scale:
+        out["scale"] = {}
+        for name, prec in (("f32", 0), ("fp16_split", 1)):
+            print(f"[bench] 1024 concurrent requests {name}", file=sys.stderr, flush=True)
+            out["scale"][name] = scale_bench(pl, workload, torch, prec)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(scene, c, threads)

@@ -65,8 +65,26 @@ typedef enum plan_status {
 #define PLAN_F_INFEASIBLE 1u /* the returned trajectory has residual r > 0 */
 #define PLAN_F_WARM 2u       /* iteration 0 sampled from a warm start       */
 
+/*
+ * Arithmetic of the lower level (Alg. 2 and the residual of each sample).
+ *   PLAN_PREC_FP32        every product and evaluation in FP32 on the vector
+ *                         ALUs.
+ *   PLAN_PREC_FP16_SPLIT  the dense products (trajectory evaluation W xi, the
+ *                         sums N^T g over the horizon and the xi-update
+ *                         A^-1 rhs) on the matrix cores in FP16 with FP32
+ *                         accumulation; every operand is split into a high
+ *                         and a low FP16 half and three products recover
+ *                         about 22 significant bits (the low x low term is
+ *                         dropped). Tables are built in FP64; everything
+ *                         between the products (projections, clips,
+ *                         residual) stays FP32. Requires every T <= 128;
+ *                         values beyond the FP16 range (|v| > 65504 after the
+ *                         scalings) give NaN residuals, which rank last.
+ * Both modes draw the same samples and use the same selection and update.
+ */
 typedef enum plan_precision {
-  PLAN_PREC_FP32 = 0 /* every lower-level product and evaluation in FP32 */
+  PLAN_PREC_FP32 = 0,
+  PLAN_PREC_FP16_SPLIT = 1
 } plan_precision;
 
 /*

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libplan.so")
 
 PLAN_OK, PLAN_E_INVALID, PLAN_E_NOMEM, PLAN_E_DEVICE, PLAN_E_BUSY, PLAN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+PLAN_PREC_FP32, PLAN_PREC_FP16_SPLIT = 0, 1
 PLAN_F_INFEASIBLE, PLAN_F_WARM = 1, 2
 NC, NX, NP = 11, 22, 8
 MAX_N, MAX_M, MAX_T = 4096, 32, 256

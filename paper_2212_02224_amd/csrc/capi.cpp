@@ -29,6 +29,8 @@
 namespace plan {
 hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int waves, size_t lds,
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1);
 }  // namespace plan
@@ -59,14 +61,41 @@ int64_t budget_rows(const plan_config &c) {
   return c.sample_budget > 0 ? c.sample_budget : (int64_t)c.max_requests * c.max_N;
 }
 
-// Dynamic LDS of the lower kernel: two neighbours per float4, per instant.
-size_t lds_bytes(int M, int T) { return (size_t)((M + 1) / 2) * T * sizeof(float4); }
+bool mfma_mode(const plan_config &c) { return c.precision == PLAN_PREC_FP16_SPLIT; }
 
-// Workgroups of one request: ceil(T/64) waves per sample, 4 waves per group.
-int blocks_for(int N, int T) {
+// Waves per workgroup of the matrix-core kernel: 4 instant tiles per wave.
+int mfma_waves(int T) { return (T + 4 * kMfmaTpw - 1) / (4 * kMfmaTpw); }
+
+// Dynamic LDS of the lower kernels: two neighbours per float4 and instant;
+// the matrix-core kernel adds its basis table (kEvInstHalfs halves per
+// instant of the padded horizon), the fixed trajectory part (two float4 per
+// instant) and the double-buffered partial sums.
+size_t lds_bytes(int M, int T, bool mfma) {
+  size_t b = (size_t)((M + 1) / 2) * T * sizeof(float4);
+  if (mfma) {
+    const size_t NI = 4 * (size_t)((T + 3) / 4);
+    b += NI * kEvInstHalfs * 2 + (2 * NI + (size_t)2 * mfma_waves(T) * kWave) * sizeof(float4);
+  }
+  return b;
+}
+
+// Workgroups of one request. VALU kernel: ceil(T/64) waves per sample, 4
+// waves per group; matrix-core kernel: 16 samples per group.
+int blocks_for(int N, int T, bool mfma) {
+  if (mfma) return (N + kMfmaSamples - 1) / kMfmaSamples;
   const int spb = 4 / ((T + kWave - 1) / kWave);
   return (N + spb - 1) / spb;
 }
+
+// Lower-level launches of one upper iteration: one per horizon length in the
+// matrix-core mode (its workgroup shape depends on T), one in total else.
+struct LaunchSet {
+  int n_act = 0, ngroups = 0;
+  struct Group {
+    int act_off = 0, n = 0, nblocks = 0, waves = 0;
+    size_t lds = 0;
+  } grp[4];
+};
 
 struct DevBuf {
   char *base = nullptr;
@@ -81,14 +110,14 @@ struct DevBuf {
 
 // Device bytes of every region, in allocation order.
 struct Layout {
-  size_t basis = 0, step1 = 0, proj = 0, offs = 0;
+  size_t basis = 0, step1 = 0, proj = 0, offs = 0, mops = 0, mainv = 0;
   size_t desc = 0, dist = 0, result = 0, act = 0;
   size_t p = 0, zs = 0, rc = 0, sess = 0, xiout = 0;
   size_t tr_p = 0, tr_rc = 0, tr_idx = 0, tr_dist = 0;
   size_t total() const {
     size_t s = 0;
-    for (size_t b : {basis, step1, proj, offs, desc, dist, result, act, p, zs, rc, sess, xiout, tr_p, tr_rc,
-                     tr_idx, tr_dist})
+    for (size_t b : {basis, step1, proj, offs, mops, mainv, desc, dist, result, act, p, zs, rc, sess, xiout,
+                     tr_p, tr_rc, tr_idx, tr_dist})
       s += (b + 255) & ~(size_t)255;
     return s;
   }
@@ -102,11 +131,15 @@ Layout compute_layout(const plan_config &c) {
   for (int i = 0; i < c.n_T; ++i) L.basis += (size_t)kBasisCols * ((c.T_set[i] + 63) / 64 * 64) * 4;
   L.step1 = (size_t)c.n_T * kStep1Floats * 4;
   L.proj = (size_t)c.n_T * c.n_M * kProjFloats * 4;
-  L.offs = (size_t)c.n_T * 2 * 4;
+  L.offs = (size_t)c.n_T * 3 * 4;
+  if (mfma_mode(c)) {
+    for (int i = 0; i < c.n_T; ++i) L.mops += (size_t)4 * ((c.T_set[i] + 3) / 4) * kEvInstHalfs * 2;
+    L.mainv = (size_t)c.n_T * c.n_M * 2 * kWave * 8;
+  }
   L.desc = S * sizeof(ReqDesc);
   L.dist = S * sizeof(DistState);
   L.result = S * sizeof(ResultRec);
-  L.act = (2 * S + 1) * 4;
+  L.act = (2 * S + 8) * 4;
   L.p = R * 8 * 4;
   L.zs = R * kZ * 4;
   L.rc = R * 2 * 4;
@@ -147,7 +180,10 @@ const char *validate_config(const plan_config &c) {
   elite_sizes(c, c.max_N, n, q);
   if (n > kMaxCes) return "ConstraintEliteSet larger than 1024 samples is not supported";
   if (q > kMaxEs) return "EliteSet larger than 256 samples is not supported";
-  if (c.precision != PLAN_PREC_FP32) return "unsupported precision";
+  if (c.precision != PLAN_PREC_FP32 && c.precision != PLAN_PREC_FP16_SPLIT) return "unsupported precision";
+  if (mfma_mode(c))
+    for (int i = 0; i < c.n_T; ++i)
+      if (c.T_set[i] > kMfmaMaxT) return "PLAN_PREC_FP16_SPLIT supports T <= 128";
   return nullptr;
 }
 
@@ -183,7 +219,8 @@ struct plan_handle {
   int64_t rows = 0;
   // tables
   float *basis = nullptr, *step1 = nullptr, *proj = nullptr;
-  int32_t *basis_off = nullptr, *basis_tpad = nullptr;
+  int32_t *basis_off = nullptr, *basis_tpad = nullptr, *mops_off = nullptr;
+  uint16_t *mops = nullptr, *mainv = nullptr;
   // slots and the row pool
   ReqDesc *desc = nullptr;
   DistState *dist = nullptr;
@@ -203,8 +240,7 @@ struct plan_handle {
   DistState *h_dist = nullptr;
   // batch mode: staged requests in slots 0..staged-1
   int staged = 0;
-  int nblocks = 0;
-  size_t lds = 0;
+  LaunchSet ls;
   std::vector<int> staged_req;
   std::vector<int> staged_status;
   int staged_total = 0;
@@ -292,7 +328,8 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   const int ti = find_T(c, r.T), mi = find_M(c, r.M);
   if (ti < 0) return "T not in T_set";
   if (mi < 0) return "M not in M_set";
-  if (lds_bytes(r.M, r.T) > 60 * 1024) return "M * T too large for the LDS table";
+  if (lds_bytes(r.M, r.T, false) > 60 * 1024) return "M * T too large for the LDS table";
+  if (mfma_mode(c) && lds_bytes(r.M, r.T, true) > 64 * 1024) return "M * T too large for the LDS table";
   if (!finite_all(r.ego, 6) || !std::isfinite(r.kappa_road)) return "non-finite ego state";
   if (r.M > 0 && r.obstacles == nullptr) return "obstacles missing";
   if (r.M > 0 && !finite_all(r.obstacles, 4 * r.M)) return "non-finite obstacle";
@@ -399,6 +436,9 @@ LowerArgs lower_args(plan_handle *h, int n_act, int l_uniform) {
   a.cost = h->cost;
   a.xi_bar_out = nullptr;
   a.xi_star_out = nullptr;
+  a.mops = h->mops;
+  a.mops_off = h->mops_off;
+  a.mainv = h->mainv;
   return a;
 }
 
@@ -427,18 +467,85 @@ plan_status timed(plan_handle *h, int kind, F &&launch, const char *what) {
   return PLAN_OK;
 }
 
-// One upper iteration of n_act resident slots (the act arrays are on the
-// device): lower_kernel then select_update_kernel.
-plan_status launch_iteration(plan_handle *h, int n_act, int nblocks, size_t lds, int l_uniform) {
-  const LowerArgs la = lower_args(h, n_act, l_uniform);
-  const SelArgs sa = sel_args(h, l_uniform);
-  plan_status st = timed(
-      h, 0, [&](hipEvent_t a, hipEvent_t b) { return launch_lower(la, h->mp, nblocks, lds, h->stream, a, b); },
-      "lower_kernel");
-  if (st == PLAN_OK)
+// Order the slots into launch groups and fill the host act / prefix arrays:
+// group k's slots at act[off..off+n), its workgroup prefix counts at
+// prefix[off + k .. off + k + n].
+void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
+  const bool mf = mfma_mode(h->cfg);
+  int32_t *act = h->h_act, *prefix = h->h_act + h->cfg.max_requests;
+  ls = LaunchSet();
+  ls.n_act = n;
+  int keys[4];
+  int nkeys = 0;
+  for (int i = 0; i < n; ++i) {
+    const int key = mf ? h->h_desc[slots[i]].T : 0;
+    bool seen = false;
+    for (int k = 0; k < nkeys; ++k) seen |= keys[k] == key;
+    if (!seen) keys[nkeys++] = key;
+  }
+  std::sort(keys, keys + nkeys);
+  int pos = 0;
+  for (int k = 0; k < nkeys; ++k) {
+    LaunchSet::Group &gr = ls.grp[k];
+    gr.act_off = pos;
+    int blocks = 0;
+    for (int i = 0; i < n; ++i) {
+      const ReqDesc &d = h->h_desc[slots[i]];
+      if ((mf ? d.T : 0) != keys[k]) continue;
+      act[pos] = slots[i];
+      prefix[pos + k] = blocks;
+      blocks += blocks_for(d.N, d.T, mf);
+      gr.lds = std::max(gr.lds, lds_bytes(d.M, d.T, mf));
+      ++pos;
+    }
+    gr.n = pos - gr.act_off;
+    gr.nblocks = blocks;
+    prefix[pos + k] = blocks;
+    gr.waves = mf ? mfma_waves(keys[k]) : kBlock / kWave;
+  }
+  ls.ngroups = nkeys;
+}
+
+plan_status upload_launch_set(plan_handle *h, const LaunchSet &ls) {
+  if (ls.n_act == 0) return PLAN_OK;
+  const int32_t *act = h->h_act, *prefix = h->h_act + h->cfg.max_requests;
+  HIP_TRY(h, hipMemcpyAsync(h->act_slots, act, sizeof(int32_t) * ls.n_act, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->blk_prefix, prefix, sizeof(int32_t) * (ls.n_act + ls.ngroups),
+                            hipMemcpyHostToDevice, h->stream));
+  return PLAN_OK;
+}
+
+plan_status launch_lower_set(plan_handle *h, const LaunchSet &ls, int l_uniform, double *xi_bar, double *xi_star) {
+  for (int k = 0; k < ls.ngroups; ++k) {
+    const LaunchSet::Group &gr = ls.grp[k];
+    LowerArgs la = lower_args(h, gr.n, l_uniform);
+    la.act_slots += gr.act_off;
+    la.blk_prefix += gr.act_off + k;
+    la.xi_bar_out = xi_bar;
+    la.xi_star_out = xi_star;
+    const bool mf = mfma_mode(h->cfg);
+    plan_status st = timed(
+        h, 0,
+        [&](hipEvent_t a, hipEvent_t b) {
+          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, gr.waves, gr.lds, h->stream, a, b)
+                    : launch_lower(la, h->mp, gr.nblocks, gr.lds, h->stream, a, b);
+        },
+        mf ? "lower_mfma_kernel" : "lower_kernel");
+    if (st != PLAN_OK) return st;
+  }
+  return PLAN_OK;
+}
+
+// One upper iteration of the resident slots of a launch set (its arrays are
+// on the device): the lower kernel(s) then select_update_kernel.
+plan_status launch_iteration(plan_handle *h, const LaunchSet &ls, int l_uniform) {
+  plan_status st = launch_lower_set(h, ls, l_uniform, nullptr, nullptr);
+  if (st == PLAN_OK) {
+    const SelArgs sa = sel_args(h, l_uniform);
     st = timed(
-        h, 1, [&](hipEvent_t a, hipEvent_t b) { return launch_select(sa, h->mp, n_act, h->stream, a, b); },
+        h, 1, [&](hipEvent_t a, hipEvent_t b) { return launch_select(sa, h->mp, ls.n_act, h->stream, a, b); },
         "select_update_kernel");
+  }
   return st;
 }
 
@@ -447,8 +554,7 @@ plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int firs
   if (!h->resident.empty() || !h->queue.empty())
     return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them before batch calls");
   h->staged = 0;
-  h->nblocks = 0;
-  h->lds = 0;
+  h->ls = LaunchSet();
   h->staged_req.clear();
   h->staged_status.assign(n, PLAN_OK);
   h->staged_total = n;
@@ -456,7 +562,7 @@ plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int firs
   for (int i = 0; i < n; ++i)
     if (reqs[i].session_id != 0) last_of_session[reqs[i].session_id] = i;
   int64_t row = 0;
-  int32_t *act = h->h_act, *prefix = h->h_act + h->cfg.max_requests;
+  std::vector<int> slots;
   for (int i = 0; i < n; ++i) {
     if (h->staged >= h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more requests than max_requests");
     ReqDesc &d = h->h_desc[h->staged];
@@ -472,25 +578,18 @@ plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int firs
     row += d.N;
     const int slot = h->staged++;
     h->staged_req.push_back(i);
-    act[slot] = slot;
-    prefix[slot] = h->nblocks;
-    h->nblocks += blocks_for(d.N, d.T);
-    h->lds = std::max(h->lds, lds_bytes(d.M, d.T));
+    slots.push_back(slot);
   }
-  prefix[h->staged] = h->nblocks;
   if (h->staged == 0) return PLAN_OK;
+  make_launch_set(h, slots.data(), h->staged, h->ls);
   HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc) * h->staged, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->act_slots, act, sizeof(int32_t) * h->staged, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->blk_prefix, prefix, sizeof(int32_t) * (h->staged + 1), hipMemcpyHostToDevice,
-                            h->stream));
-  return PLAN_OK;
+  return upload_launch_set(h, h->ls);
 }
 
 plan_status launch_impl(plan_handle *h) {
   if (h->staged == 0) return PLAN_OK;
   plan_status st = PLAN_OK;
-  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l)
-    st = launch_iteration(h, h->staged, h->nblocks, h->lds, l);
+  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) st = launch_iteration(h, h->ls, l);
   return st;
 }
 
@@ -700,6 +799,11 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->proj = (float *)h->mem.take(L.proj);
   h->basis_off = (int32_t *)h->mem.take(L.offs);
   h->basis_tpad = h->basis_off + c.n_T;
+  h->mops_off = h->basis_off + 2 * c.n_T;
+  if (L.mops) {
+    h->mops = (uint16_t *)h->mem.take(L.mops);
+    h->mainv = (uint16_t *)h->mem.take(L.mainv);
+  }
   h->desc = (ReqDesc *)h->mem.take(L.desc);
   h->dist = (DistState *)h->mem.take(L.dist);
   h->result = (ResultRec *)h->mem.take(L.result);
@@ -740,18 +844,29 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     h->own_stream = e == hipSuccess;
   }
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_desc, sizeof(ReqDesc) * S);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_act, sizeof(int32_t) * (2 * S + 1));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_act, sizeof(int32_t) * (2 * S + 8));
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_result, sizeof(ResultRec) * S);
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_dist, sizeof(DistState) * S);
   // ---- upload tables
   if (e == hipSuccess) {
     std::vector<float> basis_all;
-    std::vector<int32_t> offs(2 * c.n_T);
+    std::vector<uint16_t> mops_all, mainv_all, tmp;
+    std::vector<int32_t> offs(3 * c.n_T);
     for (int i = 0; i < c.n_T; ++i) {
       offs[i] = (int32_t)basis_all.size();
       offs[c.n_T + i] = bts[i].Tpad;
       basis_all.insert(basis_all.end(), bts[i].table.begin(), bts[i].table.end());
+      if (h->mops) {
+        offs[2 * c.n_T + i] = (int32_t)mops_all.size();
+        build_mfma_basis(bts[i], tmp);
+        mops_all.insert(mops_all.end(), tmp.begin(), tmp.end());
+      }
     }
+    if (h->mops)
+      for (auto &t : pj) {
+        build_mfma_inverse(t, tmp);
+        mainv_all.insert(mainv_all.end(), tmp.begin(), tmp.end());
+      }
     std::vector<float> s1all, pjall;
     for (auto &t : s1) s1all.insert(s1all.end(), t.table.begin(), t.table.end());
     for (auto &t : pj) pjall.insert(pjall.end(), t.table.begin(), t.table.end());
@@ -762,6 +877,10 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
       e = hipMemcpyAsync(h->step1, s1all.data(), s1all.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(h->proj, pjall.data(), pjall.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && h->mops)
+      e = hipMemcpyAsync(h->mops, mops_all.data(), mops_all.size() * 2, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && h->mainv)
+      e = hipMemcpyAsync(h->mainv, mainv_all.data(), mainv_all.size() * 2, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->sess, 0, L.sess, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   }
@@ -841,24 +960,21 @@ plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const doub
   d.row_off = 0;
   std::vector<float> pf((size_t)N * 8);
   for (size_t i = 0; i < pf.size(); ++i) pf[i] = (float)p[i];
-  const int nb = blocks_for(d.N, d.T);
-  const int S = h->cfg.max_requests;
-  h->h_act[0] = 0;
-  h->h_act[S] = 0;
-  h->h_act[S + 1] = nb;
+  const int slot0 = 0;
+  LaunchSet ls;
+  make_launch_set(h, &slot0, 1, ls);
   HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc), hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->act_slots, h->h_act, sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->blk_prefix, h->h_act + S, 2 * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  plan_status ust = upload_launch_set(h, ls);
+  if (ust != PLAN_OK) return ust;
   HIP_TRY(h, hipMemcpyAsync(h->p, pf.data(), pf.size() * 4, hipMemcpyHostToDevice, h->stream));
-  LowerArgs la = lower_args(h, 1, 0);
-  la.xi_bar_out = h->xi_out;
-  la.xi_star_out = h->xi_out + (size_t)h->cfg.max_N * 22;
-  HIP_TRY(h, launch_lower(la, h->mp, nb, lds_bytes(d.M, d.T), h->stream, nullptr, nullptr));
+  double *xi_bar_d = h->xi_out, *xi_star_d = h->xi_out + (size_t)h->cfg.max_N * 22;
+  ust = launch_lower_set(h, ls, 0, xi_bar_d, xi_star_d);
+  if (ust != PLAN_OK) return ust;
   std::vector<double> xo((size_t)N * 22 * 2);
   std::vector<float> rc((size_t)N * 2);
-  HIP_TRY(h, hipMemcpyAsync(xo.data(), la.xi_bar_out, (size_t)N * 22 * 8, hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(xo.data() + (size_t)N * 22, la.xi_star_out, (size_t)N * 22 * 8,
-                            hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(xo.data(), xi_bar_d, (size_t)N * 22 * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(xo.data() + (size_t)N * 22, xi_star_d, (size_t)N * 22 * 8, hipMemcpyDeviceToHost,
+                            h->stream));
   HIP_TRY(h, hipMemcpyAsync(rc.data(), h->resid, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipMemcpyAsync(rc.data() + N, h->cost, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -970,28 +1086,24 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
     admitted.push_back(slot);
     h->queue.pop_front();
   }
-  for (int slot : admitted)
-    HIP_TRY(h, hipMemcpyAsync(h->desc + slot, h->h_desc + slot, sizeof(ReqDesc), hipMemcpyHostToDevice,
-                              h->stream));
+  // descriptors of the admitted slots, one copy per run of consecutive slots
+  std::sort(admitted.begin(), admitted.end());
+  for (size_t a = 0; a < admitted.size();) {
+    size_t b = a + 1;
+    while (b < admitted.size() && admitted[b] == admitted[b - 1] + 1) ++b;
+    HIP_TRY(h, hipMemcpyAsync(h->desc + admitted[a], h->h_desc + admitted[a], sizeof(ReqDesc) * (b - a),
+                              hipMemcpyHostToDevice, h->stream));
+    a = b;
+  }
   const int n_act = (int)h->resident.size();
   if (n_act > 0) {
     // One upper iteration for every resident request.
-    int32_t *act = h->h_act, *prefix = h->h_act + S;
-    int nblocks = 0;
-    size_t lds = 0;
-    for (int i = 0; i < n_act; ++i) {
-      const Resident &rs = h->resident[i];
-      act[i] = rs.slot;
-      prefix[i] = nblocks;
-      nblocks += blocks_for(rs.N, rs.T);
-      const ReqDesc &d = h->h_desc[rs.slot];
-      lds = std::max(lds, lds_bytes(d.M, d.T));
-    }
-    prefix[n_act] = nblocks;
-    HIP_TRY(h, hipMemcpyAsync(h->act_slots, act, sizeof(int32_t) * n_act, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(h->blk_prefix, prefix, sizeof(int32_t) * (n_act + 1), hipMemcpyHostToDevice,
-                              h->stream));
-    plan_status st = launch_iteration(h, n_act, nblocks, lds, -1);
+    std::vector<int> slots(n_act);
+    for (int i = 0; i < n_act; ++i) slots[i] = h->resident[i].slot;
+    LaunchSet ls;
+    make_launch_set(h, slots.data(), n_act, ls);
+    plan_status st = upload_launch_set(h, ls);
+    if (st == PLAN_OK) st = launch_iteration(h, ls, -1);
     if (st != PLAN_OK) return st;
     std::vector<int> finished;
     for (int i = 0; i < n_act; ++i) {

@@ -320,12 +320,18 @@ __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, i
   }
 }
 
-// One target pass (steps split_alpha_o .. update_slack of Alg. 2) at this
-// lane's instant, accumulated into the lane's share of N^T g.
-__device__ __forceinline__ void target_pass(const Lane &L, const Scal &S, const float (&zs)[15],
-                                            const float4 *__restrict__ obs, int npair, int T, int t,
-                                            bool tv, float &da_prev, float (&g)[16]) {
-  State6 s = eval_traj(L, zs, S.vx0);
+// Differences between the targets of one (alpha, d) step and the current
+// trajectory at one instant: x axis (obstacles, velocity, acceleration) and
+// y axis (obstacles plus the lane bounds, velocity, acceleration).
+struct Corr {
+  float dox, dvx, dax, wy, dvy, day;
+};
+
+// Steps split_alpha_o .. update_slack of Alg. 2 at one instant, from the
+// trajectory state s there. da_prev carries d_a of the previous step. All
+// differences are zero where tv is false.
+__device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const float4 *__restrict__ obs,
+                                           int npair, int T, int t, bool tv, float &da_prev) {
   float ax, ay;
   neighbour_pass(obs, npair, T, t, s.x * S.ia, s.y * S.ib, ax, ay);
   float dox = ax * S.ell_a, doy = ay * S.ell_b;
@@ -352,26 +358,38 @@ __device__ __forceinline__ void target_pass(const Lane &L, const Scal &S, const 
   const float ahi = sig > 0.f ? fminf(S.a_max, dv * dv * S.kmax * frcp(sig)) : S.a_max;
   const float dan = fminf(an, ahi);
   const float kv = (dv - vn) * rv, ka = (dan - an) * ra;
-  float dvx = vz ? dv : kv * s.xd, dvy = kv * s.yd;
-  float dax = az ? dan : ka * s.xdd, day = ka * s.ydd;
+  Corr c;
+  c.dvx = vz ? dv : kv * s.xd;
+  c.dvy = kv * s.yd;
+  c.dax = az ? dan : ka * s.xdd;
+  c.day = ka * s.ydd;
   if (tv) da_prev = dan;
   // lane bounds: e - s - G xi = clip(y, y_lb, y_ub) - y
-  float wy = doy + (fminf(fmaxf(s.y, S.y_lb), S.y_ub) - s.y);
-  if (!tv) dox = wy = dvx = dvy = dax = day = 0.f;
+  c.wy = doy + (fminf(fmaxf(s.y, S.y_lb), S.y_ub) - s.y);
+  c.dox = dox;
+  if (!tv) c.dox = c.wy = c.dvx = c.dvy = c.dax = c.day = 0.f;
+  return c;
+}
+
+// One target pass at this lane's instant, accumulated into the lane's share
+// of N^T g.
+__device__ __forceinline__ void target_pass(const Lane &L, const Scal &S, const float (&zs)[15],
+                                            const float4 *__restrict__ obs, int npair, int T, int t,
+                                            bool tv, float &da_prev, float (&g)[16]) {
+  const State6 s = eval_traj(L, zs, S.vx0);
+  const Corr c = targets_at(s, S, obs, npair, T, t, tv, da_prev);
 #pragma unroll
-  for (int c = 0; c < 8; ++c) g[c] = fmaf(L.bx[c], dox, fmaf(L.bdx[c], dvx, L.bddx[c] * dax));
+  for (int k = 0; k < 8; ++k) g[k] = fmaf(L.bx[k], c.dox, fmaf(L.bdx[k], c.dvx, L.bddx[k] * c.dax));
 #pragma unroll
-  for (int c = 0; c < 6; ++c) g[8 + c] = fmaf(L.bx[c], wy, fmaf(L.bdx[c], dvy, L.bddx[c] * day));
-  g[14] = fmaf(L.by7, wy, fmaf(L.bdy7, dvy, L.bddy7 * day));
+  for (int k = 0; k < 6; ++k) g[8 + k] = fmaf(L.bx[k], c.wy, fmaf(L.bdx[k], c.dvy, L.bddx[k] * c.day));
+  g[14] = fmaf(L.by7, c.wy, fmaf(L.bdy7, c.dvy, L.bddy7 * c.day));
   g[15] = 0.f;
 }
 
 // Residual r (sum of max(0, g) over Table ineq_list) and upper cost c_u at
-// this lane's instant.
-__device__ __forceinline__ void residual_pass(const Lane &L, const Scal &S, const float (&zs)[15],
-                                              const float4 *__restrict__ obs, int npair, int T, int t,
-                                              bool tv, float &res, float &cost) {
-  State6 s = eval_traj(L, zs, S.vx0);
+// one instant of the trajectory state s.
+__device__ __forceinline__ void residual_at(const State6 &s, const Scal &S, const float4 *__restrict__ obs,
+                                            int npair, int T, int t, bool tv, float &res, float &cost) {
   const float xs = s.x * S.ia, ys = s.y * S.ib;
   float r = 0.f;
   for (int c = 0; c < npair; ++c) {
@@ -395,8 +413,15 @@ __device__ __forceinline__ void residual_pass(const Lane &L, const Scal &S, cons
   cost = tv ? e * e : 0.f;
 }
 
-// Workgroup -> (slot, first sample): binary search of the workgroup index in
-// the prefix counts of the launch's active slots (uniform scalar loads).
+__device__ __forceinline__ void residual_pass(const Lane &L, const Scal &S, const float (&zs)[15],
+                                              const float4 *__restrict__ obs, int npair, int T, int t,
+                                              bool tv, float &res, float &cost) {
+  residual_at(eval_traj(L, zs, S.vx0), S, obs, npair, T, t, tv, res, cost);
+}
+
+// Workgroup -> slot: binary search of the workgroup index in the prefix
+// counts of the launch's active slots (uniform scalar loads). Returns the
+// slot and the workgroup's rank within it.
 __device__ __forceinline__ int2 block_slot(const LowerArgs &A) {
   int lo = 0, hi = A.n_act - 1;
   const int b = blockIdx.x;
@@ -405,10 +430,156 @@ __device__ __forceinline__ int2 block_slot(const LowerArgs &A) {
     if (A.blk_prefix[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
-  const int slot = A.act_slots[lo];
-  const int T = A.desc[slot].T;
-  const int spb = 4 / ((T + kWave - 1) / kWave);
-  return make_int2(slot, (b - A.blk_prefix[lo]) * spb);
+  return make_int2(A.act_slots[lo], b - A.blk_prefix[lo]);
+}
+
+// Neighbour positions relative to the reference line x0 + vx0 t, divided by
+// the ellipse axes, two neighbours per entry [pair][T] (an odd last one is
+// paired with a point far away). Constant velocities as in the collision
+// row of Table ineq_list.
+__device__ void stage_neighbours(const ReqDesc &D, const MethodParams &P, float4 *s_obs) {
+  const int T = D.T, M = D.M, npair = (M + 1) >> 1;
+  const double x0 = D.ego[0], vx0 = D.ego[2];
+  const double ia = 1.0 / P.ell_a, ib = 1.0 / P.ell_b;
+  for (int idx = threadIdx.x; idx < npair * T; idx += blockDim.x) {
+    const int c = idx / T, k = idx - c * T;
+    const double tk = P.t_f * (double)k / (double)(T - 1);
+    float v[4];
+    for (int h = 0; h < 2; ++h) {
+      const int i = 2 * c + h;
+      if (i < M) {
+        v[2 * h] = (float)(((D.obs[i][0] - x0) + (D.obs[i][2] - vx0) * tk) * ia);
+        v[2 * h + 1] = (float)((D.obs[i][1] + D.obs[i][3] * tk) * ib);
+      } else {
+        v[2 * h] = 1e18f;
+        v[2 * h + 1] = 1e18f;
+      }
+    }
+    s_obs[idx] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// Sampling distribution of upper iteration l into LDS (Gaussian draws only):
+// the request's or the session's at iteration 0 (factored here), else the
+// one the previous update left with its factor.
+__device__ void load_distribution(const LowerArgs &A, const ReqDesc &D, const MethodParams &P, int slot, int l,
+                                  double *s_mu, double *s_chol) {
+  if (l == 0) {
+    if (threadIdx.x == 0) {
+      const double *m0 = D.mu0, *s0 = D.sigma0;
+      if (D.init_mode == kInitSession) {
+        m0 = A.sess + (size_t)D.session * 72;
+        s0 = m0 + 8;
+      }
+      for (int a = 0; a < 8; ++a) s_mu[a] = m0[a];
+      if (!chol8(s0, P.cov_jitter, s_chol))
+        for (int i = 0; i < 64; ++i) s_chol[i] = 0.0;  // reported by the update
+    }
+  } else if (threadIdx.x < 72) {
+    const DistState &Sd = A.dist[slot];
+    if (threadIdx.x < 8) s_mu[threadIdx.x] = Sd.mu[threadIdx.x];
+    else s_chol[threadIdx.x - 8] = Sd.chol[threadIdx.x - 8];
+  }
+}
+
+__device__ __forceinline__ Scal make_scal(const ReqDesc &D, const MethodParams &P) {
+  Scal S;
+  S.vx0 = (float)D.ego[2];
+  S.rho = (float)P.rho;
+  S.ia = (float)(1.0 / P.ell_a);
+  S.ib = (float)(1.0 / P.ell_b);
+  S.ell_a = (float)P.ell_a;
+  S.ell_b = (float)P.ell_b;
+  S.v_min = (float)P.v_min;
+  S.v_max = (float)P.v_max;
+  S.a_max = (float)P.a_max;
+  S.kmax = (float)P.kappa_max;
+  S.inv_kmax = (float)(1.0 / P.kappa_max);
+  S.c_max = (float)P.c_max;
+  S.kappa_abs = (float)fabs(D.kappa);
+  S.y_lb = (float)P.y_lb;
+  S.y_ub = (float)P.y_ub;
+  S.v_eps = (float)P.v_eps;
+  return S;
+}
+
+// Part of the trajectory at instant tt fixed by the initial conditions
+// (eq. boundary_cond_initial: c0, c1, c2 of each axis), x relative to the
+// reference line and without vx0.
+__device__ __forceinline__ State6 fixed_part(const float *Bt, int Tp, int tt, const ReqDesc &D,
+                                             const MethodParams &P) {
+  const double y0 = D.ego[1], vy0 = D.ego[3], ax0 = D.ego[4], ay0 = D.ego[5];
+  const double n = 10.0, tf = P.t_f;
+  // relative x frame: c0 = c1 = 0, c2 = ax0 t_f^2 / (n (n - 1))
+  const double cx2 = ax0 * tf * tf / (n * (n - 1.0));
+  const double cy0 = y0, cy1 = y0 + vy0 * tf / n;
+  const double cy2 = y0 + 2.0 * vy0 * tf / n + ay0 * tf * tf / (n * (n - 1.0));
+  const float W0 = Bt[(kColFix + 0) * Tp + tt], W1 = Bt[(kColFix + 1) * Tp + tt], W2 = Bt[(kColFix + 2) * Tp + tt];
+  const float Wd0 = Bt[(kColFix + 3) * Tp + tt], Wd1 = Bt[(kColFix + 4) * Tp + tt],
+              Wd2 = Bt[(kColFix + 5) * Tp + tt];
+  const float Wdd0 = Bt[(kColFix + 6) * Tp + tt], Wdd1 = Bt[(kColFix + 7) * Tp + tt],
+              Wdd2 = Bt[(kColFix + 8) * Tp + tt];
+  const float fx2 = (float)cx2, fy0 = (float)cy0, fy1 = (float)cy1, fy2 = (float)cy2;
+  State6 f;
+  f.x = W2 * fx2;
+  f.xd = Wd2 * fx2;
+  f.xdd = Wdd2 * fx2;
+  f.y = fmaf(W0, fy0, fmaf(W1, fy1, W2 * fy2));
+  f.yd = fmaf(Wd0, fy0, fmaf(Wd1, fy1, Wd2 * fy2));
+  f.ydd = fmaf(Wdd0, fy0, fmaf(Wdd1, fy1, Wdd2 * fy2));
+  return f;
+}
+
+// Step 1 (eq. over_3 through its affine map): free coefficient v of
+// z_bar = S p' + R b', p' = [y_d, v_d - vx0], b' = (ax0, y0, vy0, ay0).
+__device__ __forceinline__ float step1_coef(const float *S1, const ReqDesc &D, const float (&pin)[8], int v) {
+  const float *R1 = S1 + 16 * 8;
+  const double vx0 = D.ego[2];
+  float pp[8];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    pp[m] = pin[m];
+    pp[4 + m] = (float)((double)pin[4 + m] - vx0);
+  }
+  const float bb[4] = {(float)D.ego[4], (float)D.ego[1], (float)D.ego[3], (float)D.ego[5]};
+  float zb = 0.f;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) zb = fmaf(S1[v * 8 + m], pp[m], zb);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) zb = fmaf(R1[v * 4 + m], bb[m], zb);
+  return zb;
+}
+
+// FP64 coefficients of xi (absolute x) from the free coefficients: lane
+// owners write coefficient v of z (and of z_bar); writer_fixed adds c0..c2.
+__device__ __forceinline__ void write_xi(const ReqDesc &D, const MethodParams &P, double *xs, double *xb, int v,
+                                         float z, float zb, bool writer_fixed) {
+  const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
+  const double ax0 = D.ego[4], ay0 = D.ego[5];
+  const double n = 10.0, tf = P.t_f;
+  if (v < 8) {
+    const double ref = x0 + vx0 * tf * (double)(3 + v) / n;
+    xs[3 + v] = (double)z + ref;
+    xb[3 + v] = (double)zb + ref;
+  } else if (v < 14) {
+    xs[11 + 3 + (v - 8)] = (double)z;
+    xb[11 + 3 + (v - 8)] = (double)zb;
+  } else if (v == 14) {
+    xs[11 + 9] = xs[11 + 10] = (double)z;
+    xb[11 + 9] = xb[11 + 10] = (double)zb;
+  }
+  if (writer_fixed) {
+    const double c0 = x0, c1 = x0 + vx0 * tf / n;
+    const double c2 = x0 + 2.0 * vx0 * tf / n + ax0 * tf * tf / (n * (n - 1.0));
+    const double e0 = y0, e1 = y0 + vy0 * tf / n;
+    const double e2 = y0 + 2.0 * vy0 * tf / n + ay0 * tf * tf / (n * (n - 1.0));
+    xs[0] = xb[0] = c0;
+    xs[1] = xb[1] = c1;
+    xs[2] = xb[2] = c2;
+    xs[11] = xb[11] = e0;
+    xs[12] = xb[12] = e1;
+    xs[13] = xb[13] = e2;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
@@ -426,75 +597,18 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int sl = wave / NW;
   const int wi = wave - sl * NW;
-  const int j = bi.y + sl;
+  const int j = bi.y * spb + sl;
   const bool active = (sl < spb) && (j < N);
   const int t = wi * kWave + lane;
   const bool tv = active && t < T;
   const int tt = t < T ? t : T - 1;
   const size_t slot_off = (size_t)D.row_off;
 
-  const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
-  const double ax0 = D.ego[4], ay0 = D.ego[5];
-  const double ia = 1.0 / P.ell_a, ib = 1.0 / P.ell_b;
-
-  // Neighbour positions relative to the reference line, divided by the
-  // ellipse axes, two neighbours per entry (an odd last one is paired with a
-  // point far away).
-  for (int idx = threadIdx.x; idx < npair * T; idx += kBlock) {
-    const int c = idx / T, k = idx - c * T;
-    const double tk = P.t_f * (double)k / (double)(T - 1);
-    float v[4];
-    for (int h = 0; h < 2; ++h) {
-      const int i = 2 * c + h;
-      if (i < M) {
-        v[2 * h] = (float)(((D.obs[i][0] - x0) + (D.obs[i][2] - vx0) * tk) * ia);
-        v[2 * h + 1] = (float)((D.obs[i][1] + D.obs[i][3] * tk) * ib);
-      } else {
-        v[2 * h] = 1e18f;
-        v[2 * h + 1] = 1e18f;
-      }
-    }
-    s_obs[idx] = make_float4(v[0], v[1], v[2], v[3]);
-  }
-  // Distribution of this iteration (Gaussian draws only).
+  stage_neighbours(D, P, s_obs);
   const bool forced = D.init_mode == kInitForced;
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
-  if (!forced && !structured) {
-    if (l == 0) {
-      if (threadIdx.x == 0) {
-        const double *m0 = D.mu0, *s0 = D.sigma0;
-        if (D.init_mode == kInitSession) {
-          m0 = A.sess + (size_t)D.session * 72;
-          s0 = m0 + 8;
-        }
-        for (int a = 0; a < 8; ++a) s_mu[a] = m0[a];
-        if (!chol8(s0, P.cov_jitter, s_chol))
-          for (int i = 0; i < 64; ++i) s_chol[i] = 0.0;  // reported by the update
-      }
-    } else if (threadIdx.x < 72) {
-      const DistState &Sd = A.dist[bi.x];
-      if (threadIdx.x < 8) s_mu[threadIdx.x] = Sd.mu[threadIdx.x];
-      else s_chol[threadIdx.x - 8] = Sd.chol[threadIdx.x - 8];
-    }
-  }
-
-  Scal S;
-  S.vx0 = (float)vx0;
-  S.rho = (float)P.rho;
-  S.ia = (float)ia;
-  S.ib = (float)ib;
-  S.ell_a = (float)P.ell_a;
-  S.ell_b = (float)P.ell_b;
-  S.v_min = (float)P.v_min;
-  S.v_max = (float)P.v_max;
-  S.a_max = (float)P.a_max;
-  S.kmax = (float)P.kappa_max;
-  S.inv_kmax = (float)(1.0 / P.kappa_max);
-  S.c_max = (float)P.c_max;
-  S.kappa_abs = (float)fabs(D.kappa);
-  S.y_lb = (float)P.y_lb;
-  S.y_ub = (float)P.y_ub;
-  S.v_eps = (float)P.v_eps;
+  if (!forced && !structured) load_distribution(A, D, P, bi.x, l, s_mu, s_chol);
+  const Scal S = make_scal(D, P);
 
   // Basis rows of this lane's instant and the fixed part of the trajectory.
   const float *Bt = A.basis + A.basis_off[D.t_idx];
@@ -510,24 +624,13 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   L.bdy7 = Bt[(kColY7 + 1) * Tp + tt];
   L.bddy7 = Bt[(kColY7 + 2) * Tp + tt];
   {
-    const double n = 10.0, tf = P.t_f;
-    // relative x frame: c0 = c1 = 0, c2 = ax0 t_f^2 / (n (n - 1))
-    const double cx2 = ax0 * tf * tf / (n * (n - 1.0));
-    const double cy0 = y0, cy1 = y0 + vy0 * tf / n;
-    const double cy2 = y0 + 2.0 * vy0 * tf / n + ay0 * tf * tf / (n * (n - 1.0));
-    float W0 = Bt[(kColFix + 0) * Tp + tt], W1 = Bt[(kColFix + 1) * Tp + tt],
-          W2 = Bt[(kColFix + 2) * Tp + tt];
-    float Wd0 = Bt[(kColFix + 3) * Tp + tt], Wd1 = Bt[(kColFix + 4) * Tp + tt],
-          Wd2 = Bt[(kColFix + 5) * Tp + tt];
-    float Wdd0 = Bt[(kColFix + 6) * Tp + tt], Wdd1 = Bt[(kColFix + 7) * Tp + tt],
-          Wdd2 = Bt[(kColFix + 8) * Tp + tt];
-    float fx2 = (float)cx2, fy0 = (float)cy0, fy1 = (float)cy1, fy2 = (float)cy2;
-    L.xf = W2 * fx2;
-    L.xdf = Wd2 * fx2;
-    L.xddf = Wdd2 * fx2;
-    L.yf = fmaf(W0, fy0, fmaf(W1, fy1, W2 * fy2));
-    L.ydf = fmaf(Wd0, fy0, fmaf(Wd1, fy1, Wd2 * fy2));
-    L.yddf = fmaf(Wdd0, fy0, fmaf(Wdd1, fy1, Wdd2 * fy2));
+    const State6 f = fixed_part(Bt, Tp, tt, D, P);
+    L.xf = f.x;
+    L.xdf = f.xd;
+    L.xddf = f.xdd;
+    L.yf = f.y;
+    L.ydf = f.yd;
+    L.yddf = f.ydd;
   }
   const int v = lane >> 2;
   float arow[16];
@@ -555,25 +658,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     }
   }
 
-  // Step 1 (eq. over_3 through its affine map): z_bar = S p' + R b'.
-  float zb;
-  {
-    const float *S1 = A.step1 + (size_t)D.t_idx * kStep1Floats;
-    const float *R1 = S1 + 16 * 8;
-    float pp[8];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      pp[m] = pin[m];
-      pp[4 + m] = (float)((double)pin[4 + m] - vx0);
-    }
-    const float bb[4] = {(float)ax0, (float)y0, (float)vy0, (float)ay0};
-    zb = 0.f;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) zb = fmaf(S1[v * 8 + m], pp[m], zb);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) zb = fmaf(R1[v * 4 + m], bb[m], zb);
-  }
-
+  const float zb = step1_coef(A.step1 + (size_t)D.t_idx * kStep1Floats, D, pin, v);
   float z = zb, mu = 0.f;
   float zs[15];
 #pragma unroll
@@ -652,33 +737,364 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     A.resid[row] = rr;
     A.cost[row] = cc;
   }
-  if (A.xi_star_out != nullptr && wi == 0) {
-    // absolute coefficients in FP64: add back the reference line on x
-    const double n = 10.0, tf = P.t_f;
-    double *xs = A.xi_star_out + (size_t)j * 22;
-    double *xb = A.xi_bar_out + (size_t)j * 22;
-    if ((lane & 3) == 0 && v < 8) {
-      double ref = x0 + vx0 * tf * (double)(3 + v) / n;
-      xs[3 + v] = (double)z + ref;
-      xb[3 + v] = (double)zb + ref;
-    } else if ((lane & 3) == 0 && v >= 8 && v < 14) {
-      xs[11 + 3 + (v - 8)] = (double)z;
-      xb[11 + 3 + (v - 8)] = (double)zb;
-    } else if ((lane & 3) == 0 && v == 14) {
-      xs[11 + 9] = xs[11 + 10] = (double)z;
-      xb[11 + 9] = xb[11 + 10] = (double)zb;
-    } else if (lane == 61) {
-      double c0 = x0, c1 = x0 + vx0 * tf / n;
-      double c2 = x0 + 2.0 * vx0 * tf / n + ax0 * tf * tf / (n * (n - 1.0));
-      double e0 = y0, e1 = y0 + vy0 * tf / n;
-      double e2 = y0 + 2.0 * vy0 * tf / n + ay0 * tf * tf / (n * (n - 1.0));
-      xs[0] = xb[0] = c0;
-      xs[1] = xb[1] = c1;
-      xs[2] = xb[2] = c2;
-      xs[11] = xb[11] = e0;
-      xs[12] = xb[12] = e1;
-      xs[13] = xb[13] = e2;
+  if (A.xi_star_out != nullptr && wi == 0 && ((lane & 3) == 0 || lane == 61))
+    write_xi(D, P, A.xi_star_out + (size_t)j * 22, A.xi_bar_out + (size_t)j * 22, (lane & 3) == 0 ? v : 99, z,
+             zb, lane == 61);
+}
+
+// ---------------------------------------------------------------------------
+// Lower level on the matrix cores (FP16 high/low split, FP32 accumulation).
+//
+// A workgroup serves 16 samples of one request with ceil(T / 16) waves; wave
+// w owns the instant tiles 4w .. 4w + 3 (4 instants each). Lane l of every
+// wave belongs to sample n = l % 16 and to lane group g = l / 16, which holds
+//   * free coefficients 4g .. 4g + 3 of its sample (state z, z_bar, lambda),
+//   * at each tile, position / velocity / acceleration of both axes at
+//     instant 4 tile + g (the accumulator layout of the evaluation product).
+// Per tile and iteration, with every operand split as v = hi + lo in FP16:
+//   evaluation  [x, xd, xdd](4 instants) = fixed + B_hi z + B_lo z
+//               (v_mfma_f32_16x16x16_f16, z = [z_hi; z_lo]; 2 per axis)
+//   N^T g       += C_hi d_hi + C_hi d_lo + C_lo d_hi
+//               (v_mfma_f32_16x16x32_f16: both axes' differences of an
+//               instant in one operand; 3 per tile)
+// and once per iteration the xi-update dz = A^-1 rhs (3 products). The basis
+// table is staged in LDS per workgroup; the sums N^T g of the waves meet in
+// LDS and every wave applies the same update. Everything between the
+// products is the FP32 code of the VALU kernel.
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mma(h4 a, h4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ f4 mma32(h8 a, h8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// v = hi + lo: hi is v cut to 11 significant bits (exact in FP16 in its
+// normal range), lo the remainder rounded to FP16.
+__device__ __forceinline__ void split4(f4 v, h4 &hi, h4 &lo) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const float h = __uint_as_float(__float_as_uint(v[u]) & 0xFFFFE000u);
+    hi[u] = (_Float16)h;
+    lo[u] = (_Float16)(v[u] - h);
+  }
+}
+
+// (d0, d1, d2, 0, e0, e1, e2, 0) split into high and low halves.
+__device__ __forceinline__ void split_corr(const Corr &c, h8 &hi, h8 &lo) {
+  h4 h0, l0, h1, l1;
+  split4(f4{c.dox, c.dvx, c.dax, 0.f}, h0, l0);
+  split4(f4{c.wy, c.dvy, c.day, 0.f}, h1, l1);
+  hi = h8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+  lo = h8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+}
+
+__device__ __forceinline__ void swap32u(uint32_t &a, uint32_t &b) {
+  auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  a = r[0];
+  b = r[1];
+}
+
+// Evaluation operands from the state: lanes 0..31 hold the x coefficients,
+// 32..63 the y coefficients; one exchange of half-waves gives
+// bx = [x_hi; x_lo] and by = [y_hi; y_lo] (lane group g holds rows 4g..4g+3).
+__device__ __forceinline__ void coef_operands(f4 z, h4 &bx, h4 &by) {
+  h4 hi, lo;
+  split4(z, hi, lo);
+  uint2 a = __builtin_bit_cast(uint2, hi), b = __builtin_bit_cast(uint2, lo);
+  swap32u(a.x, b.x);
+  swap32u(a.y, b.y);
+  bx = __builtin_bit_cast(h4, a);
+  by = __builtin_bit_cast(h4, b);
+}
+
+// Draw of Alg. 1 for the 16 samples of a wave: lane group g runs Philox block
+// min(g, 2) and Box-Muller pair g of its sample; the same values as
+// wave_draw.
+__device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int l, bool structured,
+                           const double *mu, const double *chol, int lane, float (&p)[8]) {
+  const int n = lane & 15, g = lane >> 4;
+  uint32_t w[4];
+  rng_block(seed, j, l, g < 3 ? g : 2, w);
+  const int src = n + 16 * (g >> 1);
+  const uint32_t w0 = __shfl(w[0], src, 64), w1 = __shfl(w[1], src, 64);
+  const uint32_t w2 = __shfl(w[2], src, 64), w3 = __shfl(w[3], src, 64);
+  const bool odd = g & 1;
+  float n0, n1;
+  normals2(odd ? w2 : w0, odd ? w3 : w1, n0, n1);
+  float z[8];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    z[2 * m] = __shfl(n0, n + 16 * m, 64);
+    z[2 * m + 1] = __shfl(n1, n + 16 * m, 64);
+  }
+  uint32_t wb1[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) wb1[m] = __shfl(w[m], n + 16, 64);
+  const uint32_t sel = __shfl(w[0], n + 32, 64);
+  if (structured) {
+    const int ln = (int)(((uint64_t)sel * 3u) >> 32);
+    const double lc = P.lane_c[ln];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      p[m] = (float)(lc + P.lane_sigma * (double)z[m]);
+      const double u = (double)((wb1[m] >> 8) + 1u) * (1.0 / 16777216.0);
+      p[4 + m] = (float)(P.vd_lo + (P.vd_hi - P.vd_lo) * u);
     }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      double s = mu[a];
+#pragma unroll
+      for (int b = 0; b <= a; ++b) s += chol[a * 8 + b] * (double)z[b];
+      p[a] = (float)s;
+    }
+  }
+}
+
+// Dynamic LDS of the matrix-core kernel: basis table [4 NT][kEvInstHalfs],
+// neighbours [pair][T] (float4), fixed trajectory part [4 NT][2] (float4),
+// partial sums [2][waves][64] (float4).
+__host__ __device__ inline int mfma_waves(int T) { return (T + 4 * kMfmaTpw - 1) / (4 * kMfmaTpw); }
+
+__global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(LowerArgs A, MethodParams P) {
+  extern __shared__ float4 s_dyn[];
+  __shared__ double s_mu[8], s_chol[64];
+  __shared__ float s_rc[kMfmaMaxWaves][kMfmaSamples][2];
+
+  const int2 bi = block_slot(A);
+  const int slot = bi.x;
+  const ReqDesc &D = A.desc[slot];
+  const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
+  const int T = D.T, M = D.M, N = D.N;
+  const int npair = (M + 1) >> 1;
+  const int NT = (T + 3) >> 2;
+  const int NWv = blockDim.x / kWave;  // = mfma_waves(T), checked by the host
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int n = lane & 15, g = lane >> 4;
+  const int j = bi.y * kMfmaSamples + n;
+  const bool active = j < N;
+  const size_t slot_off = (size_t)D.row_off;
+
+  const int tab_f4 = NT * kEvInstHalfs / 2;  // 4 NT instants x 224 bytes, in float4
+  _Float16 *s_tab = reinterpret_cast<_Float16 *>(s_dyn);
+  float4 *s_obs = s_dyn + tab_f4;
+  float4 *s_fix = s_obs + npair * T;
+  float4 *s_part = s_fix + 8 * NT;
+
+  {
+    const float4 *src = reinterpret_cast<const float4 *>(A.mops + A.mops_off[D.t_idx]);
+    for (int i = threadIdx.x; i < tab_f4; i += blockDim.x) s_dyn[i] = src[i];
+  }
+  stage_neighbours(D, P, s_obs);
+  const bool forced = D.init_mode == kInitForced;
+  const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
+  if (!forced && !structured) load_distribution(A, D, P, slot, l, s_mu, s_chol);
+  const Scal S = make_scal(D, P);
+  {
+    // fixed part per instant: (x, xd + vx0, xdd, 0), (y, yd, ydd, 0); zero
+    // beyond the horizon
+    const float *Bt = A.basis + A.basis_off[D.t_idx];
+    const int Tp = A.basis_tpad[D.t_idx];
+    for (int t = threadIdx.x; t < 4 * NT; t += blockDim.x) {
+      float4 fx = make_float4(0.f, 0.f, 0.f, 0.f), fy = fx;
+      if (t < T) {
+        const State6 f = fixed_part(Bt, Tp, t, D, P);
+        fx = make_float4(f.x, S.vx0 + f.xd, f.xdd, 0.f);
+        fy = make_float4(f.y, f.yd, f.ydd, 0.f);
+      }
+      s_fix[2 * t] = fx;
+      s_fix[2 * t + 1] = fy;
+    }
+  }
+
+  // Per-lane offsets (in halves) into the basis table, relative to the first
+  // instant of a tile.
+  //   evaluation (row n = 4 a + q, column group g): 4 coefficients from
+  //   4 (g % 2) of order min(q, 2) (row q = 3 is not used) at instant a;
+  //   the low-half operand multiplies both halves of z (the lo x lo term
+  //   only adds precision).
+  const int ev_off = (n >> 2) * kEvInstHalfs + min(n & 3, 2) * 16 + 4 * (g & 1);
+  //   accumulation (row n = coefficient, column group g = instant): orders
+  //   0..2 of coefficient n of x (n < 8) or n - 8 of y (8 <= n < 15), the
+  //   zero pad elsewhere.
+  const int ac_x = g * kEvInstHalfs + (n < 8 ? n : kEvPad);
+  const int ac_y = g * kEvInstHalfs + (n >= 8 && n < 15 ? kEvAxisHalfs + (n - 8) : kEvPad);
+  const int q_step_x = n < 8 ? 16 : 0, q_step_y = n >= 8 && n < 15 ? 16 : 0;
+  auto ev_op = [&](int tile, int axis, int half) -> h4 {
+    return *reinterpret_cast<const h4 *>(s_tab + tile * 4 * kEvInstHalfs + ev_off + axis * kEvAxisHalfs +
+                                         half * 8);
+  };
+  auto ac_op = [&](int tile, int half) -> h8 {
+    const _Float16 *bx = s_tab + tile * 4 * kEvInstHalfs + ac_x + half * 8;
+    const _Float16 *by = s_tab + tile * 4 * kEvInstHalfs + ac_y + half * 8;
+    return h8{bx[0], bx[q_step_x], bx[2 * q_step_x], (_Float16)0.f,
+              by[0], by[q_step_y], by[2 * q_step_y], (_Float16)0.f};
+  };
+
+  const h4 *Ai = reinterpret_cast<const h4 *>(A.mainv) + (size_t)D.tm_idx * 2 * kWave;
+  const h4 ai_hi = Ai[lane], ai_lo = Ai[kWave + lane];
+  f4 Dv;
+  {
+    const float *Pj = A.proj + (size_t)D.tm_idx * kProjFloats;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Dv[u] = Pj[256 + 4 * g + u];
+  }
+  __syncthreads();  // basis table, neighbours, fixed part and distribution ready
+
+  float pin[8];
+  if (forced) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) pin[m] = active ? A.p[(slot_off + j) * 8 + m] : 0.f;
+  } else {
+    group_draw(P, D.seed, j, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
+    if (active && wave == 0 && g == 0) {
+      float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
+      dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
+      dst[1] = make_float4(pin[4], pin[5], pin[6], pin[7]);
+    }
+  }
+  f4 zb;
+  {
+    const float *S1 = A.step1 + (size_t)D.t_idx * kStep1Floats;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) zb[u] = step1_coef(S1, D, pin, 4 * g + u);
+  }
+  f4 z = zb, mu = {0.f, 0.f, 0.f, 0.f};
+
+  // Trajectory state at this lane's instant of a tile.
+  auto evaluate = [&](int tile, h4 bx, h4 by) -> State6 {
+    const float4 cx = s_fix[2 * (4 * tile + g)], cy = s_fix[2 * (4 * tile + g) + 1];
+    f4 ex = {cx.x, cx.y, cx.z, cx.w}, ey = {cy.x, cy.y, cy.z, cy.w};
+    ex = mma(ev_op(tile, 0, 0), bx, ex);
+    ex = mma(ev_op(tile, 0, 1), bx, ex);
+    ey = mma(ev_op(tile, 1, 0), by, ey);
+    ey = mma(ev_op(tile, 1, 1), by, ey);
+    State6 st;
+    st.x = ex[0];
+    st.xd = ex[1];
+    st.xdd = ex[2];
+    st.y = ey[0];
+    st.yd = ey[1];
+    st.ydd = ey[2];
+    return st;
+  };
+
+  float da[kMfmaTpw];
+  int buf = 0;
+  // One target pass over this wave's tiles at the current z (first: the
+  // initial d_a from the same evaluation); returns N^T g of the workgroup.
+  auto pass = [&](bool first) -> f4 {
+    h4 bx, by;
+    coef_operands(z, bx, by);
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < kMfmaTpw; ++i) {
+      const int tile = wave * kMfmaTpw + i;
+      if (tile < NT) {
+        const int t = 4 * tile + g;
+        const bool tv = active && t < T;
+        const State6 st = evaluate(tile, bx, by);
+        if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
+        const Corr c = targets_at(st, S, s_obs, npair, T, t < T ? t : T - 1, tv, da[i]);
+        h8 dh, dl;
+        split_corr(c, dh, dl);
+        const h8 ch = ac_op(tile, 0), cl = ac_op(tile, 1);
+        acc = mma32(ch, dh, acc);
+        acc = mma32(ch, dl, acc);
+        acc = mma32(cl, dh, acc);
+      }
+    }
+    s_part[(buf * NWv + wave) * kWave + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    __syncthreads();
+    f4 G = {0.f, 0.f, 0.f, 0.f};
+    for (int w = 0; w < NWv; ++w) {
+      const float4 q = s_part[(buf * NWv + w) * kWave + lane];
+      G += f4{q.x, q.y, q.z, q.w};
+    }
+    buf ^= 1;
+    return G;
+  };
+
+  f4 G = pass(true);
+  const int K = P.K;
+  for (int k = 1; k <= K; ++k) {
+    // xi-update (eq. split_xy): dz = A^-1 rhs on the matrix cores
+    f4 rhs;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) rhs[u] = fmaf(Dv[u], zb[u] - z[u], fmaf(S.rho, G[u], mu[u])) * kRhsScale;
+    h4 rh, rl;
+    split4(rhs, rh, rl);
+    f4 dz = {0.f, 0.f, 0.f, 0.f};
+    dz = mma(ai_hi, rh, dz);
+    dz = mma(ai_hi, rl, dz);
+    dz = mma(ai_lo, rh, dz);
+    z += dz * (float)(1.0 / (kAinvScale * kRhsScale));
+    if (k < K) {
+      G = pass(false);
+      mu += (0.5f * S.rho) * G;  // eq. update_lagrange
+    }
+  }
+
+  // Residual and upper cost of xi* = xi^K.
+  float rr = 0.f, cc = 0.f;
+  {
+    h4 bx, by;
+    coef_operands(z, bx, by);
+#pragma unroll
+    for (int i = 0; i < kMfmaTpw; ++i) {
+      const int tile = wave * kMfmaTpw + i;
+      if (tile < NT) {
+        const int t = 4 * tile + g;
+        float r1, c1;
+        residual_at(evaluate(tile, bx, by), S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, r1, c1);
+        rr += r1;
+        cc += c1;
+      }
+    }
+  }
+  // sum over the 4 lane groups of a sample, then over the waves
+  {
+    float a = rr, b = rr;
+    swap32(a, b);
+    rr = a + b;
+    a = rr;
+    b = rr;
+    swap16(a, b);
+    rr = a + b;
+    a = cc;
+    b = cc;
+    swap32(a, b);
+    cc = a + b;
+    a = cc;
+    b = cc;
+    swap16(a, b);
+    cc = a + b;
+  }
+  if (g == 0) {
+    s_rc[wave][n][0] = rr;
+    s_rc[wave][n][1] = cc;
+  }
+  __syncthreads();
+  if (wave != 0 || !active) return;
+  rr = 0.f;
+  cc = 0.f;
+  for (int w = 0; w < NWv; ++w) {
+    rr += s_rc[w][n][0];
+    cc += s_rc[w][n][1];
+  }
+  const size_t row = slot_off + j;
+  reinterpret_cast<float4 *>(A.zs + row * kZ)[g] = make_float4(z[0], z[1], z[2], z[3]);
+  if (g == 0) {
+    A.resid[row] = rr;
+    A.cost[row] = cc;
+  }
+  if (A.xi_star_out != nullptr) {
+    double *xs = A.xi_star_out + (size_t)j * 22, *xb = A.xi_bar_out + (size_t)j * 22;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) write_xi(D, P, xs, xb, 4 * g + u, z[u], zb[u], g == 3 && u == 3);
   }
 }
 
@@ -990,6 +1406,17 @@ hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, 
     hipLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), lds, st, a, p);
   return hipGetLastError();
 }
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int waves, size_t lds,
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (waves < 1 || waves > kMfmaMaxWaves) return hipErrorInvalidValue;
+  if (ev0 != nullptr)
+    hipExtLaunchKernelGGL(lower_mfma_kernel, dim3(nblocks), dim3(kWave * waves), (uint32_t)lds, st, ev0, ev1, 0,
+                          a, p);
+  else
+    hipLaunchKernelGGL(lower_mfma_kernel, dim3(nblocks), dim3(kWave * waves), lds, st, a, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1) {
   if (ev0)

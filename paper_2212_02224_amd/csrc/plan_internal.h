@@ -18,7 +18,13 @@ constexpr int kStep1Floats = 16 * 8 + 16 * 4;
 constexpr int kProjFloats = 16 * 16 + 16;
 constexpr int kMaxCes = 1024;        // LDS bound of the ConstraintEliteSet
 constexpr int kMaxEs = 256;          // LDS bound of the EliteSet
-constexpr int kBaCols = 45;          // columns of the per-(T, M) B A^-1 table
+// Matrix-core (FP16 high/low) lower level.
+constexpr int kMfmaTpw = 4;          // instant tiles (4 instants each) per wave
+constexpr int kMfmaMaxWaves = 8;     // waves per workgroup, so T <= 128
+constexpr int kMfmaMaxT = 4 * kMfmaTpw * kMfmaMaxWaves;
+constexpr int kMfmaSamples = 16;     // samples per workgroup (the MFMA N dimension)
+constexpr double kAinvScale = 256.0; // A^-1 is stored times this (exact power of two)
+constexpr float kRhsScale = 1.0f / 16.0f;  // the xi-update right-hand side is split times this
 
 // Columns of the per-T basis table (each column holds Tpad floats):
 //   0..7   W[:, 3..10]     8..15 Wd[:, 3..10]     16..23 Wdd[:, 3..10]
@@ -29,13 +35,14 @@ enum BasisCol {
   kColW = 0, kColWd = 8, kColWdd = 16, kColY7 = 24, kColFix = 27, kColT = 36
 };
 
-// Columns of the per-(T, M) table BA = B A^-1 (each Tpad floats): for the
-// x axis 8 columns per derivative order (W, Wd, Wdd), then for the y axis 7
-// per order: 0..7 W_x, 8..15 Wd_x, 16..23 Wdd_x, 24..30 W_y, 31..37 Wd_y,
-// 38..44 Wdd_y. Row t maps a right-hand side of the xi-update to the change
-// of the trajectory at t.
-enum BaCol { kBaWx = 0, kBaWdx = 8, kBaWddx = 16, kBaWy = 24, kBaWdy = 31, kBaWddy = 38 };
-
+// Basis table of the matrix-core lower level, per instant t (padded to a
+// multiple of 4 instants, zero beyond T), in FP16 halves:
+//   [axis x, y][q = position, velocity, acceleration][hi 0..7 | lo 8..15]
+// over the 8 free coefficients of the axis (x: c3..c10; y: c3..c8, c9 + c10,
+// 0), then a zero pad of 16 halves. v = hi + lo to about 22 bits.
+constexpr int kEvAxisHalfs = 48;          // 3 orders x 16
+constexpr int kEvPad = 96;                // offset of the zero pad
+constexpr int kEvInstHalfs = 112;         // halves per instant (224 bytes)
 // How iteration 0 draws its samples.
 enum InitMode : int32_t {
   kInitStructured = 0,  // structured initial sampler (lanes + uniform speeds)
@@ -112,6 +119,10 @@ struct LowerArgs {
   float *cost;               // row pool [rows]
   double *xi_bar_out;        // optional [N][22] (single request only)
   double *xi_star_out;       // optional [N][22] (single request only)
+  // matrix-core lower level only
+  const uint16_t *mops;      // concatenated per-T basis tables (FP16 bits)
+  const int32_t *mops_off;   // offset (in FP16 values) of table t_idx
+  const uint16_t *mainv;     // per-(T, M) [2][64][4] high / low of kAinvScale A^-1
 };
 
 // Arguments of the selection / update kernel and the init kernel.

@@ -11,6 +11,9 @@
 //   proj    inverse of A = N^T N + rho N^T (F^T F + G^T G) N (the xi-update
 //           of Alg. 2, eq. split_xy, in the free coordinates), block diagonal
 //           in x (8 x 8) and y (7 x 7), and D = diag(N^T N).
+//   mfma    the same basis and inverse as FP16 high/low pairs, laid out as
+//           the per-lane operands of v_mfma_f32_16x16x16_f16 (reduced-
+//           precision lower level).
 #include "precompute.h"
 
 #include <cmath>
@@ -285,29 +288,56 @@ void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt) {
   pt.table.resize(kProjFloats);
   for (int i = 0; i < 256; ++i) pt.table[i] = (float)pt.Ainv[i];
   for (int i = 0; i < 16; ++i) pt.table[256 + i] = (float)pt.D[i];
-  // BA = (basis rows of the free coefficients) x A^-1, per derivative order.
-  // x(t) changes by sum_d BA_x[t][d] rhs_d when z changes by A^-1 rhs.
-  pt.ba.assign((size_t)kBaCols * bt.Tpad, 0.f);
-  const std::vector<double> *rows[3] = {&bt.W, &bt.Wd, &bt.Wdd};
-  for (int k = 0; k < T; ++k) {
-    for (int o = 0; o < 3; ++o) {
-      const double *B = &(*rows[o])[k * kNC];
-      double bx[8], by[7];
-      for (int c = 0; c < 8; ++c) bx[c] = B[3 + c];
-      for (int c = 0; c < 6; ++c) by[c] = B[3 + c];
-      by[6] = B[9] + B[10];
-      for (int d = 0; d < 8; ++d) {
-        double s = 0.0;
-        for (int c = 0; c < 8; ++c) s += bx[c] * Ax[c * 8 + d];
-        pt.ba[(size_t)(kBaWx + 8 * o + d) * bt.Tpad + k] = (float)s;
-      }
-      for (int d = 0; d < 7; ++d) {
-        double s = 0.0;
-        for (int c = 0; c < 7; ++c) s += by[c] * Ay[c * 7 + d];
-        pt.ba[(size_t)(kBaWy + 7 * o + d) * bt.Tpad + k] = (float)s;
-      }
+}
+
+namespace {
+
+// FP16 bits of v rounded to nearest, and of the rounded remainder.
+uint16_t half_bits(double v) {
+  const _Float16 h = (_Float16)v;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+void split_half(double v, uint16_t &hi, uint16_t &lo) {
+  const _Float16 h = (_Float16)v;
+  std::memcpy(&hi, &h, 2);
+  lo = half_bits(v - (double)h);
+}
+
+// Basis value of free coefficient c of an axis (x: c3..c10; y: c3..c8, then
+// c9 + c10; anything else 0) for derivative order q at instant t.
+double free_basis(const BasisTable &bt, bool y_axis, int q, int t, int c) {
+  if (q > 2 || t >= bt.T || c < 0) return 0.0;  // beyond the horizon: zero
+  const std::vector<double> &B = q == 0 ? bt.W : (q == 1 ? bt.Wd : bt.Wdd);
+  const double *row = &B[(size_t)t * kNC];
+  if (!y_axis) return c < 8 ? row[3 + c] : 0.0;
+  if (c < 6) return row[3 + c];
+  if (c == 6) return row[9] + row[10];
+  return 0.0;
+}
+
+}  // namespace
+
+void build_mfma_basis(const BasisTable &bt, std::vector<uint16_t> &ops) {
+  const int NI = 4 * ((bt.T + 3) / 4);
+  ops.assign((size_t)NI * kEvInstHalfs, 0);
+  for (int t = 0; t < NI; ++t)
+    for (int ax = 0; ax < 2; ++ax)
+      for (int q = 0; q < 3; ++q)
+        for (int c = 0; c < 8; ++c) {
+          uint16_t *e = &ops[(size_t)t * kEvInstHalfs + ax * kEvAxisHalfs + q * 16];
+          split_half(t < bt.T ? free_basis(bt, ax == 1, q, t, c) : 0.0, e[c], e[8 + c]);
+        }
+}
+
+void build_mfma_inverse(const ProjTable &pt, std::vector<uint16_t> &ops) {
+  ops.assign(2 * 64 * 4, 0);
+  for (int lane = 0; lane < 64; ++lane)
+    for (int u = 0; u < 4; ++u) {
+      const int i = lane % 16, k = 4 * (lane / 16) + u;
+      split_half(kAinvScale * pt.Ainv[i * 16 + k], ops[(0 * 64 + lane) * 4 + u], ops[(1 * 64 + lane) * 4 + u]);
     }
-  }
 }
 
 }  // namespace plan

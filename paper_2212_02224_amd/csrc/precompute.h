@@ -1,6 +1,7 @@
 // precompute.h -- host FP64 construction of the per-T and per-(T, M) tables.
 #pragma once
 
+#include <cstdint>
 #include <vector>
 
 #include "plan_internal.h"
@@ -25,11 +26,17 @@ struct Step1Table {
 struct ProjTable {
   std::vector<double> Ainv, D;     // 16 x 16 block diagonal, 16
   std::vector<float> table;        // kProjFloats
-  std::vector<float> ba;           // kBaCols x Tpad: basis rows times A^-1 (device layout)
 };
 
 void build_basis(int T, double t_f, BasisTable &bt);
 void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, Step1Table &st);
 void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt);
+
+// FP16 bit patterns of the tables of the matrix-core lower level:
+//   basis   [4 ceil(T/4)][kEvInstHalfs] (layout in plan_internal.h)
+//   inverse [2][64 lanes][4]: high then low half of kAinvScale * A^-1 in the
+//           A-operand lane order of v_mfma_f32_16x16x16_f16
+void build_mfma_basis(const BasisTable &bt, std::vector<uint16_t> &ops);
+void build_mfma_inverse(const ProjTable &pt, std::vector<uint16_t> &ops);
 
 }  // namespace plan

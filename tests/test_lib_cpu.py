@@ -75,13 +75,24 @@ def test_config_defaults_and_workspace(pl):
 
 @pytest.mark.parametrize("over", [dict(max_N=0), dict(max_N=5000), dict(T_set=[8]), dict(M_set=[40]),
                                   dict(upper_iters=0), dict(gamma=0.0), dict(y_lb=3.0, y_ub=-3.0),
-                                  dict(frac_ces=0.01, frac_es=0.05), dict(precision=7)])
+                                  dict(frac_ces=0.01, frac_es=0.05), dict(precision=7), dict(precision=2),
+                                  dict(precision=1, T_set=[50, 200])])
 def test_invalid_config_rejected_before_device(pl, over):
     cfg = pl.plan_config_init(**over)
     assert pl.plan_workspace_bytes(cfg) == 0
     with pytest.raises(pl.PlanError) as e:
         pl.plan_create(cfg)
     assert e.value.status == pl.PLAN_E_INVALID
+
+
+def test_fp16_split_config_accepted(pl):
+    """The matrix-core mode adds its FP16 tables to the workspace."""
+    base = pl.plan_workspace_bytes(pl.plan_config_init())
+    mixed = pl.plan_workspace_bytes(pl.plan_config_init(precision=pl.PLAN_PREC_FP16_SPLIT))
+    # per T: 4 ceil(T/4) instants x 224 bytes; per (T, M): 1 KiB (A^-1 halves)
+    tables = sum(4 * ((T + 3) // 4) * 224 for T in (50, 100)) + 2 * 3 * 1024
+    assert mixed - base >= tables
+    assert pl.plan_workspace_bytes(pl.plan_config_init(precision=1, T_set=[128])) > 0
 
 
 def test_elite_sizes_match_oracle(pl, orc):
