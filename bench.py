@@ -19,8 +19,9 @@ scene. Beside the headline (FP32) the line carries
             and its position difference to the FP32 lower level on 256
             inputs (the error of both against the FP64 oracle is stated
             by the parity tests),
-  served    the served stream of 256 requests (saturated rate, then Poisson
-            arrivals at 0.7 of it; p50/p99 latency) in both precisions,
+  served    the served stream of 256 requests in both precisions: each
+            one's saturated rate, then the same Poisson arrivals at 0.5, 0.7
+            and 0.9 of the FP32 saturated rate (p50/p99 latency),
   scale     1024 concurrent requests of N = 4096, T = 100, M = 20 in both
             precisions.
 """
@@ -88,7 +89,19 @@ def served_stream(pl, workload, n_req: int, seed: int = 4):
 
 def run_served(pl, h, reqs, arrivals):
     """Submit each request at its arrival time (seconds after start), drive
-    plan_progress until all finish; returns (latencies, makespan)."""
+    plan_progress until all finish; returns (latencies, makespan). Python's
+    cyclic garbage collector is paused meanwhile (a collection of the
+    interpreter's heap takes tens of ms and would land in the timings)."""
+    import gc
+    gc.collect()
+    gc.disable()
+    try:
+        return _run_served(pl, h, reqs, arrivals)
+    finally:
+        gc.enable()
+
+
+def _run_served(pl, h, reqs, arrivals):
     import numpy as np
     order = np.argsort(arrivals, kind="stable")
     pending = {}
@@ -113,28 +126,41 @@ def run_served(pl, h, reqs, arrivals):
     return lat, time.perf_counter() - t0
 
 
-def served_bench(pl, workload, torch, precision=0, n_req=256, slots=64):
-    """Saturated rate, then Poisson arrivals at 0.7 of it: p50/p99 latency."""
+def served_bench(pl, workload, torch, n_req=256, slots=64, loads=(0.5, 0.7, 0.9)):
+    """The served stream in both precisions: the saturated rate of each (all
+    requests at t = 0), then the same Poisson arrival sequences for both at
+    the given fractions of the FP32 saturated rate; p50/p99 latency."""
     import numpy as np
     L, K = 5, 20
-    cfg = pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=K, upper_iters=L, max_N=2048,
-                              max_requests=slots, precision=precision)
-    ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
-    h = pl.plan_create(cfg, workspace=ws, stream=torch.cuda.current_stream().cuda_stream)
     reqs = served_stream(pl, workload, n_req)
     solves = sum(r.N for r in reqs) * L
-    run_served(pl, h, reqs[:8], np.zeros(8))  # warm-up
-    _, sat_span = run_served(pl, h, reqs, np.zeros(n_req))
-    rate_sat = n_req / sat_span
-    lam = 0.7 * rate_sat
-    arrivals = np.cumsum(np.random.default_rng(11).exponential(1.0 / lam, n_req))
-    lat, span = run_served(pl, h, reqs, arrivals)
-    return {"requests": n_req, "slots": slots, "L": L, "K": K,
-            "mix": "N in {256,512,1000,2048}, M in {4,10,20}, T in {50,100}",
-            "saturated_requests_per_s": rate_sat, "saturated_solves_per_s": solves / sat_span,
-            "arrival_rate_per_s": lam, "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
-            "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)), "solves_per_s": solves / span,
-            "makespan_s": span}
+    handles, out = {}, {}
+    for name, prec in (("f32", 0), ("fp16_split", 1)):
+        cfg = pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=K, upper_iters=L, max_N=2048,
+                                  max_requests=slots, precision=prec)
+        ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
+        h = pl.plan_create(cfg, workspace=ws, stream=torch.cuda.current_stream().cuda_stream)
+        run_served(pl, h, reqs[:16], np.zeros(16))  # warm-up
+        _, sat_span = run_served(pl, h, reqs, np.zeros(n_req))
+        handles[name] = h
+        out[name] = {"saturated_requests_per_s": n_req / sat_span, "saturated_solves_per_s": solves / sat_span,
+                     "poisson": {}}
+    lam_ref = out["f32"]["saturated_requests_per_s"]
+    for frac in loads:
+        arrivals = np.cumsum(np.random.default_rng(11).exponential(1.0 / (frac * lam_ref), n_req))
+        for name, h in handles.items():
+            lat, span = run_served(pl, h, reqs, arrivals)
+            out[name]["poisson"][f"{frac:.1f}"] = {
+                "arrival_rate_per_s": frac * lam_ref, "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)), "solves_per_s": solves / span}
+    for name in out:
+        ref = out[name]["poisson"]["0.7"] if "0.7" in out[name]["poisson"] else {}
+        out[name].update({"p50_latency_ms": ref.get("p50_latency_ms"), "p99_latency_ms": ref.get("p99_latency_ms")})
+    out["stream"] = {"requests": n_req, "slots": slots, "L": L, "K": K,
+                     "mix": "N in {256,512,1000,2048}, M in {4,10,20}, T in {50,100}",
+                     "loads": "Poisson arrivals at the given fractions of the FP32 saturated request rate; "
+                              "p50/p99 above at 0.7"}
+    return out
 
 
 def scale_bench(pl, workload, torch, precision=0, n_req=1024, N=4096, T=100, M=20):
@@ -286,10 +312,8 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
     if not args.no_served:
-        out["served"] = {}
-        for name, prec in (("f32", 0), ("fp16_split", 1)):
-            print(f"[bench] served stream {name}", file=sys.stderr, flush=True)
-            out["served"][name] = served_bench(pl, workload, torch, prec)
+        print("[bench] served stream, both precisions", file=sys.stderr, flush=True)
+        out["served"] = served_bench(pl, workload, torch)
     if not args.no_scale:
         out["scale"] = {}
         for name, prec in (("f32", 0), ("fp16_split", 1)):

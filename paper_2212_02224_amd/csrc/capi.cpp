@@ -69,12 +69,12 @@ int mfma_waves(int T) { return (T + 4 * kMfmaTpw - 1) / (4 * kMfmaTpw); }
 // Dynamic LDS of the lower kernels: two neighbours per float4 and instant;
 // the matrix-core kernel adds its basis table (kEvInstHalfs halves per
 // instant of the padded horizon), the fixed trajectory part (two float4 per
-// instant) and the double-buffered partial sums.
+// instant), the partial sums of its waves and their total.
 size_t lds_bytes(int M, int T, bool mfma) {
   size_t b = (size_t)((M + 1) / 2) * T * sizeof(float4);
   if (mfma) {
     const size_t NI = 4 * (size_t)((T + 3) / 4);
-    b += NI * kEvInstHalfs * 2 + (2 * NI + (size_t)2 * mfma_waves(T) * kWave) * sizeof(float4);
+    b += NI * kEvInstHalfs * 2 + (2 * NI + (size_t)(mfma_waves(T) + 1) * kWave) * sizeof(float4);
   }
   return b;
 }

@@ -292,12 +292,21 @@ __device__ __forceinline__ State6 eval_traj(const Lane &L, const float (&zs)[15]
   return s;
 }
 
-// Neighbour corrections at this lane's instant, in ellipse-scaled units:
+// Neighbour corrections at one instant, in ellipse-scaled units:
 // sum_i (max(1, 1/r_i) - 1) (dx_i / a, dy_i / b), r_i the normalised
 // distance (closed form of step split_alpha_o with the clip of clip_d_o);
 // at the centre (r = 0) alpha = 0 and d = 1 give (1, 0). The table holds two
 // neighbours per float4 entry, pre-divided by (a, b); loads run one entry
-// ahead of the arithmetic.
+// ahead of the arithmetic, and the distance tests of an entry are formed
+// before the (rarely taken) near branches.
+__device__ __forceinline__ void near_update(float q, float dx, float dy, float &ax, float &ay) {
+  if (q < 1.f) {
+    const float f = (q > 0.f ? frsq(q) : 1.f) - 1.f;
+    ax = fmaf(f, dx, ax + (q > 0.f ? 0.f : 1.f));
+    ay = fmaf(f, dy, ay);
+  }
+}
+
 __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, int npair, int T, int t,
                                                float xs, float ys, float &ax, float &ay) {
   ax = 0.f;
@@ -305,17 +314,11 @@ __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, i
   if (npair == 0) return;
   float4 cur = obs[t];
   for (int c = 0; c < npair; ++c) {
-    float4 nxt = obs[(c + 1 < npair ? c + 1 : c) * T + t];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const float dx = xs - (h ? cur.z : cur.x), dy = ys - (h ? cur.w : cur.y);
-      const float q = fmaf(dx, dx, dy * dy);
-      if (q < 1.f) {
-        const float f = (q > 0.f ? frsq(q) : 1.f) - 1.f;
-        ax = fmaf(f, dx, ax + (q > 0.f ? 0.f : 1.f));
-        ay = fmaf(f, dy, ay);
-      }
-    }
+    const float4 nxt = obs[(c + 1 < npair ? c + 1 : c) * T + t];
+    const float dx0 = xs - cur.x, dy0 = ys - cur.y, dx1 = xs - cur.z, dy1 = ys - cur.w;
+    const float q0 = fmaf(dx0, dx0, dy0 * dy0), q1 = fmaf(dx1, dx1, dy1 * dy1);
+    near_update(q0, dx0, dy0, ax, ay);
+    near_update(q1, dx1, dy1, ax, ay);
     cur = nxt;
   }
 }
@@ -328,12 +331,11 @@ struct Corr {
 };
 
 // Steps split_alpha_o .. update_slack of Alg. 2 at one instant, from the
-// trajectory state s there. da_prev carries d_a of the previous step. All
-// differences are zero where tv is false.
-__device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const float4 *__restrict__ obs,
-                                           int npair, int T, int t, bool tv, float &da_prev) {
-  float ax, ay;
-  neighbour_pass(obs, npair, T, t, s.x * S.ia, s.y * S.ib, ax, ay);
+// trajectory state s there and the neighbour sums (ax, ay) of
+// neighbour_pass. da_prev carries d_a of the previous step. All differences
+// are zero where tv is false.
+__device__ __forceinline__ Corr targets_from(const State6 &s, const Scal &S, float ax, float ay, bool tv,
+                                             float &da_prev) {
   float dox = ax * S.ell_a, doy = ay * S.ell_b;
   // velocity / acceleration polar variables and their clips
   const float v2 = fmaf(s.xd, s.xd, s.yd * s.yd);
@@ -369,6 +371,13 @@ __device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const
   c.dox = dox;
   if (!tv) c.dox = c.wy = c.dvx = c.dvy = c.dax = c.day = 0.f;
   return c;
+}
+
+__device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const float4 *__restrict__ obs,
+                                           int npair, int T, int t, bool tv, float &da_prev) {
+  float ax, ay;
+  neighbour_pass(obs, npair, T, t, s.x * S.ia, s.y * S.ib, ax, ay);
+  return targets_from(s, S, ax, ay, tv, da_prev);
 }
 
 // One target pass at this lane's instant, accumulated into the lane's share
@@ -745,8 +754,8 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 // ---------------------------------------------------------------------------
 // Lower level on the matrix cores (FP16 high/low split, FP32 accumulation).
 //
-// A workgroup serves 16 samples of one request with ceil(T / 16) waves; wave
-// w owns the instant tiles 4w .. 4w + 3 (4 instants each). Lane l of every
+// A workgroup serves 16 samples of one request with ceil(T / 8) waves; wave
+// w owns the instant tiles 2w, 2w + 1 (4 instants each). Lane l of every
 // wave belongs to sample n = l % 16 and to lane group g = l / 16, which holds
 //   * free coefficients 4g .. 4g + 3 of its sample (state z, z_bar, lambda),
 //   * at each tile, position / velocity / acceleration of both axes at
@@ -759,7 +768,8 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 //               instant in one operand; 3 per tile)
 // and once per iteration the xi-update dz = A^-1 rhs (3 products). The basis
 // table is staged in LDS per workgroup; the sums N^T g of the waves meet in
-// LDS and every wave applies the same update. Everything between the
+// LDS (each of the 256 values summed over the waves by one thread, in wave
+// order) and every wave applies the same update. Everything between the
 // products is the FP32 code of the VALU kernel.
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
@@ -856,7 +866,7 @@ __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int l, b
 
 // Dynamic LDS of the matrix-core kernel: basis table [4 NT][kEvInstHalfs],
 // neighbours [pair][T] (float4), fixed trajectory part [4 NT][2] (float4),
-// partial sums [2][waves][64] (float4).
+// partial sums [waves][64] (float4), their total [64] (float4).
 __host__ __device__ inline int mfma_waves(int T) { return (T + 4 * kMfmaTpw - 1) / (4 * kMfmaTpw); }
 
 __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(LowerArgs A, MethodParams P) {
@@ -883,6 +893,7 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
   float4 *s_obs = s_dyn + tab_f4;
   float4 *s_fix = s_obs + npair * T;
   float4 *s_part = s_fix + 8 * NT;
+  float4 *s_G = s_part + NWv * kWave;
 
   {
     const float4 *src = reinterpret_cast<const float4 *>(A.mops + A.mops_off[D.t_idx]);
@@ -983,9 +994,16 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
   };
 
   float da[kMfmaTpw];
-  int buf = 0;
   // One target pass over this wave's tiles at the current z (first: the
   // initial d_a from the same evaluation); returns N^T g of the workgroup.
+  auto accumulate = [&](int tile, const Corr &c, f4 acc) -> f4 {
+    h8 dh, dl;
+    split_corr(c, dh, dl);
+    const h8 ch = ac_op(tile, 0), cl = ac_op(tile, 1);
+    acc = mma32(ch, dh, acc);
+    acc = mma32(ch, dl, acc);
+    return mma32(cl, dh, acc);
+  };
   auto pass = [&](bool first) -> f4 {
     h4 bx, by;
     coef_operands(z, bx, by);
@@ -995,27 +1013,25 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
       const int tile = wave * kMfmaTpw + i;
       if (tile < NT) {
         const int t = 4 * tile + g;
-        const bool tv = active && t < T;
         const State6 st = evaluate(tile, bx, by);
         if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-        const Corr c = targets_at(st, S, s_obs, npair, T, t < T ? t : T - 1, tv, da[i]);
-        h8 dh, dl;
-        split_corr(c, dh, dl);
-        const h8 ch = ac_op(tile, 0), cl = ac_op(tile, 1);
-        acc = mma32(ch, dh, acc);
-        acc = mma32(ch, dl, acc);
-        acc = mma32(cl, dh, acc);
+        acc = accumulate(tile, targets_at(st, S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, da[i]), acc);
       }
     }
-    s_part[(buf * NWv + wave) * kWave + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    s_part[wave * kWave + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
     __syncthreads();
-    f4 G = {0.f, 0.f, 0.f, 0.f};
-    for (int w = 0; w < NWv; ++w) {
-      const float4 q = s_part[(buf * NWv + w) * kWave + lane];
-      G += f4{q.x, q.y, q.z, q.w};
+    {
+      const float *pp = reinterpret_cast<const float *>(s_part);
+      float *gg = reinterpret_cast<float *>(s_G);
+      for (int e = threadIdx.x; e < 4 * kWave; e += blockDim.x) {
+        float sum = 0.f;
+        for (int w = 0; w < NWv; ++w) sum += pp[w * 4 * kWave + e];
+        gg[e] = sum;
+      }
     }
-    buf ^= 1;
-    return G;
+    __syncthreads();
+    const float4 q = s_G[lane];
+    return f4{q.x, q.y, q.z, q.w};
   };
 
   f4 G = pass(true);
@@ -1133,68 +1149,104 @@ __device__ uint32_t block_exscan(uint32_t x, uint32_t *s_tmp, uint32_t *total) {
 
 // Select the `want` smallest (key, position) pairs of s_key[0..cnt) (ties to
 // the lower position) and write their positions, in increasing order, to
-// s_out[0..want). Radix select on the 32-bit keys, 8 bits per pass, then one
-// scan ranks the members equal to the threshold by position. cnt <= 4096.
-__device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t *s_out,
-                             uint32_t *s_hist, uint32_t *s_tmp) {
-  const int tid = threadIdx.x;
-  uint32_t prefix = 0, mask = 0;
+// s_out[0..want). If at least `want` keys equal the smallest key, they are
+// the first `want` of those. Otherwise a radix select on the 32-bit keys,
+// 8 bits per pass, narrows a prefix until the keys matching it are exactly
+// the ones still wanted or all bits are fixed; one scan then ranks the
+// members equal to the prefix by position. cnt <= PLAN_MAX_N.
+__device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t *s_out, uint32_t *s_hist,
+                             uint32_t *s_tmp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // smallest key and its multiplicity
+  uint32_t kmin = 0xFFFFFFFFu;
+  for (int i = tid; i < cnt; i += kSelBlock) kmin = min(kmin, s_key[i]);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
+  if (lane == 0) s_tmp[wave] = kmin;
+  __syncthreads();
+  kmin = s_tmp[0];
+  for (int w = 1; w < kSelBlock / kWave; ++w) kmin = min(kmin, s_tmp[w]);
+  uint32_t nmin = 0;
+  for (int i = tid; i < cnt; i += kSelBlock) nmin += s_key[i] == kmin;
+  uint32_t tot_min;
+  block_exscan(nmin, s_tmp + 8, &tot_min);
+
+  uint32_t prefix = kmin, mask = 0xFFFFFFFFu;
   int remaining = want;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    for (int i = tid; i < 256; i += kSelBlock) s_hist[i] = 0;
-    __syncthreads();
-    for (int i = tid; i < cnt; i += kSelBlock) {
-      const uint32_t k = s_key[i];
-      if ((k & mask) == prefix) atomicAdd(&s_hist[(k >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (tid < 64) {
-      uint32_t h[4], sum = 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        h[u] = s_hist[4 * tid + u];
-        sum += h[u];
-      }
-      uint32_t incl = sum;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = __shfl_up(incl, d, 64);
-        if (tid >= d) incl += y;
-      }
-      uint32_t before = incl - sum;
-      for (int u = 0; u < 4; ++u) {
-        if (before < (uint32_t)remaining && (uint32_t)remaining <= before + h[u]) {
-          s_tmp[16] = 4 * tid + u;
-          s_tmp[17] = before;
+  if (tot_min < (uint32_t)want) {
+    prefix = 0;
+    mask = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      for (int i = tid; i < 256; i += kSelBlock) s_hist[i] = 0;
+      __syncthreads();
+      for (int i0 = 0; i0 < cnt; i0 += kSelBlock) {
+        const int i = i0 + tid;
+        const uint32_t k = i < cnt ? s_key[i] : 0u;
+        const bool match = i < cnt && (k & mask) == prefix;
+        const uint32_t digit = (k >> shift) & 255u;
+        // one atomic for the lanes sharing the first matching lane's digit
+        // (skewed keys would otherwise serialise on one bin)
+        const uint64_t act = __ballot(match);
+        if (act) {
+          const int leader = __builtin_ctzll(act);
+          const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)digit, leader);
+          const uint64_t same = __ballot(match && digit == dl);
+          if (lane == leader) atomicAdd(&s_hist[dl], (uint32_t)__popcll(same));
+          if (match && digit != dl) atomicAdd(&s_hist[digit], 1u);
         }
-        before += h[u];
       }
+      __syncthreads();
+      if (tid < 64) {
+        uint32_t h[4], sum = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          h[u] = s_hist[4 * tid + u];
+          sum += h[u];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          uint32_t y = __shfl_up(incl, d, 64);
+          if (tid >= d) incl += y;
+        }
+        uint32_t before = incl - sum;
+        for (int u = 0; u < 4; ++u) {
+          if (before < (uint32_t)remaining && (uint32_t)remaining <= before + h[u]) {
+            s_tmp[16] = 4 * tid + u;
+            s_tmp[17] = before;
+            s_tmp[18] = h[u];
+          }
+          before += h[u];
+        }
+      }
+      __syncthreads();
+      const uint32_t b = s_tmp[16];
+      remaining -= (int)s_tmp[17];
+      prefix |= b << shift;
+      mask |= 0xFFu << shift;
+      const bool exact = s_tmp[18] == (uint32_t)remaining;
+      __syncthreads();
+      if (exact) break;  // every key matching the prefix is selected
     }
-    __syncthreads();
-    const uint32_t b = s_tmp[16];
-    remaining -= (int)s_tmp[17];
-    prefix |= b << shift;
-    mask |= 0xFFu << shift;
-    __syncthreads();
   }
   // Positions are split into contiguous chunks, one per thread, so both scans
   // run in position order.
   const int chunk = (cnt + kSelBlock - 1) / kSelBlock;
   const int p0 = tid * chunk, p1 = min(cnt, p0 + chunk);
   uint32_t eq = 0;
-  for (int i = p0; i < p1; ++i) eq += s_key[i] == prefix;
+  for (int i = p0; i < p1; ++i) eq += (s_key[i] & mask) == prefix;
   uint32_t tot;
   uint32_t eq_before = block_exscan(eq, s_tmp, &tot);
   uint32_t sel = 0;
   for (int i = p0; i < p1; ++i) {
-    const uint32_t k = s_key[i];
+    const uint32_t k = s_key[i] & mask;
     if (k < prefix) ++sel;
     else if (k == prefix) sel += (eq_before++ < (uint32_t)remaining);
   }
   eq_before -= eq;
   uint32_t pos = block_exscan(sel, s_tmp, &tot);
   for (int i = p0; i < p1; ++i) {
-    const uint32_t k = s_key[i];
+    const uint32_t k = s_key[i] & mask;
     bool take = k < prefix;
     if (k == prefix) take = eq_before++ < (uint32_t)remaining;
     if (take) s_out[pos++] = (uint32_t)i;
@@ -1203,17 +1255,19 @@ __device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t 
 }
 
 __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, MethodParams P) {
-  __shared__ uint32_t s_key[PLAN_MAX_N];
+  __shared__ uint32_t s_key[PLAN_MAX_N];  // residual keys
+  __shared__ float s_c[PLAN_MAX_N];       // c_u + r
   __shared__ uint32_t s_ces[kMaxCes];
   __shared__ uint32_t s_key2[kMaxCes];
   __shared__ uint32_t s_es[kMaxCes];
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_tmp[32];
   __shared__ double s_w[kMaxEs];
-  __shared__ double s_p[kMaxEs][8];
+  __shared__ float s_p[kMaxEs][8];
   __shared__ double s_mu[8], s_mun[8], s_sig[64];
+  __shared__ double s_part[4][64 + 8];
   __shared__ double s_sum;
-  __shared__ unsigned long long s_best;
+  __shared__ unsigned long long s_best[kSelBlock / kWave];
 
   const int slot = A.slots[blockIdx.x];
   ReqDesc &D = A.desc[slot];
@@ -1227,6 +1281,13 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   const float *p = A.p + base * 8;
   const bool last = (l == P.L - 1);
 
+  // Residual keys and costs c_u + r of all samples into LDS.
+#pragma unroll 4
+  for (int i = tid; i < N; i += kSelBlock) {
+    const float rr = r[i], cc = cu[i];
+    s_key[i] = order_key(rr);
+    s_c[i] = cc + rr;
+  }
   // Distribution before this update: the prior at iteration 0.
   if (l == 0) {
     if (tid == 0) {
@@ -1247,54 +1308,69 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       R.status = ok ? 0 : PLAN_E_INVALID;
       R.iterations = 0;
     }
-  } else if (tid < 72) {
-    if (tid < 8) s_mu[tid] = Sd.mu[tid];
-    else s_sig[tid - 8] = Sd.sigma[tid - 8];
+  } else {
+    for (int i = tid; i < 72; i += kSelBlock) {
+      if (i < 8) s_mu[i] = Sd.mu[i];
+      else s_sig[i - 8] = Sd.sigma[i - 8];
+    }
   }
-  if (tid == 0) s_best = ~0ull;
   __syncthreads();
   if (R.status != 0) return;
 
   // ConstraintEliteSet: the n smallest (r_j, j).
-  for (int i = tid; i < N; i += kSelBlock) s_key[i] = order_key(r[i]);
-  __syncthreads();
   block_select(s_key, N, n, s_ces, s_hist, s_tmp);
   // EliteSet: the q smallest (c_u + r, j) over the ConstraintEliteSet, whose
   // members are listed in increasing sample index.
   for (int i = tid; i < n; i += kSelBlock) {
     const uint32_t j = s_ces[i];
-    s_key2[i] = order_key(cu[j] + r[j]);
+    s_key2[i] = order_key(s_c[j]);
     if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)j;
   }
   __syncthreads();
   block_select(s_key2, n, q, s_es, s_hist, s_tmp);
-  for (int i = tid; i < q; i += kSelBlock) {
-    const uint32_t pos = s_es[i];
-    atomicMin(&s_best, ((unsigned long long)s_key2[pos] << 32) | s_ces[pos]);
+  // Lowest cost of the EliteSet (ties: lower index): the set is listed in
+  // increasing index, so the first minimum of its keys.
+  {
+    unsigned long long best = ~0ull;
+    for (int i = tid; i < q; i += kSelBlock) {
+      const uint32_t pos = s_es[i];
+      best = min(best, ((unsigned long long)s_key2[pos] << 32) | s_ces[pos]);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const unsigned long long o = __shfl_xor(best, d, 64);
+      best = min(best, o);
+    }
+    if ((tid & 63) == 0) s_best[tid >> 6] = best;
   }
   __syncthreads();
-  const uint32_t jbest = (uint32_t)(s_best & 0xFFFFFFFFull);
-
-  // Weights s_j = exp(-(c_j - c_min) / gamma) and the elite rows, in FP64.
-  const double cmin = (double)(cu[jbest] + r[jbest]);
-  for (int i = tid; i < q; i += kSelBlock) {
-    const uint32_t j = s_ces[s_es[i]];
-    s_w[i] = exp(-((double)(cu[j] + r[j]) - cmin) / P.gamma);
-    if (A.tr_es) A.tr_es[((size_t)slot * P.L + l) * A.max_es + i] = (int32_t)j;
+  uint32_t jbest;
+  {
+    unsigned long long best = s_best[0];
+    for (int w = 1; w < kSelBlock / kWave; ++w) best = min(best, s_best[w]);
+    jbest = (uint32_t)(best & 0xFFFFFFFFull);
   }
+
+  // Elite rows (issued first: the loads overlap the weights) and the weights
+  // s_j = exp(-(c_j - c_min) / gamma), in FP64.
   for (int e = tid; e < q * 8; e += kSelBlock) {
     const int i = e >> 3, a = e & 7;
-    s_p[i][a] = (double)p[(size_t)s_ces[s_es[i]] * 8 + a];
+    s_p[i][a] = p[(size_t)s_ces[s_es[i]] * 8 + a];
+  }
+  const double cmin = (double)s_c[jbest];
+  for (int i = tid; i < q; i += kSelBlock) {
+    const uint32_t j = s_ces[s_es[i]];
+    s_w[i] = exp(-((double)s_c[j] - cmin) / P.gamma);
+    if (A.tr_es) A.tr_es[((size_t)slot * P.L + l) * A.max_es + i] = (int32_t)j;
   }
   __syncthreads();
-  // eq. mean_update: 64 threads, 8 partial sums per component in a fixed
+  // eq. mean_update: 32 threads, 4 partial sums per component in a fixed
   // order, then combined.
-  __shared__ double s_part[8][64 + 8];
-  if (tid < 64) {
+  if (tid < 32) {
     const int a = tid & 7, part = tid >> 3;
     double m = 0.0, ssum = 0.0;
-    for (int i = part; i < q; i += 8) {
-      m += s_w[i] * s_p[i][a];
+    for (int i = part; i < q; i += 4) {
+      m += s_w[i] * (double)s_p[i][a];
       ssum += s_w[i];
     }
     s_part[part][a] = m;
@@ -1303,7 +1379,7 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   __syncthreads();
   if (tid < 8) {
     double m = 0.0, ssum = 0.0;
-    for (int part = 0; part < 8; ++part) {
+    for (int part = 0; part < 4; ++part) {
       m += s_part[part][tid];
       ssum += s_part[part][64 + tid];
     }
@@ -1311,20 +1387,13 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
     if (tid == 0) s_sum = ssum;
   }
   __syncthreads();
-  // eq. cov_update around the new mean: 512 threads, 8 partial sums per
-  // entry (products commute, so the matrix comes out exactly symmetric).
-  if (tid < 512) {
-    const int e = tid & 63, part = tid >> 6;
-    const int a = e >> 3, b = e & 7;
+  // eq. cov_update around the new mean: one thread per entry, elites in
+  // order (products commute, so the matrix comes out exactly symmetric).
+  if (tid < 64) {
+    const int a = tid >> 3, b = tid & 7;
     const double ma = s_mun[a], mb = s_mun[b];
     double c = 0.0;
-    for (int i = part; i < q; i += 8) c += s_w[i] * (s_p[i][a] - ma) * (s_p[i][b] - mb);
-    s_part[part][e] = c;
-  }
-  __syncthreads();
-  if (tid < 64) {
-    double c = 0.0;
-    for (int part = 0; part < 8; ++part) c += s_part[part][tid];
+    for (int i = 0; i < q; ++i) c += s_w[i] * ((double)s_p[i][a] - ma) * ((double)s_p[i][b] - mb);
     s_sig[tid] = (1.0 - P.eta) * s_sig[tid] + P.eta * c / s_sum;
   }
   __syncthreads();
@@ -1392,12 +1461,6 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   }
 }
 
-}  // namespace plan
-
-// Launch wrappers (C++ linkage, used by the engine).
-namespace plan {
-// With start/stop events the dispatch itself records them (no separate
-// marker packets between kernels).
 hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0)

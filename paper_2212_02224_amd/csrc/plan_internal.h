@@ -11,7 +11,7 @@ namespace plan {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // lower kernel: 4 waves
-constexpr int kSelBlock = 1024;      // selection / update kernel
+constexpr int kSelBlock = 256;       // selection / update kernel (4 waves)
 constexpr int kZ = 16;               // free coefficients (8 x + 7 y) padded
 constexpr int kBasisCols = 37;       // columns of the per-T basis table
 constexpr int kStep1Floats = 16 * 8 + 16 * 4;
@@ -19,8 +19,8 @@ constexpr int kProjFloats = 16 * 16 + 16;
 constexpr int kMaxCes = 1024;        // LDS bound of the ConstraintEliteSet
 constexpr int kMaxEs = 256;          // LDS bound of the EliteSet
 // Matrix-core (FP16 high/low) lower level.
-constexpr int kMfmaTpw = 4;          // instant tiles (4 instants each) per wave
-constexpr int kMfmaMaxWaves = 8;     // waves per workgroup, so T <= 128
+constexpr int kMfmaTpw = 2;          // instant tiles (4 instants each) per wave
+constexpr int kMfmaMaxWaves = 16;    // waves per workgroup, so T <= 128
 constexpr int kMfmaMaxT = 4 * kMfmaTpw * kMfmaMaxWaves;
 constexpr int kMfmaSamples = 16;     // samples per workgroup (the MFMA N dimension)
 constexpr double kAinvScale = 256.0; // A^-1 is stored times this (exact power of two)
