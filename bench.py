@@ -11,9 +11,9 @@ upper iterations) with its inputs already resident in HBM.
 Metric: lower-level QP solves per second = N * L / plan time.
 
 Prints one JSON line (see the keys below), including the roofline of the
-dominant kernel (lower_kernel, timed with HIP events on the library's stream
-over the timed region) and the FP64 oracle timed on host cores on the same
-scene. Beside the headline (FP32) the line carries
+dominant kernel (lower_kernel, its launches timed with HIP events on the
+library's stream over a second timed region of the same steps) and the FP64
+oracle timed on host cores on a sample of the same scene. Beside the headline (FP32) the line carries
   mixed     the same plan with the lower level on the matrix cores
             (PLAN_PREC_FP16_SPLIT),
             and its position difference to the FP32 lower level on 256
@@ -55,6 +55,23 @@ def lower_flops_per_sample(T: int, M: int, K: int) -> float:
     per_update = 271 + 30
     residual = T * (126 + 9 * M)
     return step1 + K * per_update + K * T * per_pass_instant + residual
+
+
+def profiled_traffic():
+    """HBM bytes per lower_kernel launch of this workload from the committed
+    rocprofv3 summary (FETCH_SIZE and WRITE_SIZE passes, calibrated by a copy
+    of known size), or None if the kernels have changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, "profiles", "lower_kernel_plan-N1000-T100-M10.md")).read()
+        src = open(os.path.join(ROOT, "paper_2212_02224_amd", "csrc", "kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (\d+)\s+kernels\.hip sha256: ([0-9a-f]+)", text)
+    if not m or not hashlib.sha256(src).hexdigest().startswith(m.group(2)):
+        return None
+    return float(m.group(1))
 
 
 def cpu_baseline(scene, c, threads: int):
@@ -208,8 +225,12 @@ def precision_gap(pl, workload, c, n_samples=256):
 
 
 def time_plan(pl, torch, c, scene, precision, steps, warmup):
-    """One staged plan launched warmup + steps times; returns (elapsed s,
-    kernel ms dict, launch counts, result)."""
+    """One staged plan launched warmup + steps times in an uninstrumented
+    timed region (the throughput), then steps times with HIP events recorded
+    by every dispatch (kernel durations; the events cost host time per
+    launch, so this region is not used for the throughput). Returns (elapsed
+    s of the first region, kernel ms dict of the second, launch counts,
+    result)."""
     N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
     cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=1,
                               precision=precision)
@@ -221,13 +242,16 @@ def time_plan(pl, torch, c, scene, precision, steps, warmup):
     for _ in range(warmup):
         pl.plan_launch(h)
     torch.cuda.synchronize()
-    pl.plan_profile(h, True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         pl.plan_launch(h)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    pl.plan_profile(h, True)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        pl.plan_launch(h)
+    torch.cuda.synchronize()
     ms, cnt = pl.plan_profile_read(h)
     pl.plan_profile(h, False)
     res = pl.plan_collect(h)[0]
@@ -290,7 +314,8 @@ def main() -> int:
                    "requests_per_step": 1},
         "roofline": {"bound": "alu", "kernel": "lower_kernel", "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": None, "avg_ms": lower_avg_ms, "flop_per_launch": flop,
+                     "traffic": profiled_traffic(), "traffic_unit": "bytes per launch",
+                     "avg_ms": lower_avg_ms, "flop_per_launch": flop,
                      "launches": cnt["lower"]},
         "kernel_ms_per_step": {k: ms[k] / args.steps for k in ms},
         "plan": {"best_index": res.best_index, "cost_upper": res.cost_upper, "residual": res.residual},
