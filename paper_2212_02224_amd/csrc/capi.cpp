@@ -29,7 +29,7 @@
 namespace plan {
 hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int waves, size_t lds,
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, int T, size_t lds,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1);
@@ -63,18 +63,15 @@ int64_t budget_rows(const plan_config &c) {
 
 bool mfma_mode(const plan_config &c) { return c.precision == PLAN_PREC_FP16_SPLIT; }
 
-// Waves per workgroup of the matrix-core kernel: 4 instant tiles per wave.
-int mfma_waves(int T) { return (T + 4 * kMfmaTpw - 1) / (4 * kMfmaTpw); }
-
 // Dynamic LDS of the lower kernels: two neighbours per float4 and instant;
 // the matrix-core kernel adds its basis table (kEvInstHalfs halves per
 // instant of the padded horizon), the fixed trajectory part (two float4 per
-// instant), the partial sums of its waves and their total.
+// instant), the N^T g sums of its tile pairs and their total.
 size_t lds_bytes(int M, int T, bool mfma) {
   size_t b = (size_t)((M + 1) / 2) * T * sizeof(float4);
   if (mfma) {
-    const size_t NI = 4 * (size_t)((T + 3) / 4);
-    b += NI * kEvInstHalfs * 2 + (2 * NI + (size_t)(mfma_waves(T) + 1) * kWave) * sizeof(float4);
+    const size_t NT = (size_t)((T + 3) / 4), NI = 4 * NT;
+    b += NI * kEvInstHalfs * 2 + (2 * NI + ((NT + 1) / 2 + 1) * kWave) * sizeof(float4);
   }
   return b;
 }
@@ -92,7 +89,7 @@ int blocks_for(int N, int T, bool mfma) {
 struct LaunchSet {
   int n_act = 0, ngroups = 0;
   struct Group {
-    int act_off = 0, n = 0, nblocks = 0, waves = 0;
+    int act_off = 0, n = 0, nblocks = 0, T = 0;
     size_t lds = 0;
   } grp[4];
 };
@@ -213,6 +210,7 @@ struct plan_handle {
   std::string err;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int n_cu = 256;  // compute units of the device
   bool own_mem = false;
   DevBuf mem;
   Layout lay;
@@ -501,7 +499,7 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
     gr.n = pos - gr.act_off;
     gr.nblocks = blocks;
     prefix[pos + k] = blocks;
-    gr.waves = mf ? mfma_waves(keys[k]) : kBlock / kWave;
+    gr.T = keys[k];
   }
   ls.ngroups = nkeys;
 }
@@ -527,7 +525,10 @@ plan_status launch_lower_set(plan_handle *h, const LaunchSet &ls, int l_uniform,
     plan_status st = timed(
         h, 0,
         [&](hipEvent_t a, hipEvent_t b) {
-          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, gr.waves, gr.lds, h->stream, a, b)
+          // two tiles per wave while a launch cannot fill every CU with two
+          // workgroups, else four (same arithmetic either way)
+          const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
+          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.T, gr.lds, h->stream, a, b)
                     : launch_lower(la, h->mp, gr.nblocks, gr.lds, h->stream, a, b);
         },
         mf ? "lower_mfma_kernel" : "lower_kernel");
@@ -837,6 +838,12 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->free_rows[0] = h->rows;
   // ---- stream and pinned staging
   hipError_t e = hipSuccess;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      h->n_cu = cus;
+  }
   if (c.stream) {
     h->stream = (hipStream_t)c.stream;
   } else {

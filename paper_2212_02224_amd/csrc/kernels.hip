@@ -754,8 +754,9 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 // ---------------------------------------------------------------------------
 // Lower level on the matrix cores (FP16 high/low split, FP32 accumulation).
 //
-// A workgroup serves 16 samples of one request with ceil(T / 8) waves; wave
-// w owns the instant tiles 2w, 2w + 1 (4 instants each). Lane l of every
+// A workgroup serves 16 samples of one request with ceil(T / (4 TPW)) waves;
+// wave w owns the instant tiles TPW w .. TPW w + TPW - 1 (4 instants each;
+// TPW = 2 or 4, chosen per launch). Lane l of every
 // wave belongs to sample n = l % 16 and to lane group g = l / 16, which holds
 //   * free coefficients 4g .. 4g + 3 of its sample (state z, z_bar, lambda),
 //   * at each tile, position / velocity / acceleration of both axes at
@@ -767,10 +768,14 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 //               (v_mfma_f32_16x16x32_f16: both axes' differences of an
 //               instant in one operand; 3 per tile)
 // and once per iteration the xi-update dz = A^-1 rhs (3 products). The basis
-// table is staged in LDS per workgroup; the sums N^T g of the waves meet in
-// LDS (each of the 256 values summed over the waves by one thread, in wave
-// order) and every wave applies the same update. Everything between the
-// products is the FP32 code of the VALU kernel.
+// table is staged in LDS per workgroup. N^T g is accumulated per pair of
+// tiles (2p, 2p + 1) from zero; the pair sums meet in LDS, each of the 256
+// values is summed over the pairs in pair order by one thread, and every wave
+// applies the same update. The arithmetic is therefore the same for either
+// TPW: small launches use TPW = 2 (more waves, half the serial work per
+// workgroup), large ones TPW = 4 (two workgroups fit a CU and cover each
+// other's barriers). Everything between the products is the FP32 code of the
+// VALU kernel.
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
@@ -865,14 +870,13 @@ __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int l, b
 }
 
 // Dynamic LDS of the matrix-core kernel: basis table [4 NT][kEvInstHalfs],
-// neighbours [pair][T] (float4), fixed trajectory part [4 NT][2] (float4),
-// partial sums [waves][64] (float4), their total [64] (float4).
-__host__ __device__ inline int mfma_waves(int T) { return (T + 4 * kMfmaTpw - 1) / (4 * kMfmaTpw); }
-
-__global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(LowerArgs A, MethodParams P) {
+// neighbours [pair of neighbours][T] (float4), fixed trajectory part [4 NT][2]
+// (float4), N^T g per tile pair [ceil(NT / 2)][64] (float4), total [64].
+template <int TPW>
+__global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_dyn[];
   __shared__ double s_mu[8], s_chol[64];
-  __shared__ float s_rc[kMfmaMaxWaves][kMfmaSamples][2];
+  __shared__ float s_rc[kMfmaMaxPairs][kMfmaSamples][2];
 
   const int2 bi = block_slot(A);
   const int slot = bi.x;
@@ -881,7 +885,7 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
   const int T = D.T, M = D.M, N = D.N;
   const int npair = (M + 1) >> 1;
   const int NT = (T + 3) >> 2;
-  const int NWv = blockDim.x / kWave;  // = mfma_waves(T), checked by the host
+  const int NPr = (NT + 1) >> 1;       // tile pairs
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int n = lane & 15, g = lane >> 4;
   const int j = bi.y * kMfmaSamples + n;
@@ -893,7 +897,7 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
   float4 *s_obs = s_dyn + tab_f4;
   float4 *s_fix = s_obs + npair * T;
   float4 *s_part = s_fix + 8 * NT;
-  float4 *s_G = s_part + NWv * kWave;
+  float4 *s_G = s_part + NPr * kWave;
 
   {
     const float4 *src = reinterpret_cast<const float4 *>(A.mops + A.mops_off[D.t_idx]);
@@ -993,7 +997,7 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
     return st;
   };
 
-  float da[kMfmaTpw];
+  float da[TPW];
   // One target pass over this wave's tiles at the current z (first: the
   // initial d_a from the same evaluation); returns N^T g of the workgroup.
   auto accumulate = [&](int tile, const Corr &c, f4 acc) -> f4 {
@@ -1007,25 +1011,38 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
   auto pass = [&](bool first) -> f4 {
     h4 bx, by;
     coef_operands(z, bx, by);
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < kMfmaTpw; ++i) {
-      const int tile = wave * kMfmaTpw + i;
-      if (tile < NT) {
-        const int t = 4 * tile + g;
-        const State6 st = evaluate(tile, bx, by);
-        if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-        acc = accumulate(tile, targets_at(st, S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, da[i]), acc);
+    for (int pr = 0; pr < TPW / 2; ++pr) {
+      const int pair = wave * (TPW / 2) + pr;
+      if (2 * pair < NT) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = 2 * pr + h, tile = 2 * pair + h;
+          if (tile < NT) {
+            const int t = 4 * tile + g;
+            const State6 st = evaluate(tile, bx, by);
+            if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
+            acc = accumulate(tile, targets_at(st, S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, da[i]),
+                             acc);
+          }
+        }
+        s_part[pair * kWave + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
     }
-    s_part[wave * kWave + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
     __syncthreads();
     {
       const float *pp = reinterpret_cast<const float *>(s_part);
       float *gg = reinterpret_cast<float *>(s_G);
       for (int e = threadIdx.x; e < 4 * kWave; e += blockDim.x) {
+        // all loads first (they are independent), then the sum in pair order
+        float v[kMfmaMaxPairs];
+#pragma unroll
+        for (int w = 0; w < kMfmaMaxPairs; ++w) v[w] = w < NPr ? pp[w * 4 * kWave + e] : 0.f;
         float sum = 0.f;
-        for (int w = 0; w < NWv; ++w) sum += pp[w * 4 * kWave + e];
+#pragma unroll
+        for (int w = 0; w < kMfmaMaxPairs; ++w)
+          if (w < NPr) sum += v[w];
         gg[e] = sum;
       }
     }
@@ -1054,50 +1071,53 @@ __global__ void __launch_bounds__(kWave * kMfmaMaxWaves) lower_mfma_kernel(Lower
     }
   }
 
-  // Residual and upper cost of xi* = xi^K.
-  float rr = 0.f, cc = 0.f;
+  // Residual and upper cost of xi* = xi^K: per tile pair, summed over the
+  // 4 lane groups of a sample, then over the pairs in pair order.
   {
     h4 bx, by;
     coef_operands(z, bx, by);
 #pragma unroll
-    for (int i = 0; i < kMfmaTpw; ++i) {
-      const int tile = wave * kMfmaTpw + i;
-      if (tile < NT) {
-        const int t = 4 * tile + g;
-        float r1, c1;
-        residual_at(evaluate(tile, bx, by), S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, r1, c1);
-        rr += r1;
-        cc += c1;
+    for (int pr = 0; pr < TPW / 2; ++pr) {
+      const int pair = wave * (TPW / 2) + pr;
+      if (2 * pair < NT) {
+        float rr = 0.f, cc = 0.f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int tile = 2 * pair + h;
+          if (tile < NT) {
+            const int t = 4 * tile + g;
+            float r1, c1;
+            residual_at(evaluate(tile, bx, by), S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, r1, c1);
+            rr += r1;
+            cc += c1;
+          }
+        }
+        float a = rr, b = rr;
+        swap32(a, b);
+        rr = a + b;
+        a = rr;
+        b = rr;
+        swap16(a, b);
+        rr = a + b;
+        a = cc;
+        b = cc;
+        swap32(a, b);
+        cc = a + b;
+        a = cc;
+        b = cc;
+        swap16(a, b);
+        cc = a + b;
+        if (g == 0) {
+          s_rc[pair][n][0] = rr;
+          s_rc[pair][n][1] = cc;
+        }
       }
     }
   }
-  // sum over the 4 lane groups of a sample, then over the waves
-  {
-    float a = rr, b = rr;
-    swap32(a, b);
-    rr = a + b;
-    a = rr;
-    b = rr;
-    swap16(a, b);
-    rr = a + b;
-    a = cc;
-    b = cc;
-    swap32(a, b);
-    cc = a + b;
-    a = cc;
-    b = cc;
-    swap16(a, b);
-    cc = a + b;
-  }
-  if (g == 0) {
-    s_rc[wave][n][0] = rr;
-    s_rc[wave][n][1] = cc;
-  }
   __syncthreads();
   if (wave != 0 || !active) return;
-  rr = 0.f;
-  cc = 0.f;
-  for (int w = 0; w < NWv; ++w) {
+  float rr = 0.f, cc = 0.f;
+  for (int w = 0; w < NPr; ++w) {
     rr += s_rc[w][n][0];
     cc += s_rc[w][n][1];
   }
@@ -1469,14 +1489,15 @@ hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, 
     hipLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), lds, st, a, p);
   return hipGetLastError();
 }
-hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int waves, size_t lds,
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, int T, size_t lds,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (waves < 1 || waves > kMfmaMaxWaves) return hipErrorInvalidValue;
+  if ((tpw != 2 && tpw != 4) || T < 1 || T > kMfmaMaxT) return hipErrorInvalidValue;
+  const int waves = (T + 4 * tpw - 1) / (4 * tpw);
+  auto kern = tpw == 2 ? lower_mfma_kernel<2> : lower_mfma_kernel<4>;
   if (ev0 != nullptr)
-    hipExtLaunchKernelGGL(lower_mfma_kernel, dim3(nblocks), dim3(kWave * waves), (uint32_t)lds, st, ev0, ev1, 0,
-                          a, p);
+    hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(kWave * waves), (uint32_t)lds, st, ev0, ev1, 0, a, p);
   else
-    hipLaunchKernelGGL(lower_mfma_kernel, dim3(nblocks), dim3(kWave * waves), lds, st, a, p);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kWave * waves), lds, st, a, p);
   return hipGetLastError();
 }
 

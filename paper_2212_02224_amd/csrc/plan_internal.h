@@ -19,9 +19,8 @@ constexpr int kProjFloats = 16 * 16 + 16;
 constexpr int kMaxCes = 1024;        // LDS bound of the ConstraintEliteSet
 constexpr int kMaxEs = 256;          // LDS bound of the EliteSet
 // Matrix-core (FP16 high/low) lower level.
-constexpr int kMfmaTpw = 2;          // instant tiles (4 instants each) per wave
-constexpr int kMfmaMaxWaves = 16;    // waves per workgroup, so T <= 128
-constexpr int kMfmaMaxT = 4 * kMfmaTpw * kMfmaMaxWaves;
+constexpr int kMfmaMaxT = 128;       // horizon limit of the matrix-core kernel
+constexpr int kMfmaMaxPairs = kMfmaMaxT / 8;  // pairs of 4-instant tiles
 constexpr int kMfmaSamples = 16;     // samples per workgroup (the MFMA N dimension)
 constexpr double kAinvScale = 256.0; // A^-1 is stored times this (exact power of two)
 constexpr float kRhsScale = 1.0f / 16.0f;  // the xi-update right-hand side is split times this

@@ -190,3 +190,24 @@ def test_mixed_served_equals_alone(pl):
         a, b = got[t], ref[i]
         assert a.status == b.status == 0 and a.best_index == b.best_index, i
         assert np.array_equal(a.xi_best, b.xi_best) and np.array_equal(a.mu, b.mu), i
+
+
+def test_mixed_tiles_per_wave_does_not_change_results(pl):
+    """A large launch runs four instant tiles per wave, a small one two; the
+    sums are formed per tile pair in a fixed order, so every request's result
+    is bitwise the same either way (here: alone = two, in a batch of 12k
+    samples = four)."""
+    cfg = pl.plan_config_init(T_set=[100], M_set=[10], proj_iters=10, upper_iters=2, max_N=4096, max_requests=4,
+                              precision=1)
+    h = pl.plan_create(cfg)
+    reqs = []
+    for i, N in enumerate([4096, 4096, 4096, 64]):
+        s = workload.scene(4, 300 + i, 10)
+        reqs.append(pl.Request(N=N, T=100, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
+    big = pl.plan_solve_batch(h, reqs)
+    for i in (0, 3):
+        alone = pl.plan_solve_batch(h, [reqs[i]])[0]
+        assert big[i].status == 0 and alone.status == 0
+        assert alone.best_index == big[i].best_index, i
+        assert np.array_equal(alone.xi_best, big[i].xi_best), i
+        assert np.array_equal(alone.mu, big[i].mu) and np.array_equal(alone.sigma, big[i].sigma), i
