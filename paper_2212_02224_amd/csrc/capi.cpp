@@ -502,6 +502,29 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
     gr.T = keys[k];
   }
   ls.ngroups = nkeys;
+  // A light matrix-core load runs all horizons in one launch shaped for the
+  // longest (waves without a tile pair only join the barriers), so its
+  // groups do not wait for each other; the arithmetic per request is the
+  // same in any launch.
+  int total = 0;
+  for (int k = 0; k < nkeys; ++k) total += ls.grp[k].nblocks;
+  if (mf && nkeys > 1 && total < 2 * h->n_cu) {
+    LaunchSet::Group all;
+    all.act_off = 0;
+    all.n = n;
+    all.T = ls.grp[nkeys - 1].T;
+    int blocks = 0;
+    for (int i = 0; i < n; ++i) {
+      const ReqDesc &d = h->h_desc[act[i]];
+      prefix[i] = blocks;
+      blocks += blocks_for(d.N, d.T, mf);
+      all.lds = std::max(all.lds, lds_bytes(d.M, d.T, mf));
+    }
+    prefix[n] = blocks;
+    all.nblocks = blocks;
+    ls.grp[0] = all;
+    ls.ngroups = 1;
+  }
 }
 
 plan_status upload_launch_set(plan_handle *h, const LaunchSet &ls) {
