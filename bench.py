@@ -194,10 +194,21 @@ def scale_bench(pl, workload, torch, precision=0, n_req=1024, N=4096, T=100, M=2
         s = workload.scene(5, i, M)
         reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
     run_served(pl, h, reqs[:4], np.zeros(4))  # warm-up
+    pl.plan_profile(h, True)
     lat, span = run_served(pl, h, reqs, np.zeros(n_req))
+    ms, cnt = pl.plan_profile_read(h)
+    pl.plan_profile(h, False)
+    # the batched solve's roofline: every upper iteration's lower launches
+    # over all 4.19M resident samples, HIP-event timed
+    flop = n_req * N * lower_flops_per_sample(T, M, K)
+    lower_s = 1e-3 * ms["lower"] / L
+    achieved = flop / lower_s / 1e12
     return {"requests": n_req, "N": N, "T": T, "M": M, "L": L, "K": K, "solves_per_s": n_req * N * L / span,
             "makespan_s": span, "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
-            "p99_latency_ms": 1e3 * float(np.percentile(lat, 99))}
+            "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_ALU_TFLOPS, "lower_ms_per_iteration": 1e3 * lower_s,
+                         "flop_per_iteration": flop}}
 
 
 def precision_gap(pl, workload, c, n_samples=256):

@@ -1134,6 +1134,41 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   }
 }
 
+// Lower Cholesky factor of A + jitter I (8x8, FP64) by lanes 0..7 of a
+// wave, lane i owning row i: column j is finished by lane j (diagonal) and
+// lanes i > j (below it) in parallel. Every lane of the wave must call it;
+// returns false on all lanes if A + jitter I is not positive definite.
+__device__ bool chol8_wave(const double *A, double jitter, double *Lo, int lane) {
+  const int i = lane & 7;
+  double row[8], Lr[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    row[k] = A[i * 8 + k] + (k == i ? jitter : 0.0);
+    Lr[k] = 0.0;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    // row j of L so far, from lane j
+    double Lj[8];
+#pragma unroll
+    for (int k = 0; k < j; ++k) Lj[k] = __shfl(Lr[k], j, 64);
+    double s = row[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= Lr[k] * Lj[k];
+    // lane j: s is the pivot; lanes i > j: s is the numerator of L[i][j]
+    const double piv = __shfl(s, j, 64);
+    ok = ok && piv > 0.0;
+    const double l = ok ? sqrt(piv) : 1.0, il = 1.0 / l;
+    if (i == j) Lr[j] = l;
+    else if (i > j) Lr[j] = s * il;
+  }
+  if (lane < 8)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) Lo[i * 8 + k] = ok ? Lr[k] : 0.0;
+  return ok;
+}
+
 // ---------------------------------------------------------------------------
 // Selection and update: one 1024-thread workgroup per request.
 
@@ -1408,18 +1443,16 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   }
   __syncthreads();
   // eq. cov_update around the new mean: one thread per entry, elites in
-  // order (products commute, so the matrix comes out exactly symmetric).
+  // order. c_ab and c_ba come out bitwise equal (products commute), so the
+  // symmetrised entry 0.5 (new_ab + new_ba) is formed by the same thread.
   if (tid < 64) {
     const int a = tid >> 3, b = tid & 7;
     const double ma = s_mun[a], mb = s_mun[b];
     double c = 0.0;
     for (int i = 0; i < q; ++i) c += s_w[i] * ((double)s_p[i][a] - ma) * ((double)s_p[i][b] - mb);
-    s_sig[tid] = (1.0 - P.eta) * s_sig[tid] + P.eta * c / s_sum;
-  }
-  __syncthreads();
-  if (tid < 64) {
-    const int a = tid >> 3, b = tid & 7;
-    const double sym = 0.5 * (s_sig[a * 8 + b] + s_sig[b * 8 + a]);
+    const double cs = P.eta * c / s_sum;
+    const double nab = (1.0 - P.eta) * s_sig[a * 8 + b] + cs, nba = (1.0 - P.eta) * s_sig[b * 8 + a] + cs;
+    const double sym = 0.5 * (nab + nba);
     s_part[0][tid] = sym;
     Sd.sigma[tid] = sym;
     if (A.tr_sigma) A.tr_sigma[((size_t)slot * P.L + l) * 64 + tid] = sym;
@@ -1434,13 +1467,13 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    double sym[64];
-    for (int i = 0; i < 64; ++i) sym[i] = s_part[0][i];
-    const bool ok = chol8(sym, P.cov_jitter, Sd.chol);
-    R.iterations = l + 1;
-    if (!ok) R.status = PLAN_E_INVALID;
-    if (A.l_uniform < 0) D.cur_iter = l + 1;
+  if (tid < 64) {
+    const bool ok = chol8_wave(&s_part[0][0], P.cov_jitter, Sd.chol, tid);
+    if (tid == 0) {
+      R.iterations = l + 1;
+      if (!ok) R.status = PLAN_E_INVALID;
+      if (A.l_uniform < 0) D.cur_iter = l + 1;
+    }
   }
   if (last && tid < 64) {
     // Return: lowest c_u + r in the final EliteSet (ties: lower index).
