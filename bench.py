@@ -211,6 +211,45 @@ def scale_bench(pl, workload, torch, precision=0, n_req=1024, N=4096, T=100, M=2
                          "flop_per_iteration": flop}}
 
 
+def mpc_bench(pl, workload, torch, precision=0, episodes=256, cycles=20, n_exec=5, c=None, init=0):
+    """Receding-horizon closed loop (MPC-Bi-Level): `episodes` synthetic
+    highway scenes replan every cycle with the headline planner settings,
+    execute n_exec instants and replan, all on the device. Loop rate per
+    episode, plans and QP-solves per second, the paper's two metrics
+    (episodes with a collision; average speed of the collision-free ones,
+    the mean of |v| over the cycle states)."""
+    import numpy as np
+    N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
+    cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N,
+                              max_requests=episodes, precision=precision)
+    ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
+    h = pl.plan_create(cfg, workspace=ws, stream=torch.cuda.current_stream().cuda_stream)
+    reqs = []
+    for i in range(episodes):
+        s = workload.scene(7, i, M)
+        reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i,
+                               session_id=1 + i))
+    warm_up = [pl.Request(N=r.N, T=r.T, ego=r.ego, obstacles=r.obstacles, seed=r.seed, session_id=10 ** 6 + i)
+            for i, r in enumerate(reqs[:4])]
+    pl.plan_mpc_run(h, warm_up, 1, n_exec, init=init, log=())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, log = pl.plan_mpc_run(h, reqs, cycles, n_exec, init=init, log=("ego", "collided", "status", "cost"))
+    dt = time.perf_counter() - t0
+    hit = log["collided"].any(axis=1)
+    speed = np.hypot(log["ego"][:, :, 2], log["ego"][:, :, 3]).mean(axis=1)
+    return {"init": ("sampler", "warm")[init], "episodes": episodes, "cycles": cycles, "n_exec": n_exec,
+            "N": N, "T": T, "M": M, "L": L, "K": K,
+            "seconds": dt, "loop_rate_hz": cycles / dt, "plans_per_s": episodes * cycles / dt,
+            "solves_per_s": episodes * cycles * N * L / dt,
+            "failed_plans": int((log["status"] != 0).sum()),
+            "infeasible_plans": int((log["cost"][:, :, 1] > 0).sum()),
+            "episodes_with_collision": int(hit.sum()),
+            "collided_cycles": int(log["collided"].sum()),
+            "avg_speed_collision_free_mps": float(speed[~hit].mean()) if (~hit).any() else None,
+            "driven_s": cycles * n_exec * cfg.t_f / (T - 1)}
+
+
 def precision_gap(pl, workload, c, n_samples=256):
     """Lower level of both precisions on the same n_samples behavioural
     inputs of the headline scene (seeded: lane offsets +- N(0, 0.3^2), speeds
@@ -280,6 +319,7 @@ def main() -> int:
     ap.add_argument("--no-served", action="store_true", help="skip the served (Poisson) measurement")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP16-split plan and the accuracy check")
     ap.add_argument("--no-scale", action="store_true", help="skip the 1024-request measurement")
+    ap.add_argument("--no-mpc", action="store_true", help="skip the receding-horizon closed loop")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 512 MiB device-to-device three times (a "
                          "kernel of known traffic that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -355,6 +395,12 @@ def main() -> int:
         for name, prec in (("f32", 0), ("fp16_split", 1)):
             print(f"[bench] 1024 concurrent requests {name}", file=sys.stderr, flush=True)
             out["scale"][name] = scale_bench(pl, workload, torch, prec)
+    if not args.no_mpc:
+        out["mpc"] = {}
+        for name, prec, eps, cyc, init in (("f32_1", 0, 1, 200, 0), ("f32_256", 0, 256, 20, 0),
+                                           ("fp16_split_256", 1, 256, 20, 0), ("f32_256_warm", 0, 256, 20, 1)):
+            print(f"[bench] closed loop {name}: {eps} episodes x {cyc} cycles", file=sys.stderr, flush=True)
+            out["mpc"][name] = mpc_bench(pl, workload, torch, prec, eps, cyc, c=c, init=init)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(scene, c, threads)

@@ -270,6 +270,77 @@ plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticke
 plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued);
 plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out);
 
+/*
+ * Receding-horizon closed loop (MPC-Bi-Level, Sec. V-A "MPC Baselines").
+ * Every episode replans with Alg. 1 once per cycle, executes the first
+ * n_exec instants of the trajectory it got (5 in Sec. V-A), and replans
+ * from the state reached. The first upper iteration of cycles 2.. draws
+ * from (init):
+ *   PLAN_MPC_SAMPLER  the initial sampler, as at the first cycle of a
+ *                     request without a warm start. Sec. V-A feeds each
+ *                     cycle's observation to the learned sampler; the
+ *                     structured sampler of plan_config stands in for it.
+ *   PLAN_MPC_WARM     the distribution the episode's previous cycle left
+ *                     (warm start across planning cycles, Sec. IV "Trajectory
+ *                     Sampling Approaches"), kept on the device in its
+ *                     session. Sigma shrinks with every update, so over many
+ *                     cycles the samples concentrate on one behaviour.
+ * The loop runs on the library's stream without a
+ * host round trip between cycles: after a cycle's L upper iterations an
+ * advance kernel (one workgroup per episode, FP64) evaluates the returned
+ * trajectory at t_0 .. t_{n_exec}, tests every executed instant against
+ * every neighbour's ellipse (the collision row of Table ineq_list: a
+ * collision when ((x - x_o) / a)^2 + ((y - y_o) / b)^2 < 1, a = ell_a,
+ * b = ell_b), and writes the next cycle's request in place.
+ *
+ *   reqs      the first cycle's requests, one per episode (n <= max_requests);
+ *             with PLAN_MPC_WARM each needs a distinct nonzero session_id
+ *             (optional otherwise; nonzero ids must be distinct, and the
+ *             last cycle's mu, Sigma stay in them). Episode i at cycle c
+ *             plans from the state its cycle c - 1 reached at t_{n_exec}
+ *             (held if that plan failed), with seed reqs[i].seed + c and the
+ *             neighbours at scene time s = (c n_exec) t_f / (T - 1), the
+ *             position of neighbour m formed as fma(v_m, s, p_m) from its
+ *             first-cycle position p_m and velocity v_m (constant-velocity
+ *             traffic, as in the collision row). Instant k of cycle c is
+ *             tested against the neighbours at s = (c n_exec + k) t_f / (T - 1).
+ *   cycles    planning cycles, >= 1.
+ *   n_exec    instants executed per cycle, 1 <= n_exec <= T - 1.
+ *   init      PLAN_MPC_SAMPLER or PLAN_MPC_WARM (above).
+ *   log       caller-owned host arrays, each nullable, row-major:
+ *               ego       n x (cycles + 1) x 6  b_0 of every cycle, then the
+ *                                                final state
+ *               xi        n x cycles x 22       trajectory returned by each cycle
+ *               mu, sigma n x cycles x 8, x 64  distribution after each cycle
+ *               cost      n x cycles x 2        (c_u, r) of the returned sample
+ *               collided  n x cycles            1 if an executed instant
+ *                                                meets a neighbour's ellipse
+ *               status    n x cycles            the cycle's plan status
+ *             A NULL log (or NULL members) records nothing; the call
+ *             allocates device memory for the requested logs and frees it.
+ *   out       nullable; n results of the last cycle (its mu, Sigma are the
+ *             episodes' warm starts, kept in their sessions).
+ * Errors: PLAN_E_INVALID for a bad request (the whole call fails), a missing
+ * or repeated session_id, n, cycles, n_exec or init out of range; PLAN_E_BUSY
+ * while served requests are in flight; PLAN_E_NOMEM if the log memory cannot
+ * be allocated. A batch staged before the call is replaced.
+ */
+typedef enum plan_mpc_init { PLAN_MPC_SAMPLER = 0, PLAN_MPC_WARM = 1 } plan_mpc_init;
+
+typedef struct plan_mpc_log {
+  double *ego;
+  double *xi;
+  double *mu;
+  double *sigma;
+  double *cost;
+  int32_t *collided;
+  int32_t *status;
+} plan_mpc_log;
+
+plan_status plan_mpc_run(plan_handle *h, const plan_request *reqs, int32_t n,
+                         int32_t cycles, int32_t n_exec, int32_t init,
+                         plan_mpc_log *log, plan_result *out);
+
 /* Kernel timing by HIP events recorded on the library's stream around every
  * launch of plan_launch / plan_solve_batch. enable != 0 starts recording (and
  * clears the totals); plan_profile_read waits for the stream and returns the

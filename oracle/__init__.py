@@ -109,6 +109,7 @@ def _load():
     lib.orc_sample.argtypes = [P, C.c_uint64, C.c_int, C.c_int, C.c_int, _PD, _PD, _PD]
     lib.orc_plan.argtypes = [P, S, C.c_uint64, C.c_int, _PD, _PD,
                              C.POINTER(_PlanOut), C.POINTER(_Trace)]
+    lib.orc_advance.argtypes = [P, _PD, _PD, C.c_int, C.c_int, C.c_int, _PD, _PD, _PI]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_get_threads.restype = C.c_int
     _lib = lib
@@ -316,3 +317,47 @@ def plan(par: Params, scene: Scene, seed: int, N: int, mu0=None, Sigma0=None,
     return PlanResult(out.best_index, np.array(out.p_best), np.array(out.xi_best),
                       out.cost_upper, out.residual, np.array(out.mu),
                       np.array(out.Sigma).reshape(NP, NP), arrays)
+
+
+def advance(par: Params, xi, obs0, cycle: int, n_exec: int):
+    """One step of the receding-horizon loop (MPC-Bi-Level, Sec. V-A): the
+    state (x, y, vx, vy, ax, ay) of trajectory xi at t_{n_exec}, the
+    neighbours (M x 4, first-cycle states obs0) at the start of cycle + 1,
+    and whether an executed instant t_0..t_{n_exec} of cycle ``cycle`` meets
+    a neighbour's ellipse."""
+    xi = _f64(xi).reshape(NX)
+    obs0 = np.ascontiguousarray(_f64(obs0).reshape(-1, 4))
+    M = obs0.shape[0]
+    ego = np.zeros(6)
+    obs = np.zeros((max(M, 1), 4))
+    hit = C.c_int()
+    rc = _load().orc_advance(C.byref(par), _pd(xi), _pd(obs0 if M else np.zeros((1, 4))), M, int(cycle),
+                             int(n_exec), _pd(ego), _pd(obs), C.byref(hit))
+    if rc != 0:
+        raise ValueError("oracle advance: n_exec out of [1, T - 1] or negative cycle")
+    return ego, obs[:M], bool(hit.value)
+
+
+def closed_loop(par: Params, scene: Scene, seed: int, N: int, cycles: int, n_exec: int,
+                warm: bool = False, mu0=None, Sigma0=None) -> dict:
+    """Receding-horizon loop of one episode (MPC-Bi-Level, Sec. V-A): Alg. 1
+    per cycle (seed + c at cycle c), then ``advance``. Cycles after the first
+    start from the initial sampler, or with ``warm`` from the previous
+    cycle's final mu, Sigma (Sec. IV). Returns per-cycle logs shaped like the
+    library's plan_mpc_run logs."""
+    obs0 = np.asarray(scene.obs, float).reshape(-1, 4)
+    ego = np.asarray(scene.ego, float).copy()
+    obs = obs0.copy()
+    out = dict(ego=np.zeros((cycles + 1, 6)), xi=np.zeros((cycles, NX)), mu=np.zeros((cycles, NP)),
+               sigma=np.zeros((cycles, NP, NP)), cost=np.zeros((cycles, 2)), collided=np.zeros(cycles, np.int32))
+    out["ego"][0] = ego
+    m, S = mu0, Sigma0
+    for c in range(cycles):
+        res = plan(par, Scene(ego, obs, scene.kappa_road), (int(seed) + c) % 2 ** 64, N, m, S)
+        out["xi"][c], out["mu"][c], out["sigma"][c] = res.xi_best, res.mu, res.Sigma
+        out["cost"][c] = (res.cost_upper, res.residual)
+        ego, obs, hit = advance(par, res.xi_best, obs0, c, n_exec)
+        out["ego"][c + 1] = ego
+        out["collided"][c] = int(hit)
+        m, S = (res.mu, res.Sigma) if warm else (None, None)
+    return out

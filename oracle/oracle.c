@@ -1013,3 +1013,67 @@ int orc_plan(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
   free(c_es);
   return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Receding-horizon loop (MPC-Bi-Level, Sec. V-A "MPC Baselines"): the ego
+ * executes the first n_exec instants of its trajectory, then replans from
+ * the state reached. Neighbours keep their velocities (the constant-velocity
+ * motion of the collision row of Table ineq_list). Scene time of instant m
+ * of an episode: s_m = m t_f / (T - 1); cycle c starts at m = c n_exec. A
+ * neighbour with first-cycle position p and velocity v is at fma(v, s, p)
+ * (the exactly rounded p + v s). An executed instant k = 0..n_exec collides
+ * with a neighbour when ((x - x_o)/a)^2 + ((y - y_o)/b)^2 < 1. */
+
+static double scene_time(long m, double t_f, int T) {
+  return ((double)m * t_f) / (double)(T - 1);
+}
+
+int orc_advance(const orc_params *par, const double *xi, const double *obs0, int M, int cycle, int n_exec,
+                double *ego_next, double *obs_next, int *collided) {
+  const int T = par->T;
+  if (n_exec < 1 || n_exec > T - 1 || cycle < 0) return -1;
+  double *W = (double *)malloc(sizeof(double) * T * NC);
+  double *Wd = (double *)malloc(sizeof(double) * T * NC);
+  double *Wdd = (double *)malloc(sizeof(double) * T * NC);
+  orc_basis(T, par->t_f, W, Wd, Wdd);
+  /* trajectory of eq. param at instant k: rows of W, Wd, Wdd times the
+   * coefficients of each axis */
+  int hit = 0;
+  for (int k = 0; k <= n_exec; ++k) {
+    double x = 0.0, y = 0.0;
+    for (int i = 0; i < NC; ++i) {
+      x += W[k * NC + i] * xi[i];
+      y += W[k * NC + i] * xi[NC + i];
+    }
+    const double s = scene_time((long)cycle * n_exec + k, par->t_f, T);
+    for (int m = 0; m < M; ++m) {
+      const double xo = fma(obs0[4 * m + 2], s, obs0[4 * m + 0]);
+      const double yo = fma(obs0[4 * m + 3], s, obs0[4 * m + 1]);
+      const double u = (x - xo) / par->ell_a, v = (y - yo) / par->ell_b;
+      if (u * u + v * v < 1.0) hit = 1;
+    }
+  }
+  const int k = n_exec;
+  double st[6] = {0, 0, 0, 0, 0, 0}; /* x, y, xdot, ydot, xddot, yddot */
+  for (int i = 0; i < NC; ++i) {
+    st[0] += W[k * NC + i] * xi[i];
+    st[1] += W[k * NC + i] * xi[NC + i];
+    st[2] += Wd[k * NC + i] * xi[i];
+    st[3] += Wd[k * NC + i] * xi[NC + i];
+    st[4] += Wdd[k * NC + i] * xi[i];
+    st[5] += Wdd[k * NC + i] * xi[NC + i];
+  }
+  memcpy(ego_next, st, sizeof(st));
+  const double sn = scene_time((long)(cycle + 1) * n_exec, par->t_f, T);
+  for (int m = 0; m < M; ++m) {
+    obs_next[4 * m + 0] = fma(obs0[4 * m + 2], sn, obs0[4 * m + 0]);
+    obs_next[4 * m + 1] = fma(obs0[4 * m + 3], sn, obs0[4 * m + 1]);
+    obs_next[4 * m + 2] = obs0[4 * m + 2];
+    obs_next[4 * m + 3] = obs0[4 * m + 3];
+  }
+  *collided = hit;
+  free(W);
+  free(Wd);
+  free(Wdd);
+  return 0;
+}

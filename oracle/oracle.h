@@ -143,6 +143,13 @@ int orc_plan(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
              orc_plan_trace *trace);
 
 /* Threads used by the OpenMP loops over samples (1 = serial). */
+/* One step of the receding-horizon loop (MPC-Bi-Level, Sec. V-A): state of
+ * xi at t_{n_exec} (x, y, xdot, ydot, xddot, yddot), the neighbours (M x 4,
+ * first-cycle states obs0) at the start of cycle + 1, and whether an
+ * executed instant of cycle `cycle` meets a neighbour's ellipse. */
+int orc_advance(const orc_params *par, const double *xi, const double *obs0, int M, int cycle, int n_exec,
+                double *ego_next, double *obs_next, int *collided);
+
 void orc_set_threads(int n);
 int orc_get_threads(void);
 

@@ -5,11 +5,13 @@ The planner runs as HIP kernels in ``libplan.so`` behind the C ABI of
 ``workload`` builds seeded synthetic scenes.
 """
 from .binding import (PLAN_E_BUSY, PLAN_E_DEVICE, PLAN_E_INVALID, PLAN_E_NOMEM,  # noqa: F401
-                      PLAN_E_UNSUPPORTED, PLAN_F_INFEASIBLE, PLAN_F_WARM, PLAN_OK,
+                      PLAN_E_UNSUPPORTED, PLAN_F_INFEASIBLE, PLAN_F_WARM, PLAN_MPC_SAMPLER,
+                      PLAN_MPC_WARM, PLAN_OK,
                       PLAN_PREC_FP16_SPLIT, PLAN_PREC_FP32, Handle,
                       PlanError, Request, Result, elite_sizes, exported_symbols, load,
                       plan_collect, plan_config_init, plan_create, plan_destroy,
-                      plan_get_trace, plan_last_error, plan_launch, plan_lower_solve,
+                      MPC_LOGS, plan_get_trace, plan_last_error, plan_launch, plan_lower_solve,
+                      plan_mpc_run,
                       plan_poll, plan_progress, plan_submit,
                       plan_profile, plan_profile_read, plan_solve_batch, plan_stage,
                       plan_workspace_bytes)

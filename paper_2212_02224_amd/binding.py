@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libplan.so")
 PLAN_OK, PLAN_E_INVALID, PLAN_E_NOMEM, PLAN_E_DEVICE, PLAN_E_BUSY, PLAN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 PLAN_PREC_FP32, PLAN_PREC_FP16_SPLIT = 0, 1
 PLAN_F_INFEASIBLE, PLAN_F_WARM = 1, 2
+PLAN_MPC_SAMPLER, PLAN_MPC_WARM = 0, 1
 NC, NX, NP = 11, 22, 8
 MAX_N, MAX_M, MAX_T = 4096, 32, 256
 
@@ -54,6 +55,7 @@ class plan_config(C.Structure):
 
 
 _PD = C.POINTER(C.c_double)
+_PI = C.POINTER(C.c_int32)
 
 
 class plan_request(C.Structure):
@@ -77,6 +79,11 @@ class plan_result(C.Structure):
         ("mu", C.c_double * NP), ("sigma", C.c_double * (NP * NP)),
         ("latency_s", C.c_double),
     ]
+
+
+class plan_mpc_log(C.Structure):
+    _fields_ = [("ego", _PD), ("xi", _PD), ("mu", _PD), ("sigma", _PD), ("cost", _PD),
+                ("collided", _PI), ("status", _PI)]
 
 
 _lib = None
@@ -113,11 +120,12 @@ def load():
     lib.plan_submit.argtypes = [H, Req, C.POINTER(C.c_uint64)]
     lib.plan_progress.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.plan_poll.argtypes = [H, C.c_uint64, Res]
+    lib.plan_mpc_run.argtypes = [H, Req, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(plan_mpc_log), Res]
     lib.plan_profile.argtypes = [H, C.c_int32]
     lib.plan_profile_read.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in ("plan_create", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
                  "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-                 "plan_profile", "plan_profile_read"):
+                 "plan_mpc_run", "plan_profile", "plan_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -127,7 +135,7 @@ def exported_symbols() -> list[str]:
     return ["plan_config_init", "plan_workspace_bytes", "plan_create", "plan_destroy",
             "plan_last_error", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
             "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-            "plan_profile", "plan_profile_read"]
+            "plan_mpc_run", "plan_profile", "plan_profile_read"]
 
 
 def _check(status: int, handle=None) -> int:
@@ -347,6 +355,32 @@ def plan_poll(h: Handle, ticket: int) -> Result | None:
         return None
     _check(st, h.ptr)
     return _result(out)
+
+
+MPC_LOGS = ("ego", "xi", "mu", "sigma", "cost", "collided", "status")
+
+
+def plan_mpc_run(h: Handle, reqs: Sequence[Request], cycles: int, n_exec: int = 5,
+                 init: int = PLAN_MPC_SAMPLER, log=MPC_LOGS) -> tuple[list[Result], dict]:
+    """Receding-horizon closed loop of len(reqs) episodes (see plan_mpc_run in
+    include/plan.h). ``init``: PLAN_MPC_SAMPLER or PLAN_MPC_WARM. ``log``:
+    names of the per-cycle logs to record (a subset of MPC_LOGS). Returns
+    (results of the last cycle, {name: array})."""
+    n = len(reqs)
+    m = _Marshalled(reqs)
+    out = (plan_result * max(1, n))()
+    shapes = dict(ego=(n, cycles + 1, 6), xi=(n, cycles, NX), mu=(n, cycles, NP), sigma=(n, cycles, NP, NP),
+                  cost=(n, cycles, 2), collided=(n, cycles), status=(n, cycles))
+    logs = {}
+    lg = plan_mpc_log()
+    for name in log:
+        if name not in shapes:
+            raise ValueError(f"unknown log {name!r}")
+        a = np.zeros(shapes[name], np.int32 if name in ("collided", "status") else np.float64)
+        logs[name] = a
+        setattr(lg, name, a.ctypes.data_as(_PI if a.dtype == np.int32 else _PD))
+    _check(load().plan_mpc_run(h.ptr, m.arr, n, int(cycles), int(n_exec), int(init), C.byref(lg), out), h.ptr)
+    return [_result(out[i]) for i in range(n)], logs
 
 
 def plan_profile(h: Handle, enable: bool = True) -> None:

@@ -33,6 +33,7 @@ hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblo
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1);
+hipError_t launch_advance(const AdvArgs &a, const MethodParams &p, int n, hipStream_t st);
 }  // namespace plan
 
 using namespace plan;
@@ -972,6 +973,101 @@ plan_status plan_solve_batch(plan_handle *h, const plan_request *reqs, int32_t n
     first += m;
   }
   return worst;
+}
+
+plan_status plan_mpc_run(plan_handle *h, const plan_request *reqs, int32_t n, int32_t cycles, int32_t n_exec,
+                         int32_t init, plan_mpc_log *log, plan_result *out) {
+  if (!h || !reqs || n < 1) return fail(h, PLAN_E_INVALID, "bad arguments");
+  if (n > h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more episodes than max_requests");
+  if (cycles < 1 || cycles > (1 << 20)) return fail(h, PLAN_E_INVALID, "cycles out of range");
+  if (init != PLAN_MPC_SAMPLER && init != PLAN_MPC_WARM) return fail(h, PLAN_E_INVALID, "unknown init mode");
+  std::unordered_map<uint64_t, int> seen;
+  for (int i = 0; i < n; ++i) {
+    if (n_exec < 1 || n_exec > reqs[i].T - 1)
+      return fail(h, PLAN_E_INVALID, "episode " + std::to_string(i) + ": n_exec out of [1, T - 1]");
+    if (reqs[i].session_id == 0 && init == PLAN_MPC_WARM)
+      return fail(h, PLAN_E_INVALID, "episode " + std::to_string(i) + ": no session_id");
+    if (reqs[i].session_id != 0 && !seen.emplace(reqs[i].session_id, i).second)
+      return fail(h, PLAN_E_INVALID, "episode " + std::to_string(i) + ": session_id repeated");
+  }
+  plan_status st = stage_impl(h, reqs, n, 0);
+  if (st != PLAN_OK) return st;
+  for (int i = 0; i < n; ++i)
+    if (h->staged_status[i] != PLAN_OK) return fail(h, (plan_status)h->staged_status[i], h->err);
+
+  // Device memory of the call: first-cycle neighbour positions and the logs
+  // that were asked for.
+  const size_t nc = (size_t)n * cycles;
+  const plan_mpc_log lg = log ? *log : plan_mpc_log{};
+  struct Part {
+    void *host;
+    size_t bytes;
+    size_t off;
+  } parts[8] = {{nullptr, (size_t)n * PLAN_MAX_M * 2 * 8, 0},
+                {lg.ego, (size_t)n * (cycles + 1) * 6 * 8, 0},
+                {lg.xi, nc * 22 * 8, 0},
+                {lg.mu, nc * 8 * 8, 0},
+                {lg.sigma, nc * 64 * 8, 0},
+                {lg.cost, nc * 2 * 8, 0},
+                {lg.collided, nc * 4, 0},
+                {lg.status, nc * 4, 0}};
+  size_t total = 0;
+  for (int k = 0; k < 8; ++k) {
+    if (k > 0 && parts[k].host == nullptr) continue;
+    parts[k].off = total;
+    total += (parts[k].bytes + 255) & ~(size_t)255;
+  }
+  char *buf = nullptr;
+  if (hipMalloc(&buf, total) != hipSuccess) return fail(h, PLAN_E_NOMEM, "closed-loop log memory");
+  auto dev = [&](int k) -> void * { return (k == 0 || parts[k].host) ? buf + parts[k].off : nullptr; };
+  std::vector<double> o0((size_t)n * PLAN_MAX_M * 2, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const ReqDesc &d = h->h_desc[i];
+    for (int m = 0; m < d.M; ++m) {
+      o0[((size_t)i * PLAN_MAX_M + m) * 2] = d.obs[m][0];
+      o0[((size_t)i * PLAN_MAX_M + m) * 2 + 1] = d.obs[m][1];
+    }
+  }
+  AdvArgs aa;
+  aa.desc = h->desc;
+  aa.result = h->result;
+  aa.dist = h->dist;
+  aa.obs0 = (const double *)dev(0);
+  aa.cycles = cycles;
+  aa.n_exec = n_exec;
+  aa.warm = init == PLAN_MPC_WARM ? 1 : 0;
+  aa.ego = (double *)dev(1);
+  aa.xi = (double *)dev(2);
+  aa.mu = (double *)dev(3);
+  aa.sigma = (double *)dev(4);
+  aa.cost = (double *)dev(5);
+  aa.collided = (int32_t *)dev(6);
+  aa.status = (int32_t *)dev(7);
+  const auto t0 = Clock::now();
+  hipError_t e = hipMemcpyAsync(buf, o0.data(), o0.size() * 8, hipMemcpyHostToDevice, h->stream);
+  for (int c = 0; e == hipSuccess && st == PLAN_OK && c < cycles; ++c) {
+    st = launch_impl(h);
+    aa.cycle = c;
+    if (st == PLAN_OK) e = launch_advance(aa, h->mp, n, h->stream);
+  }
+  if (e == hipSuccess && st == PLAN_OK) e = hipStreamSynchronize(h->stream);
+  for (int k = 1; e == hipSuccess && st == PLAN_OK && k < 8; ++k)
+    if (parts[k].host) e = hipMemcpy(parts[k].host, buf + parts[k].off, parts[k].bytes, hipMemcpyDeviceToHost);
+  const double el = std::chrono::duration<double>(Clock::now() - t0).count();
+  if (e == hipSuccess && st == PLAN_OK && lg.ego) {
+    // the first cycle's state is the request's (the kernel writes the rest)
+    for (int i = 0; i < n; ++i) std::memcpy(lg.ego + (size_t)i * (cycles + 1) * 6, reqs[i].ego, 6 * 8);
+  }
+  if (e == hipSuccess && st == PLAN_OK) {
+    std::vector<plan_result> tmp(out ? 0 : n);
+    st = collect_impl(h, out ? out : tmp.data(), el);
+  }
+  hipStreamSynchronize(h->stream);
+  hipFree(buf);
+  h->staged = 0;
+  h->staged_total = 0;
+  if (e != hipSuccess) return hip_fail(h, e, "closed loop");
+  return st;
 }
 
 plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const double *p, int32_t N,

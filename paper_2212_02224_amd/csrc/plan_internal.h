@@ -147,4 +147,18 @@ struct SelArgs {
   int32_t max_N, max_ces, max_es;
 };
 
+// Arguments of the closed-loop advance kernel (one workgroup per episode,
+// episode e in slot e).
+struct AdvArgs {
+  ReqDesc *desc;
+  const ResultRec *result;
+  const DistState *dist;
+  const double *obs0;        // [n][PLAN_MAX_M][2] neighbour x, y at the first cycle
+  int32_t cycles, cycle, n_exec;
+  int32_t warm;              // nonzero: warm start from the session, else the structured sampler
+  // device logs (each nullable), laid out as the host's plan_mpc_log
+  double *ego, *xi, *mu, *sigma, *cost;
+  int32_t *collided, *status;
+};
+
 }  // namespace plan

@@ -46,8 +46,9 @@ def test_struct_layout_matches_header(pl):
 #include <stddef.h>
 #include "plan.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(plan_config), sizeof(plan_request), sizeof(plan_result),
-         offsetof(plan_config, stream), offsetof(plan_request, first_iter), offsetof(plan_result, latency_s));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(plan_config), sizeof(plan_request), sizeof(plan_result),
+         offsetof(plan_config, stream), offsetof(plan_request, first_iter), offsetof(plan_result, latency_s),
+         sizeof(plan_mpc_log), offsetof(plan_mpc_log, status));
   return 0;
 }
 '''
@@ -60,7 +61,8 @@ int main(void) {
     got = [int(x) for x in out]
     b = pl.binding
     want = [C.sizeof(b.plan_config), C.sizeof(b.plan_request), C.sizeof(b.plan_result),
-            b.plan_config.stream.offset, b.plan_request.first_iter.offset, b.plan_result.latency_s.offset]
+            b.plan_config.stream.offset, b.plan_request.first_iter.offset, b.plan_result.latency_s.offset,
+            C.sizeof(b.plan_mpc_log), b.plan_mpc_log.status.offset]
     assert got == want
 
 
