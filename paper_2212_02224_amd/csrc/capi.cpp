@@ -9,7 +9,9 @@
 //                         workgroup per request
 // Batch mode runs L such pairs for a staged batch; served mode runs one pair
 // per plan_progress call for whatever is resident, each request at its own
-// iteration (kept on the device in its descriptor).
+// iteration (kept on the device in its descriptor). The closed loop
+// (plan_mpc_run) runs L pairs per cycle followed by advance_kernel, which
+// writes the next cycle's descriptors on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
