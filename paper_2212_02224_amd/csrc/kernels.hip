@@ -1202,6 +1202,61 @@ __device__ uint32_t block_exscan(uint32_t x, uint32_t *s_tmp, uint32_t *total) {
   return base + incl - x;
 }
 
+// Exclusive prefix sum over the block with a single barrier: the wave totals
+// go to s_w[0..3], which must not be in use by a call still in flight (give
+// consecutive calls distinct slots). Returns the thread's offset.
+__device__ __forceinline__ uint32_t block_exscan1(uint32_t x, uint32_t *s_w, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) s_w[wave] = incl;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (int w = 0; w < kSelBlock / kWave; ++w) {
+    const uint32_t t = s_w[w];
+    if (w < wave) base += t;
+    tot += t;
+  }
+  *total = tot;
+  return base + incl - x;
+}
+
+// Select the `want` smallest of the distinct composite keys
+// s_k[0..cnt) = (key << 32) | position by counting, for each key, the keys
+// below it (its rank); thread t ranks position t. The positions of the
+// selected keys go to s_out[0..want) in increasing order and the position of
+// rank 0 to *s_first. s_k holds an even number of entries (a last ~0 pads an
+// odd cnt); cnt <= kSelBlock. Uses s_tmp[0..4) and two barriers.
+__device__ void rank_select(const unsigned long long *s_k, int cnt, int want, uint32_t *s_out, uint32_t *s_first,
+                            uint32_t *s_tmp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = (cnt + 1) >> 1;
+  const ulonglong2 *s_k2 = reinterpret_cast<const ulonglong2 *>(s_k);
+  bool sel = false;
+  if (tid < cnt) {
+    const unsigned long long ki = s_k[tid];
+    uint32_t rank = 0;
+#pragma unroll 8
+    for (int j = 0; j < half; ++j) {
+      const ulonglong2 v = s_k2[j];
+      rank += (v.x < ki) + (v.y < ki);
+    }
+    sel = rank < (uint32_t)want;
+    if (rank == 0) *s_first = (uint32_t)tid;
+  }
+  const uint64_t bal = __ballot(sel);
+  if (lane == 0) s_tmp[wave] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += s_tmp[w];
+  if (sel) s_out[before + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)tid;
+  __syncthreads();
+}
+
 // Select the `want` smallest (key, position) pairs of s_key[0..cnt) (ties to
 // the lower position) and write their positions, in increasing order, to
 // s_out[0..want). If at least `want` keys equal the smallest key, they are
@@ -1212,9 +1267,13 @@ __device__ uint32_t block_exscan(uint32_t x, uint32_t *s_tmp, uint32_t *total) {
 __device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t *s_out, uint32_t *s_hist,
                              uint32_t *s_tmp) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // Positions are split into contiguous chunks, one per thread, so the scans
+  // below run in position order.
+  const int chunk = (cnt + kSelBlock - 1) / kSelBlock;
+  const int p0 = min(cnt, tid * chunk), p1 = min(cnt, p0 + chunk);
   // smallest key and its multiplicity
   uint32_t kmin = 0xFFFFFFFFu;
-  for (int i = tid; i < cnt; i += kSelBlock) kmin = min(kmin, s_key[i]);
+  for (int i = p0; i < p1; ++i) kmin = min(kmin, s_key[i]);
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
   if (lane == 0) s_tmp[wave] = kmin;
@@ -1222,13 +1281,20 @@ __device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t 
   kmin = s_tmp[0];
   for (int w = 1; w < kSelBlock / kWave; ++w) kmin = min(kmin, s_tmp[w]);
   uint32_t nmin = 0;
-  for (int i = tid; i < cnt; i += kSelBlock) nmin += s_key[i] == kmin;
+  for (int i = p0; i < p1; ++i) nmin += s_key[i] == kmin;
   uint32_t tot_min;
-  block_exscan(nmin, s_tmp + 8, &tot_min);
+  uint32_t min_before = block_exscan1(nmin, s_tmp + 4, &tot_min);
+  if (tot_min >= (uint32_t)want) {
+    // the first `want` positions holding the smallest key
+    for (int i = p0; i < p1 && min_before < (uint32_t)want; ++i)
+      if (s_key[i] == kmin) s_out[min_before++] = (uint32_t)i;
+    __syncthreads();
+    return;
+  }
 
-  uint32_t prefix = kmin, mask = 0xFFFFFFFFu;
+  uint32_t prefix = 0, mask = 0;
   int remaining = want;
-  if (tot_min < (uint32_t)want) {
+  {
     prefix = 0;
     mask = 0;
     for (int shift = 24; shift >= 0; shift -= 8) {
@@ -1284,10 +1350,6 @@ __device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t 
       if (exact) break;  // every key matching the prefix is selected
     }
   }
-  // Positions are split into contiguous chunks, one per thread, so both scans
-  // run in position order.
-  const int chunk = (cnt + kSelBlock - 1) / kSelBlock;
-  const int p0 = tid * chunk, p1 = min(cnt, p0 + chunk);
   uint32_t eq = 0;
   for (int i = p0; i < p1; ++i) eq += (s_key[i] & mask) == prefix;
   uint32_t tot;
@@ -1313,7 +1375,8 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   __shared__ uint32_t s_key[PLAN_MAX_N];  // residual keys
   __shared__ float s_c[PLAN_MAX_N];       // c_u + r
   __shared__ uint32_t s_ces[kMaxCes];
-  __shared__ uint32_t s_key2[kMaxCes];
+  __shared__ __align__(16) unsigned long long s_key2[kSelBlock + 2];  // (key << 32) | CES position
+  __shared__ unsigned long long s_bestw[kSelBlock / kWave];
   __shared__ uint32_t s_es[kMaxCes];
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_tmp[32];
@@ -1322,7 +1385,7 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   __shared__ double s_mu[8], s_mun[8], s_sig[64];
   __shared__ double s_part[4][64 + 8];
   __shared__ double s_sum;
-  __shared__ unsigned long long s_best[kSelBlock / kWave];
+  __shared__ uint32_t s_first;
 
   const int slot = A.slots[blockIdx.x];
   ReqDesc &D = A.desc[slot];
@@ -1375,35 +1438,44 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   // ConstraintEliteSet: the n smallest (r_j, j).
   block_select(s_key, N, n, s_ces, s_hist, s_tmp);
   // EliteSet: the q smallest (c_u + r, j) over the ConstraintEliteSet, whose
-  // members are listed in increasing sample index.
-  for (int i = tid; i < n; i += kSelBlock) {
-    const uint32_t j = s_ces[i];
-    s_key2[i] = order_key(s_c[j]);
-    if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)j;
-  }
-  __syncthreads();
-  block_select(s_key2, n, q, s_es, s_hist, s_tmp);
-  // Lowest cost of the EliteSet (ties: lower index): the set is listed in
-  // increasing index, so the first minimum of its keys.
-  {
+  // members are listed in increasing sample index, so the CES position
+  // breaks ties as the sample index does. Up to one member per thread they
+  // are ranked by counting (the member of rank 0 is the lowest cost of the
+  // EliteSet, ties: lower index); larger sets go through the radix select
+  // on the cost keys (s_key is free again) and a minimum over the set.
+  uint32_t jbest;
+  if (n <= kSelBlock) {
+    for (int i = tid; i < n; i += kSelBlock) {
+      const uint32_t j = s_ces[i];
+      s_key2[i] = ((unsigned long long)order_key(s_c[j]) << 32) | (unsigned long long)i;
+      if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)j;
+    }
+    if (tid == 0 && (n & 1)) s_key2[n] = ~0ull;
+    __syncthreads();
+    rank_select(s_key2, n, q, s_es, &s_first, s_tmp);
+    jbest = s_ces[s_first];
+  } else {
+    for (int i = tid; i < n; i += kSelBlock) {
+      const uint32_t j = s_ces[i];
+      s_key[i] = order_key(s_c[j]);
+      if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)j;
+    }
+    __syncthreads();
+    block_select(s_key, n, q, s_es, s_hist, s_tmp);
     unsigned long long best = ~0ull;
     for (int i = tid; i < q; i += kSelBlock) {
       const uint32_t pos = s_es[i];
-      best = min(best, ((unsigned long long)s_key2[pos] << 32) | s_ces[pos]);
+      best = min(best, ((unsigned long long)s_key[pos] << 32) | pos);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
       const unsigned long long o = __shfl_xor(best, d, 64);
       best = min(best, o);
     }
-    if ((tid & 63) == 0) s_best[tid >> 6] = best;
-  }
-  __syncthreads();
-  uint32_t jbest;
-  {
-    unsigned long long best = s_best[0];
-    for (int w = 1; w < kSelBlock / kWave; ++w) best = min(best, s_best[w]);
-    jbest = (uint32_t)(best & 0xFFFFFFFFull);
+    if ((tid & 63) == 0) s_bestw[tid >> 6] = best;
+    __syncthreads();
+    for (int w = 0; w < kSelBlock / kWave; ++w) best = min(best, s_bestw[w]);
+    jbest = s_ces[(uint32_t)(best & 0xFFFFFFFFull)];
   }
 
   // Elite rows (issued first: the loads overlap the weights) and the weights
