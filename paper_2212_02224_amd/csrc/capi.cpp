@@ -29,7 +29,7 @@
 #include "precompute.h"
 
 namespace plan {
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st,
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, size_t lds, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, int T, size_t lds,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
@@ -79,20 +79,38 @@ size_t lds_bytes(int M, int T, bool mfma) {
   return b;
 }
 
-// Workgroups of one request. VALU kernel: ceil(T/64) waves per sample, 4
-// waves per group; matrix-core kernel: 16 samples per group.
-int blocks_for(int N, int T, bool mfma) {
+// Horizon class of the VALU kernel: up to 64 instants (one per lane), or
+// more (one or two per lane, chosen per launch).
+int t_class(int T) { return T > kWave ? 2 : 1; }
+
+// Workgroups of one request. VALU kernel: ceil(T / (64 ipl)) waves per
+// sample with ipl instants per lane, 4 waves per group; matrix-core kernel:
+// 16 samples per group.
+int blocks_for(int N, int T, bool mfma, int ipl = 1) {
   if (mfma) return (N + kMfmaSamples - 1) / kMfmaSamples;
-  const int spb = 4 / ((T + kWave - 1) / kWave);
+  const int spb = 4 / ((T + kWave * ipl - 1) / (kWave * ipl));
   return (N + spb - 1) / spb;
 }
 
+// Two instants per lane or one? Both give the same results. Workgroups run
+// in rounds of 4 per CU (one instant per lane, 120 VGPRs) or 3 per CU (two,
+// 162 VGPRs), and a round of two instants per lane takes about 1.45 times one
+// of one instant per lane (measured on full launches of N = 512..4096,
+// T = 100, M = 4..20); the variant with the fewer weighted rounds is taken.
+bool use_ipl2(int blocks1, int blocks2, int n_cu) {
+  const int r1 = (blocks1 + 4 * n_cu - 1) / (4 * n_cu);
+  const int r2 = (blocks2 + 3 * n_cu - 1) / (3 * n_cu);
+  return 29 * r2 < 20 * r1;
+}
+
 // Lower-level launches of one upper iteration: one per horizon length in the
-// matrix-core mode (its workgroup shape depends on T), one in total else.
+// matrix-core mode (its workgroup shape depends on T), one per number of
+// instants per lane in the VALU mode. Group.T is that key.
 struct LaunchSet {
   int n_act = 0, ngroups = 0;
   struct Group {
     int act_off = 0, n = 0, nblocks = 0, T = 0;
+    int ipl = 1;  // VALU kernel: instants per lane
     size_t lds = 0;
   } grp[4];
 };
@@ -479,7 +497,7 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
   int keys[4];
   int nkeys = 0;
   for (int i = 0; i < n; ++i) {
-    const int key = mf ? h->h_desc[slots[i]].T : 0;
+    const int key = mf ? h->h_desc[slots[i]].T : t_class(h->h_desc[slots[i]].T);
     bool seen = false;
     for (int k = 0; k < nkeys; ++k) seen |= keys[k] == key;
     if (!seen) keys[nkeys++] = key;
@@ -492,7 +510,7 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
     int blocks = 0;
     for (int i = 0; i < n; ++i) {
       const ReqDesc &d = h->h_desc[slots[i]];
-      if ((mf ? d.T : 0) != keys[k]) continue;
+      if ((mf ? d.T : t_class(d.T)) != keys[k]) continue;
       act[pos] = slots[i];
       prefix[pos + k] = blocks;
       blocks += blocks_for(d.N, d.T, mf);
@@ -503,6 +521,24 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
     gr.nblocks = blocks;
     prefix[pos + k] = blocks;
     gr.T = keys[k];
+    if (!mf && keys[k] == 2) {
+      int blocks2 = 0;
+      for (int i = gr.act_off; i < pos; ++i) {
+        const ReqDesc &d = h->h_desc[act[i]];
+        blocks2 += blocks_for(d.N, d.T, false, 2);
+      }
+      if (use_ipl2(blocks, blocks2, h->n_cu)) {
+        gr.ipl = 2;
+        blocks = 0;
+        for (int i = gr.act_off; i < pos; ++i) {
+          const ReqDesc &d = h->h_desc[act[i]];
+          prefix[i + k] = blocks;
+          blocks += blocks_for(d.N, d.T, false, 2);
+        }
+        gr.nblocks = blocks;
+        prefix[pos + k] = blocks;
+      }
+    }
   }
   ls.ngroups = nkeys;
   // A light matrix-core load runs all horizons in one launch shaped for the
@@ -555,7 +591,7 @@ plan_status launch_lower_set(plan_handle *h, const LaunchSet &ls, int l_uniform,
           // workgroups, else four (same arithmetic either way)
           const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
           return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.T, gr.lds, h->stream, a, b)
-                    : launch_lower(la, h->mp, gr.nblocks, gr.lds, h->stream, a, b);
+                    : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.lds, h->stream, a, b);
         },
         mf ? "lower_mfma_kernel" : "lower_kernel");
     if (st != PLAN_OK) return st;

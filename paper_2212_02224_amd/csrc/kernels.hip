@@ -380,13 +380,50 @@ __device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const
   return targets_from(s, S, ax, ay, tv, da_prev);
 }
 
-// One target pass at this lane's instant, accumulated into the lane's share
-// of N^T g.
-__device__ __forceinline__ void target_pass(const Lane &L, const Scal &S, const float (&zs)[15],
-                                            const float4 *__restrict__ obs, int npair, int T, int t,
-                                            bool tv, float &da_prev, float (&g)[16]) {
-  const State6 s = eval_traj(L, zs, S.vx0);
-  const Corr c = targets_at(s, S, obs, npair, T, t, tv, da_prev);
+// One target pass over this lane's IPL instants (slots): the trajectory at
+// each, the neighbour sums of all slots in one loop over the neighbour pairs
+// (the slots' dependency chains interleave), then the targets of each slot.
+template <int IPL>
+__device__ __forceinline__ void target_pass(const Lane (&L)[IPL], const Scal &S, const float (&zs)[15],
+                                            const float4 *__restrict__ obs, int npair, int T,
+                                            const int (&tt)[IPL], const bool (&tv)[IPL], float (&da_prev)[IPL],
+                                            Corr (&cr)[IPL]) {
+  State6 st[IPL];
+  float xs[IPL], ys[IPL], ax[IPL], ay[IPL];
+#pragma unroll
+  for (int u = 0; u < IPL; ++u) {
+    st[u] = eval_traj(L[u], zs, S.vx0);
+    xs[u] = st[u].x * S.ia;
+    ys[u] = st[u].y * S.ib;
+    ax[u] = 0.f;
+    ay[u] = 0.f;
+  }
+  if (npair > 0) {
+    float4 cur[IPL];
+#pragma unroll
+    for (int u = 0; u < IPL; ++u) cur[u] = obs[tt[u]];
+    for (int c = 0; c < npair; ++c) {
+      const int cn = c + 1 < npair ? c + 1 : c;
+      float4 nxt[IPL];
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) nxt[u] = obs[cn * T + tt[u]];
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) {
+        const float dx0 = xs[u] - cur[u].x, dy0 = ys[u] - cur[u].y;
+        const float dx1 = xs[u] - cur[u].z, dy1 = ys[u] - cur[u].w;
+        const float q0 = fmaf(dx0, dx0, dy0 * dy0), q1 = fmaf(dx1, dx1, dy1 * dy1);
+        near_update(q0, dx0, dy0, ax[u], ay[u]);
+        near_update(q1, dx1, dy1, ax[u], ay[u]);
+        cur[u] = nxt[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IPL; ++u) cr[u] = targets_from(st[u], S, ax[u], ay[u], tv[u], da_prev[u]);
+}
+
+// This lane's share of N^T g at one instant.
+__device__ __forceinline__ void g_of(const Lane &L, const Corr &c, float (&g)[16]) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) g[k] = fmaf(L.bx[k], c.dox, fmaf(L.bdx[k], c.dvx, L.bddx[k] * c.dax));
 #pragma unroll
@@ -420,12 +457,6 @@ __device__ __forceinline__ void residual_at(const State6 &s, const Scal &S, cons
   const float e = vn - S.v_max;
   res = tv ? r : 0.f;
   cost = tv ? e * e : 0.f;
-}
-
-__device__ __forceinline__ void residual_pass(const Lane &L, const Scal &S, const float (&zs)[15],
-                                              const float4 *__restrict__ obs, int npair, int T, int t,
-                                              bool tv, float &res, float &cost) {
-  residual_at(eval_traj(L, zs, S.vx0), S, obs, npair, T, t, tv, res, cost);
 }
 
 // Workgroup -> slot: binary search of the workgroup index in the prefix
@@ -591,9 +622,12 @@ __device__ __forceinline__ void write_xi(const ReqDesc &D, const MethodParams &P
   }
 }
 
+// IPL instants per lane: instant (wi IPL + u) 64 + lane in slot u of wave wi
+// of a sample; ceil(T / (64 IPL)) waves per sample.
+template <int IPL>
 __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_obs[];
-  __shared__ float s_red[2][4][16];
+  __shared__ float s_red[2][4 * IPL][16];
   __shared__ double s_mu[8], s_chol[64];
 
   const int2 bi = block_slot(A);
@@ -601,16 +635,21 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
   const int T = D.T, M = D.M, N = D.N;
   const int npair = (M + 1) >> 1;
-  const int NW = (T + kWave - 1) / kWave;
+  const int NW = (T + kWave * IPL - 1) / (kWave * IPL);
   const int spb = 4 / NW;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int sl = wave / NW;
   const int wi = wave - sl * NW;
   const int j = bi.y * spb + sl;
   const bool active = (sl < spb) && (j < N);
-  const int t = wi * kWave + lane;
-  const bool tv = active && t < T;
-  const int tt = t < T ? t : T - 1;
+  int tt[IPL];
+  bool tv[IPL];
+#pragma unroll
+  for (int u = 0; u < IPL; ++u) {
+    const int t = (wi * IPL + u) * kWave + lane;
+    tv[u] = active && t < T;
+    tt[u] = t < T ? t : T - 1;
+  }
   const size_t slot_off = (size_t)D.row_off;
 
   stage_neighbours(D, P, s_obs);
@@ -619,27 +658,28 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   if (!forced && !structured) load_distribution(A, D, P, bi.x, l, s_mu, s_chol);
   const Scal S = make_scal(D, P);
 
-  // Basis rows of this lane's instant and the fixed part of the trajectory.
+  // Basis rows of this lane's instants and the fixed part of the trajectory.
   const float *Bt = A.basis + A.basis_off[D.t_idx];
   const int Tp = A.basis_tpad[D.t_idx];
-  Lane L;
+  Lane L[IPL];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    L.bx[c] = Bt[(kColW + c) * Tp + tt];
-    L.bdx[c] = Bt[(kColWd + c) * Tp + tt];
-    L.bddx[c] = Bt[(kColWdd + c) * Tp + tt];
-  }
-  L.by7 = Bt[(kColY7 + 0) * Tp + tt];
-  L.bdy7 = Bt[(kColY7 + 1) * Tp + tt];
-  L.bddy7 = Bt[(kColY7 + 2) * Tp + tt];
-  {
-    const State6 f = fixed_part(Bt, Tp, tt, D, P);
-    L.xf = f.x;
-    L.xdf = f.xd;
-    L.xddf = f.xdd;
-    L.yf = f.y;
-    L.ydf = f.yd;
-    L.yddf = f.ydd;
+  for (int u = 0; u < IPL; ++u) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      L[u].bx[c] = Bt[(kColW + c) * Tp + tt[u]];
+      L[u].bdx[c] = Bt[(kColWd + c) * Tp + tt[u]];
+      L[u].bddx[c] = Bt[(kColWdd + c) * Tp + tt[u]];
+    }
+    L[u].by7 = Bt[(kColY7 + 0) * Tp + tt[u]];
+    L[u].bdy7 = Bt[(kColY7 + 1) * Tp + tt[u]];
+    L[u].bddy7 = Bt[(kColY7 + 2) * Tp + tt[u]];
+    const State6 f = fixed_part(Bt, Tp, tt[u], D, P);
+    L[u].xf = f.x;
+    L[u].xdf = f.xd;
+    L[u].xddf = f.xdd;
+    L[u].yf = f.y;
+    L[u].ydf = f.yd;
+    L[u].yddf = f.ydd;
   }
   const int v = lane >> 2;
   float arow[16];
@@ -674,30 +714,54 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
 
   // Initial d_a: clip(|a(xi_bar)|, 0, a_max).
-  float da_prev;
-  {
-    State6 s = eval_traj(L, zs, S.vx0);
-    da_prev = fminf(fsqrt(fmaf(s.xdd, s.xdd, s.ydd * s.ydd)), S.a_max);
+  float da_prev[IPL];
+#pragma unroll
+  for (int u = 0; u < IPL; ++u) {
+    State6 s = eval_traj(L[u], zs, S.vx0);
+    da_prev[u] = fminf(fsqrt(fmaf(s.xdd, s.xdd, s.ydd * s.ydd)), S.a_max);
   }
 
   const float4 *obs = s_obs;
   int buf = 0;
-  auto reduce_sample = [&](const float (&g)[16]) -> float {
-    float r = reduce16(g, lane);
-    if (NW > 1) {
-      if ((lane & 3) == 0) s_red[buf][wave][v] = r;
-      __syncthreads();
-      r = 0.f;
-      if (sl < spb)  // a wave beyond the last sample of the group only syncs
-        for (int w = 0; w < NW; ++w) r += s_red[buf][sl * NW + w][v];
-      buf ^= 1;
+  // Sums over the sample's instants, one 64-instant block at a time: the
+  // blocks (slot u of wave wi is block wi IPL + u) are reduced on their own
+  // and added in block order, so the result is the same for IPL 1 and 2.
+  const int B = NW * IPL, Beff = (T + kWave - 1) / kWave;
+  // r: this lane's block sums of value `col`; lanes with `write` publish them.
+  auto combine = [&](const float (&r)[IPL], bool write, int col) -> float {
+    if (Beff == 1) return r[0];  // one block: slot 0 of wave 0
+    float acc = 0.f;
+    if (NW == 1) {
+#pragma unroll
+      for (int u = 0; u < IPL; ++u)
+        if (u < Beff) acc += r[u];
+      return acc;
     }
-    return r;
+    if (write) {
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) s_red[buf][wave * IPL + u][col] = r[u];
+    }
+    __syncthreads();
+    if (sl < spb)  // a wave beyond the last sample of the group only syncs
+      for (int b = 0; b < Beff; ++b) acc += s_red[buf][sl * B + b][col];
+    return acc;
+  };
+  Corr cr[IPL];
+  auto pass = [&]() -> float {
+    target_pass<IPL>(L, S, zs, obs, npair, T, tt, tv, da_prev, cr);
+    float r[IPL];
+#pragma unroll
+    for (int u = 0; u < IPL; ++u) {
+      float g[16];
+      g_of(L[u], cr[u], g);
+      r[u] = reduce16(g, lane);
+    }
+    const float acc = combine(r, (lane & 3) == 0, v);
+    if (NW > 1) buf ^= 1;
+    return acc;
   };
 
-  float g[16];
-  target_pass(L, S, zs, obs, npair, T, tt, tv, da_prev, g);
-  float Gv = reduce_sample(g);
+  float Gv = pass();
 
   const int K = P.K;
   for (int k = 1; k <= K; ++k) {
@@ -713,31 +777,21 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 #pragma unroll
     for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
     if (k < K) {
-      target_pass(L, S, zs, obs, npair, T, tt, tv, da_prev, g);
-      Gv = reduce_sample(g);
+      Gv = pass();
       mu = fmaf(0.5f * S.rho, Gv, mu);  // eq. update_lagrange
     }
   }
 
-  // Residual and upper cost of xi* = xi^K.
-  float rr, cc;
-  residual_pass(L, S, zs, obs, npair, T, tt, tv, rr, cc);
-  rr = wave_sum(rr);
-  cc = wave_sum(cc);
-  if (NW > 1) {
-    if (lane == 0) {
-      s_red[buf][wave][0] = rr;
-      s_red[buf][wave][1] = cc;
-    }
-    __syncthreads();
-    rr = 0.f;
-    cc = 0.f;
-    if (sl < spb)
-      for (int w = 0; w < NW; ++w) {
-        rr += s_red[buf][sl * NW + w][0];
-        cc += s_red[buf][sl * NW + w][1];
-      }
+  // Residual and upper cost of xi* = xi^K, per block as above.
+  float rb[IPL], cb[IPL];
+#pragma unroll
+  for (int u = 0; u < IPL; ++u) {
+    residual_at(eval_traj(L[u], zs, S.vx0), S, obs, npair, T, tt[u], tv[u], rb[u], cb[u]);
+    rb[u] = wave_sum(rb[u]);
+    cb[u] = wave_sum(cb[u]);
   }
+  const float rr = combine(rb, lane == 0, 0);
+  const float cc = combine(cb, lane == 0, 1);
 
   if (!active) return;
   const size_t row = slot_off + j;
@@ -1586,12 +1640,14 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   }
 }
 
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, size_t lds, hipStream_t st,
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, size_t lds, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1) {
+  if (ipl != 1 && ipl != 2) return hipErrorInvalidValue;
+  auto kern = ipl == 1 ? lower_kernel<1> : lower_kernel<2>;
   if (ev0)
-    hipExtLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), (uint32_t)lds, st, ev0, ev1, 0, a, p);
+    hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(kBlock), (uint32_t)lds, st, ev0, ev1, 0, a, p);
   else
-    hipLaunchKernelGGL(lower_kernel, dim3(nblocks), dim3(kBlock), lds, st, a, p);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kBlock), lds, st, a, p);
   return hipGetLastError();
 }
 hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, int T, size_t lds,

@@ -88,6 +88,18 @@ def test_lower_parity_ragged_shapes(orc, pl, N, T, M):
     run_case(orc, pl, h, par, req, p, "ragged")
 
 
+@pytest.mark.parametrize("T,M", [(100, 10), (200, 6)])
+def test_lower_parity_two_instants_per_lane(orc, pl, T, M):
+    """2048 samples fill a launch enough for two horizon instants per lane."""
+    N, K = 2048, 12
+    par = orc.default_params(T=T, M=M, K=K)
+    h = make_handle(pl, [T], [M], K, max_N=N)
+    s = workload.scene(7, 9000 + T, M)
+    req = pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed)
+    p = orc.sample(par, s.seed, 0, N, True)
+    run_case(orc, pl, h, par, req, p, "two instants per lane")
+
+
 def test_lower_parity_general_ego_and_curved_road(orc, pl):
     """Nonzero x0, lateral velocity and accelerations, curved road (the
     centripetal clip of step clip_d_v), Gaussian samples."""

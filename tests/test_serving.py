@@ -126,3 +126,21 @@ def test_served_rejects_bad_requests_and_mixing(pl):
     assert e.value.status == pl.PLAN_E_BUSY
     drain(pl, h, [t])
     assert pl.plan_solve_batch(h, [reqs[1]])[0].status == 0
+
+
+@pytest.mark.parametrize("T", [100, 200])
+def test_instants_per_lane_do_not_change_results(pl, T):
+    """A small launch runs one horizon instant per lane, a large one two; the
+    sums are formed per 64-instant block in a fixed order, so every request's
+    result is bitwise the same either way (here: a 64-sample request alone =
+    one per lane, inside a batch of 3 x 4096 samples = two per lane)."""
+    M = 10
+    cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=10, upper_iters=2, max_N=4096, max_requests=4)
+    h = pl.plan_create(cfg)
+    reqs = []
+    for i, N in enumerate([4096, 4096, 4096, 64]):
+        s = workload.scene(4, 400 + i, M)
+        reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
+    big = pl.plan_solve_batch(h, reqs)
+    alone = pl.plan_solve_batch(h, [reqs[3]])[0]
+    assert same(alone, big[3])
