@@ -541,6 +541,27 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
     }
   }
   ls.ngroups = nkeys;
+  // VALU mode: the horizon classes need launches of their own only when the
+  // longer class runs two instants per lane; otherwise one launch of one
+  // instant per lane takes every request, whatever its T.
+  if (!mf && nkeys > 1 && ls.grp[nkeys - 1].ipl == 1) {
+    LaunchSet::Group all;
+    all.act_off = 0;
+    all.n = n;
+    all.T = 1;
+    int blocks = 0;
+    for (int i = 0; i < n; ++i) {
+      const ReqDesc &d = h->h_desc[act[i]];
+      prefix[i] = blocks;
+      blocks += blocks_for(d.N, d.T, false, 1);
+      all.lds = std::max(all.lds, lds_bytes(d.M, d.T, false));
+    }
+    prefix[n] = blocks;
+    all.nblocks = blocks;
+    ls.grp[0] = all;
+    ls.ngroups = 1;
+    return;
+  }
   // A light matrix-core load runs all horizons in one launch shaped for the
   // longest (waves without a tile pair only join the barriers), so its
   // groups do not wait for each other; the arithmetic per request is the
