@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("frac_ces", C.c_double), ("frac_es", C.c_double),
         ("lane_c", C.c_double * 3), ("lane_sigma", C.c_double),
         ("vd_lo", C.c_double), ("vd_hi", C.c_double),
+        ("behaviour", C.c_int), ("sampler", C.c_int),
     ]
 
 
@@ -97,7 +98,7 @@ def _load():
     lib.orc_lower_cost.argtypes = [P, _PD, _PD]
     lib.orc_lower_cost.restype = C.c_double
     lib.orc_step1.argtypes = [P, S, _PD, C.c_int, _PD]
-    lib.orc_project.argtypes = [P, S, _PD, C.c_int, _PD, _PD]
+    lib.orc_project.argtypes = [P, S, _PD, _PD, C.c_int, _PD, _PD]
     lib.orc_targets.argtypes = [P, S, _PD, _PD, _PD, _PD, _PD]
     lib.orc_residual_cost.argtypes = [P, S, _PD, C.c_int, _PD, _PD]
     lib.orc_select.argtypes = [_PD, _PD, C.c_int, C.c_int, C.c_int, _PI, _PI, _PD]
@@ -196,14 +197,19 @@ def step1(par: Params, scene: Scene, p) -> np.ndarray:
     return out
 
 
-def project(par: Params, scene: Scene, xi_bar, return_iterates: bool = False):
+def project(par: Params, scene: Scene, xi_bar, return_iterates: bool = False, p=None):
+    """Alg. 2 for every row of xi_bar. p (N x 8, the samples) is needed with
+    goal positions (behaviour 1): their final boundary rows come from it."""
     xb = _f64(xi_bar).reshape(-1, NX)
     N = xb.shape[0]
     out = np.zeros((N, NX))
     it = np.zeros((N, par.K + 1, NX)) if return_iterates else None
+    pp = _f64(p).reshape(N, NP) if p is not None else None
     sc = scene.c()
-    _load().orc_project(C.byref(par), C.byref(sc), _pd(xb), N, _pd(out),
-                        _pd(it) if it is not None else None)
+    rc = _load().orc_project(C.byref(par), C.byref(sc), _pd(xb), _pd(pp) if pp is not None else None, N,
+                             _pd(out), _pd(it) if it is not None else None)
+    if rc != 0:
+        raise ValueError("oracle project: goal positions need the samples p")
     return (out, it) if return_iterates else out
 
 

@@ -34,8 +34,8 @@
 #define NC ORC_NC
 #define NX ORC_NX
 #define NP ORC_NP
-#define NEQ ORC_NEQ
-#define NKKT (NX + NEQ)
+#define NEQ_MAX ORC_NEQ_MAX
+#define NKKT_MAX (NX + NEQ_MAX)
 #define DEG 10 /* polynomial order, Sec. V-A */
 #define NSEG 4 /* set-points per axis, Sec. V-A */
 
@@ -79,7 +79,13 @@ void orc_default_params(orc_params *par) {
   par->lane_sigma = 0.3;
   par->vd_lo = 5.0;
   par->vd_hi = 25.0;
+  par->behaviour = 0;
+  par->sampler = 0;
 }
+
+/* Equality rows: the 7 of the set-point reading, plus x(t_f) and y(t_f)
+ * with goal positions. */
+static int neq_of(const orc_params *par) { return par->behaviour ? 9 : 7; }
 
 static int round_half_up(double v) { return (int)floor(v + 0.5); }
 
@@ -237,15 +243,14 @@ static void basis_free(basis_t *B) {
   free(B->t);
 }
 
-/* Equality constraints A_eq xi = b (eqs. boundary_cond_initial and the
- * lateral part of final_boundary): x(0), xdot(0), xddot(0), y(0), ydot(0),
- * yddot(0), ydot(t_f) = 0. (reading: the goal positions x_f, y_f are not
- * behavioural inputs in the experiments of Sec. V-A, so only the final
- * lateral velocity is constrained.) */
-static void build_Aeq(const basis_t *B, const orc_scene *sc, double *A,
-                      double *b) {
-  int T = B->T;
-  memset(A, 0, sizeof(double) * NEQ * NX);
+/* Equality constraints A_eq xi = b (eqs. boundary_cond_initial and
+ * final_boundary): x(0), xdot(0), xddot(0), y(0), ydot(0), yddot(0),
+ * ydot(t_f) = 0, and with goal positions (behaviour 1) x(t_f) = x_f,
+ * y(t_f) = y_f. (reading: the set-point experiments of Sec. V-A have no goal
+ * positions, so there only the final lateral velocity is constrained.) */
+static int build_Aeq(const basis_t *B, const orc_params *par, double *A) {
+  int T = B->T, neq = neq_of(par);
+  memset(A, 0, sizeof(double) * NEQ_MAX * NX);
   for (int i = 0; i < NC; ++i) {
     A[0 * NX + i] = B->W[0 * NC + i];
     A[1 * NX + i] = B->Wd[0 * NC + i];
@@ -254,15 +259,29 @@ static void build_Aeq(const basis_t *B, const orc_scene *sc, double *A,
     A[4 * NX + NC + i] = B->Wd[0 * NC + i];
     A[5 * NX + NC + i] = B->Wdd[0 * NC + i];
     A[6 * NX + NC + i] = B->Wd[(T - 1) * NC + i];
+    if (neq == 9) {
+      A[7 * NX + i] = B->W[(T - 1) * NC + i];
+      A[8 * NX + NC + i] = B->W[(T - 1) * NC + i];
+    }
   }
-  if (b) {
-    b[0] = sc->ego[0];
-    b[1] = sc->ego[2];
-    b[2] = sc->ego[4];
-    b[3] = sc->ego[1];
-    b[4] = sc->ego[3];
-    b[5] = sc->ego[5];
-    b[6] = 0.0;
+  return neq;
+}
+
+/* Right-hand side b of A_eq xi = b: the ego state b_0 and the final values;
+ * with goals x_f = x0 + p[0] (measured from the ego, as all positions the
+ * planner sees, Sec. V-A) and y_f = p[1]. */
+static void eq_rhs(const orc_params *par, const orc_scene *sc, const double *p,
+                   double *b) {
+  b[0] = sc->ego[0];
+  b[1] = sc->ego[2];
+  b[2] = sc->ego[4];
+  b[3] = sc->ego[1];
+  b[4] = sc->ego[3];
+  b[5] = sc->ego[5];
+  b[6] = 0.0;
+  if (par->behaviour) {
+    b[7] = sc->ego[0] + p[0];
+    b[8] = p[1];
   }
 }
 
@@ -290,8 +309,10 @@ static void cost_rows(const orc_params *par, const basis_t *B, const double *p,
     const double *W = B->W + k * NC, *Wd = B->Wd + k * NC,
                  *Wdd = B->Wdd + k * NC;
     int sg = segment_of(k, T);
-    double y_d = p[sg];
-    double v_d = p[NSEG + sg];
+    /* with goal positions p holds no set-points: c_l and c_v drop out */
+    int setpoints = !par->behaviour;
+    double y_d = setpoints ? p[sg] : 0.0;
+    double v_d = setpoints ? p[NSEG + sg] : 0.0;
     cost_row *r;
     /* c_s, x part: xddot^2 */
     r = &rows[4 * k + 0];
@@ -311,13 +332,13 @@ static void cost_rows(const orc_params *par, const basis_t *B, const double *p,
     for (int i = 0; i < NC; ++i)
       r->a[NC + i] = Wdd[i] + par->k_p * W[i] + par->k_v * Wd[i];
     r->beta = par->k_p * y_d;
-    r->w = par->w_l;
+    r->w = setpoints ? par->w_l : 0.0;
     /* c_v: (xddot + k_p (xdot - v_d))^2 */
     r = &rows[4 * k + 3];
     memset(r->a, 0, sizeof(r->a));
     for (int i = 0; i < NC; ++i) r->a[i] = Wdd[i] + par->k_p * Wd[i];
     r->beta = par->k_p * v_d;
-    r->w = par->w_v;
+    r->w = setpoints ? par->w_v : 0.0;
   }
 }
 
@@ -348,10 +369,11 @@ int orc_step1(const orc_params *par, const orc_scene *sc, const double *p,
   basis_t B;
   basis_init(&B, par);
   int T = B.T;
-  double *K = (double *)calloc(NKKT * NKKT, sizeof(double));
-  int *piv = (int *)malloc(sizeof(int) * NKKT);
-  double Aeq[NEQ * NX], beq[NEQ];
-  build_Aeq(&B, sc, Aeq, beq);
+  double Aeq[NEQ_MAX * NX];
+  int neq = build_Aeq(&B, par, Aeq);
+  int nk = NX + neq;
+  double *K = (double *)calloc((size_t)nk * nk, sizeof(double));
+  int *piv = (int *)malloc(sizeof(int) * nk);
 
   /* Q does not depend on p: build it with any p. */
   double pz[NP] = {0};
@@ -360,14 +382,14 @@ int orc_step1(const orc_params *par, const orc_scene *sc, const double *p,
   for (int r = 0; r < 4 * T; ++r)
     for (int i = 0; i < NX; ++i)
       for (int j = 0; j < NX; ++j)
-        K[i * NKKT + j] += 2.0 * rows[r].w * rows[r].a[i] * rows[r].a[j];
-  for (int e = 0; e < NEQ; ++e)
+        K[i * nk + j] += 2.0 * rows[r].w * rows[r].a[i] * rows[r].a[j];
+  for (int e = 0; e < neq; ++e)
     for (int i = 0; i < NX; ++i) {
-      K[(NX + e) * NKKT + i] = Aeq[e * NX + i];
-      K[i * NKKT + NX + e] = Aeq[e * NX + i];
+      K[(NX + e) * nk + i] = Aeq[e * NX + i];
+      K[i * nk + NX + e] = Aeq[e * NX + i];
     }
   free(rows);
-  int rc = lu_factor(NKKT, K, piv);
+  int rc = lu_factor(nk, K, piv);
   if (rc != 0) {
     free(K);
     free(piv);
@@ -378,15 +400,17 @@ int orc_step1(const orc_params *par, const orc_scene *sc, const double *p,
   int nthreads = g_threads;
 #pragma omp parallel for schedule(static) num_threads(nthreads)
   for (int j = 0; j < N; ++j) {
+    const double *pj = p + (size_t)j * NP;
     cost_row *rw = (cost_row *)malloc(sizeof(cost_row) * 4 * T);
-    cost_rows(par, &B, p + (size_t)j * NP, rw);
-    double rhs[NKKT];
+    cost_rows(par, &B, pj, rw);
+    double rhs[NKKT_MAX], beq[NEQ_MAX];
     memset(rhs, 0, sizeof(rhs));
     for (int r = 0; r < 4 * T; ++r)
       for (int i = 0; i < NX; ++i)
         rhs[i] += 2.0 * rw[r].w * rw[r].beta * rw[r].a[i]; /* -q */
-    for (int e = 0; e < NEQ; ++e) rhs[NX + e] = beq[e];
-    lu_solve(NKKT, K, piv, rhs);
+    eq_rhs(par, sc, pj, beq);
+    for (int e = 0; e < neq; ++e) rhs[NX + e] = beq[e];
+    lu_solve(nk, K, piv, rhs);
     memcpy(xi_bar + (size_t)j * NX, rhs, sizeof(double) * NX);
     free(rw);
   }
@@ -410,7 +434,7 @@ typedef struct proj_t {
   double *xo, *yo; /* M x T neighbour trajectories */
   double *KP;   /* LU of [[I + rho F^T F + rho G^T G, A^T], [A, 0]] */
   int *piv;
-  double beq[NEQ];
+  int neq, nk;  /* equality rows, KKT size NX + neq */
 } proj_t;
 
 static void proj_init(proj_t *P, const orc_params *par, const orc_scene *sc) {
@@ -462,31 +486,32 @@ static void proj_init(proj_t *P, const orc_params *par, const orc_scene *sc) {
   /* KKT matrix of eq. split_xy: stationarity of eq. aug_lag in xi gives
    * (I + rho F^T F + rho G^T G) xi + A^T nu = xi_bar + lambda + rho F^T h
    * + rho G^T (e - s). */
-  double Aeq[NEQ * NX];
-  build_Aeq(&P->B, sc, Aeq, P->beq);
-  P->KP = (double *)calloc(NKKT * NKKT, sizeof(double));
-  for (int i = 0; i < NX; ++i) P->KP[i * NKKT + i] = 1.0;
+  double Aeq[NEQ_MAX * NX];
+  P->neq = build_Aeq(&P->B, par, Aeq);
+  int nk = P->nk = NX + P->neq;
+  P->KP = (double *)calloc((size_t)nk * nk, sizeof(double));
+  for (int i = 0; i < NX; ++i) P->KP[i * nk + i] = 1.0;
   for (int r = 0; r < P->nF; ++r)
     for (int i = 0; i < NX; ++i) {
       double fi = P->F[(size_t)r * NX + i];
       if (fi == 0.0) continue;
       for (int j = 0; j < NX; ++j)
-        P->KP[i * NKKT + j] += par->rho * fi * P->F[(size_t)r * NX + j];
+        P->KP[i * nk + j] += par->rho * fi * P->F[(size_t)r * NX + j];
     }
   for (int r = 0; r < 2 * T; ++r)
     for (int i = 0; i < NX; ++i) {
       double gi = P->G[(size_t)r * NX + i];
       if (gi == 0.0) continue;
       for (int j = 0; j < NX; ++j)
-        P->KP[i * NKKT + j] += par->rho * gi * P->G[(size_t)r * NX + j];
+        P->KP[i * nk + j] += par->rho * gi * P->G[(size_t)r * NX + j];
     }
-  for (int e2 = 0; e2 < NEQ; ++e2)
+  for (int e2 = 0; e2 < P->neq; ++e2)
     for (int i = 0; i < NX; ++i) {
-      P->KP[(NX + e2) * NKKT + i] = Aeq[e2 * NX + i];
-      P->KP[i * NKKT + NX + e2] = Aeq[e2 * NX + i];
+      P->KP[(NX + e2) * nk + i] = Aeq[e2 * NX + i];
+      P->KP[i * nk + NX + e2] = Aeq[e2 * NX + i];
     }
-  P->piv = (int *)malloc(sizeof(int) * NKKT);
-  lu_factor(NKKT, P->KP, P->piv);
+  P->piv = (int *)malloc(sizeof(int) * nk);
+  lu_factor(nk, P->KP, P->piv);
 }
 
 static void proj_free(proj_t *P) {
@@ -605,8 +630,8 @@ static void acc_norm_clip(const proj_t *P, const double *xi, double *da) {
 /* Alg. 2 for one sample (reading of the unprinted initialisation: xi^0 =
  * xi_bar, lambda^0 = 0, targets from xi_bar with d_a^{-1} = clip(|a|, 0,
  * a_max); the returned iterate is the last xi-update). */
-static void project_one(const proj_t *P, const double *xi_bar, double *xi_out,
-                        double *xi_iter) {
+static void project_one(const proj_t *P, const double *xi_bar, const double *p,
+                        double *xi_out, double *xi_iter) {
   const orc_params *par = P->par;
   int T = P->T, nF = P->nF, K = par->K;
   double rho = par->rho;
@@ -615,7 +640,8 @@ static void project_one(const proj_t *P, const double *xi_bar, double *xi_out,
   double *da = (double *)malloc(sizeof(double) * T);
   double *da_prev = (double *)malloc(sizeof(double) * T);
   double *Fx = (double *)malloc(sizeof(double) * nF);
-  double xi[NX], lam[NX], rhs[NKKT];
+  double xi[NX], lam[NX], rhs[NKKT_MAX], beq[NEQ_MAX];
+  eq_rhs(par, P->sc, p, beq);
 
   memcpy(xi, xi_bar, sizeof(xi));
   memset(lam, 0, sizeof(lam));
@@ -637,8 +663,8 @@ static void project_one(const proj_t *P, const double *xi_bar, double *xi_out,
       const double *Gr = P->G + (size_t)r * NX;
       for (int i = 0; i < NX; ++i) rhs[i] += Gr[i] * er;
     }
-    for (int e2 = 0; e2 < NEQ; ++e2) rhs[NX + e2] = P->beq[e2];
-    lu_solve(NKKT, P->KP, P->piv, rhs);
+    for (int e2 = 0; e2 < P->neq; ++e2) rhs[NX + e2] = beq[e2];
+    lu_solve(P->nk, P->KP, P->piv, rhs);
     memcpy(xi, rhs, sizeof(xi));
     if (xi_iter) memcpy(xi_iter + (size_t)k * NX, xi, sizeof(xi));
 
@@ -675,14 +701,17 @@ static void project_one(const proj_t *P, const double *xi_bar, double *xi_out,
 }
 
 int orc_project(const orc_params *par, const orc_scene *sc,
-                const double *xi_bar, int N, double *xi_star, double *xi_iter) {
+                const double *xi_bar, const double *p, int N, double *xi_star,
+                double *xi_iter) {
+  if (par->behaviour && p == NULL) return -1;
   proj_t P;
   proj_init(&P, par, sc);
   int nthreads = g_threads;
   size_t stride_it = (size_t)(par->K + 1) * NX;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
   for (int j = 0; j < N; ++j)
-    project_one(&P, xi_bar + (size_t)j * NX, xi_star + (size_t)j * NX,
+    project_one(&P, xi_bar + (size_t)j * NX, p ? p + (size_t)j * NP : NULL,
+                xi_star + (size_t)j * NX,
                 xi_iter ? xi_iter + (size_t)j * stride_it : NULL);
   proj_free(&P);
   return 0;
@@ -884,10 +913,14 @@ static void philox_block(uint64_t seed, int j, int l, int blk, uint32_t w[4]) {
   orc_philox4x32_10(ctr, key, w);
 }
 
-/* Initial sampler, a stand-in for the learned CVAE sampler of Sec. III-D:
- * one lane centre per sample (uniform over 3) plus N(0, lane_sigma^2) on
- * each of the 4 lateral set-points; each velocity set-point U(vd_lo, vd_hi].
- * Its exact moments seed the first update. */
+/* Initial sampler, a stand-in for the learned CVAE sampler of Sec. III-D.
+ * Set-points: one lane centre per sample (uniform over 3) plus
+ * N(0, lane_sigma^2) on each of the 4 lateral set-points; each velocity
+ * set-point U(vd_lo, vd_hi]. Goal positions: y_f the same lane draw (one
+ * set-point's worth), x_f - x0 = t_f U(vd_lo, vd_hi] (the distance covered at
+ * a velocity drawn like a set-point). Its exact moments seed the first
+ * update; the fixed grid (sampler 1) discretises the same distribution and
+ * uses the same moments. */
 void orc_initial_moments(const orc_params *par, double *mu, double *Sigma) {
   double mc = (par->lane_c[0] + par->lane_c[1] + par->lane_c[2]) / 3.0;
   double vc = 0.0;
@@ -896,6 +929,14 @@ void orc_initial_moments(const orc_params *par, double *mu, double *Sigma) {
   double vm = 0.5 * (par->vd_lo + par->vd_hi);
   double vv = (par->vd_hi - par->vd_lo) * (par->vd_hi - par->vd_lo) / 12.0;
   memset(Sigma, 0, sizeof(double) * NP * NP);
+  memset(mu, 0, sizeof(double) * NP);
+  if (par->behaviour) {
+    mu[0] = par->t_f * vm;
+    Sigma[0] = par->t_f * par->t_f * vv;
+    mu[1] = mc;
+    Sigma[1 * NP + 1] = vc + par->lane_sigma * par->lane_sigma;
+    return;
+  }
   for (int a = 0; a < NSEG; ++a) {
     mu[a] = mc;
     mu[NSEG + a] = vm;
@@ -905,19 +946,49 @@ void orc_initial_moments(const orc_params *par, double *mu, double *Sigma) {
   }
 }
 
+/* Fixed grid of the first upper iteration (MPC-Grid of Sec. V-A samples a
+ * pre-specified grid): sample j takes lane centre j mod 3 and the velocity
+ * vd_lo + (vd_hi - vd_lo) (floor(j/3) + 1/2) / ceil(N/3), held over the
+ * whole horizon (set-points) or as the goal t_f v ahead in that lane. */
+static void grid_point(const orc_params *par, int j, int N, double *pj) {
+  int nb = (N + 2) / 3;
+  double lane = par->lane_c[j % 3];
+  double v = par->vd_lo + (par->vd_hi - par->vd_lo) * ((double)(j / 3) + 0.5) / (double)nb;
+  memset(pj, 0, sizeof(double) * NP);
+  if (par->behaviour) {
+    pj[0] = par->t_f * v;
+    pj[1] = lane;
+    return;
+  }
+  for (int m = 0; m < NSEG; ++m) {
+    pj[m] = lane;
+    pj[NSEG + m] = v;
+  }
+}
+
 void orc_sample(const orc_params *par, uint64_t seed, int l, int N,
                 int structured, const double *mu, const double *Lc, double *p) {
   for (int j = 0; j < N; ++j) {
     uint32_t w[12];
+    double *pj = p + (size_t)j * NP;
+    if (structured && par->sampler == 1) {
+      grid_point(par, j, N, pj);
+      continue;
+    }
     philox_block(seed, j, l, 0, w);
     philox_block(seed, j, l, 1, w + 4);
-    double *pj = p + (size_t)j * NP;
     if (structured) {
       philox_block(seed, j, l, 2, w + 8);
       double n[4];
       box_muller(w[0], w[1], &n[0], &n[1]);
       box_muller(w[2], w[3], &n[2], &n[3]);
       int lane = (int)(((uint64_t)w[8] * 3u) >> 32);
+      if (par->behaviour) {
+        memset(pj, 0, sizeof(double) * NP);
+        pj[0] = par->t_f * (par->vd_lo + (par->vd_hi - par->vd_lo) * unit_open0(w[4]));
+        pj[1] = par->lane_c[lane] + par->lane_sigma * n[0];
+        continue;
+      }
       for (int m = 0; m < NSEG; ++m) {
         pj[m] = par->lane_c[lane] + par->lane_sigma * n[m];
         pj[NSEG + m] =
@@ -926,9 +997,14 @@ void orc_sample(const orc_params *par, uint64_t seed, int l, int N,
     } else {
       double z[NP];
       for (int m = 0; m < NP; m += 2) box_muller(w[m], w[m + 1], &z[m], &z[m + 1]);
+      /* with goal positions only the first two inputs are drawn */
+      int nd = par->behaviour ? 2 : NP;
       for (int a = 0; a < NP; ++a) {
-        double v = mu[a];
-        for (int b = 0; b <= a; ++b) v += Lc[a * NP + b] * z[b];
+        double v = 0.0;
+        if (a < nd) {
+          v = mu[a];
+          for (int b = 0; b <= a; ++b) v += Lc[a * NP + b] * z[b];
+        }
         pj[a] = v;
       }
     }
@@ -970,7 +1046,7 @@ int orc_plan(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
     }
     orc_sample(par, seed, l, N, draw_structured, mu, Lc, p);
     orc_step1(par, sc, p, N, xb);
-    orc_project(par, sc, xb, N, xs, NULL);
+    orc_project(par, sc, xb, p, N, xs, NULL);
     orc_residual_cost(par, sc, xs, N, r, cu);
     orc_select(r, cu, N, n, q, ces, es, c_es);
     double mu_n[NP], S_n[NP * NP];

@@ -29,6 +29,7 @@ extern "C" {
 #define ORC_NX 22 /* coefficients of xi                              */
 #define ORC_NP 8  /* behavioural inputs                              */
 #define ORC_NEQ 7 /* equality rows: 3 initial per axis + final ydot   */
+#define ORC_NEQ_MAX 9 /* plus x(t_f) = x_f, y(t_f) = y_f with goals    */
 
 typedef struct orc_params {
   int T;          /* samples of the horizon, t_k = k t_f/(T-1)          */
@@ -48,6 +49,11 @@ typedef struct orc_params {
   double lane_c[3];         /* initial sampler: lateral lane centres     */
   double lane_sigma;        /* initial sampler: offset noise (std)       */
   double vd_lo, vd_hi;      /* initial sampler: U(vd_lo, vd_hi]          */
+  int behaviour; /* 0: p = [y_d1..4, v_d1..4] (set-points, Sec. V-A);
+                    1: p = [x_f - x0, y_f, 0 ...] (goal positions, eq.
+                    behaviour_param and eq. final_boundary)             */
+  int sampler;   /* 0: random initial sampler; 1: fixed grid at the
+                    first upper iteration                              */
 } orc_params;
 
 typedef struct orc_scene {
@@ -72,10 +78,12 @@ double orc_lower_cost(const orc_params *par, const double *p, const double *xi);
 int orc_step1(const orc_params *par, const orc_scene *sc, const double *p,
               int N, double *xi_bar);
 
-/* Step 2 of Alg. 1 by Alg. 2. xi_iter (nullable) receives N x (K+1) x 22:
- * the initial iterate and every xi-update. */
+/* Step 2 of Alg. 1 by Alg. 2. p (N x 8) gives the goal positions of the
+ * final boundary rows (needed with behaviour = 1, else nullable). xi_iter
+ * (nullable) receives N x (K+1) x 22: the initial iterate and every
+ * xi-update. */
 int orc_project(const orc_params *par, const orc_scene *sc,
-                const double *xi_bar, int N, double *xi_star,
+                const double *xi_bar, const double *p, int N, double *xi_star,
                 double *xi_iter);
 
 /* One target pass of Alg. 2 (steps split_alpha_o .. update_slack) for one
