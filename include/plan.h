@@ -88,6 +88,31 @@ typedef enum plan_precision {
 } plan_precision;
 
 /*
+ * Behavioural inputs p (eq. behaviour_param, Sec. II-B). Both use the
+ * 8 slots of p (and of mu, Sigma):
+ *   PLAN_BEHAV_SETPOINTS  p = [y_d1..y_d4, v_d1..v_d4]: lateral offset and
+ *                         velocity set-points of 4 equal horizon parts,
+ *                         tracked by c_l and c_v of the lower-level cost
+ *                         (Sec. V-A); the final boundary is ydot(t_f) = 0.
+ *   PLAN_BEHAV_GOALS      p = [x_f - x0, y_f, 0, ..., 0]: a goal position
+ *                         (the Batch-MPC baseline of Sec. V-A), x_f measured
+ *                         from the ego like every position the planner sees;
+ *                         the lower-level cost is the smoothness term c_s
+ *                         alone and the final boundary is eq. final_boundary
+ *                         (x, y, ydot)(t_f) = (x_f, y_f, 0). Only p[0], p[1]
+ *                         are drawn; the other slots stay 0.
+ * The initial sampler of a request without a warm start draws, per sample,
+ * one lane centre of lane_c plus N(0, lane_sigma^2) for the lateral inputs
+ * and U(vd_lo, vd_hi] for the velocities (goal: x_f - x0 = t_f times such a
+ * velocity) (plan_sampler_t RANDOM), or takes sample j from a fixed grid
+ * (GRID: lane centre j mod 3, velocity at the midpoint of bin floor(j/3) of
+ * ceil(N/3) equal bins of (vd_lo, vd_hi], held over the horizon). With
+ * upper_iters = 1 the grid gives the MPC-Grid baseline of Sec. V-A.
+ */
+typedef enum plan_behaviour { PLAN_BEHAV_SETPOINTS = 0, PLAN_BEHAV_GOALS = 1 } plan_behaviour;
+typedef enum plan_sampler_t { PLAN_SAMPLER_RANDOM = 0, PLAN_SAMPLER_GRID = 1 } plan_sampler_t;
+
+/*
  * Configuration. plan_config_init() fills the defaults; every point the paper
  * leaves open is a field here.
  *   T_set/M_set     horizon lengths and obstacle counts that get precomputed
@@ -139,6 +164,8 @@ typedef struct plan_config {
   double lane_sigma, vd_lo, vd_hi;
   int32_t precision;
   int32_t trace; /* nonzero: keep per-iteration elite sets and mu, Sigma */
+  int32_t behaviour; /* plan_behaviour */
+  int32_t sampler;   /* plan_sampler_t: initial sampler */
   int64_t sample_budget; /* sample rows resident at once (0: max_requests * max_N) */
   void *device_workspace;
   size_t workspace_bytes;

@@ -20,6 +20,8 @@ PLAN_OK, PLAN_E_INVALID, PLAN_E_NOMEM, PLAN_E_DEVICE, PLAN_E_BUSY, PLAN_E_UNSUPP
 PLAN_PREC_FP32, PLAN_PREC_FP16_SPLIT = 0, 1
 PLAN_F_INFEASIBLE, PLAN_F_WARM = 1, 2
 PLAN_MPC_SAMPLER, PLAN_MPC_WARM = 0, 1
+PLAN_BEHAV_SETPOINTS, PLAN_BEHAV_GOALS = 0, 1
+PLAN_SAMPLER_RANDOM, PLAN_SAMPLER_GRID = 0, 1
 NC, NX, NP = 11, 22, 8
 MAX_N, MAX_M, MAX_T = 4096, 32, 256
 
@@ -48,6 +50,7 @@ class plan_config(C.Structure):
         ("lane_c", C.c_double * 3),
         ("lane_sigma", C.c_double), ("vd_lo", C.c_double), ("vd_hi", C.c_double),
         ("precision", C.c_int32), ("trace", C.c_int32),
+        ("behaviour", C.c_int32), ("sampler", C.c_int32),
         ("sample_budget", C.c_int64),
         ("device_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("stream", C.c_void_p),

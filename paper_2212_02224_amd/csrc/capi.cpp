@@ -198,6 +198,9 @@ const char *validate_config(const plan_config &c) {
   elite_sizes(c, c.max_N, n, q);
   if (n > kMaxCes) return "ConstraintEliteSet larger than 1024 samples is not supported";
   if (q > kMaxEs) return "EliteSet larger than 256 samples is not supported";
+  if (c.behaviour != PLAN_BEHAV_SETPOINTS && c.behaviour != PLAN_BEHAV_GOALS) return "unknown behaviour";
+  if (c.sampler != PLAN_SAMPLER_RANDOM && c.sampler != PLAN_SAMPLER_GRID) return "unknown sampler";
+  if (c.behaviour == PLAN_BEHAV_GOALS && !(c.w_s > 0)) return "goal positions need w_s > 0 (the cost is c_s alone)";
   if (c.precision != PLAN_PREC_FP32 && c.precision != PLAN_PREC_FP16_SPLIT) return "unsupported precision";
   if (mfma_mode(c))
     for (int i = 0; i < c.n_T; ++i)
@@ -325,6 +328,8 @@ MethodParams method_params(const plan_config &c) {
   m.vd_hi = c.vd_hi;
   m.K = c.proj_iters;
   m.L = c.upper_iters;
+  m.behaviour = c.behaviour;
+  m.sampler = c.sampler;
   return m;
 }
 
@@ -845,8 +850,10 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     const CostWeights cw{c.k_p, c.k_v, c.w_s, c.w_l, c.w_v};
     for (int i = 0; i < c.n_T; ++i) {
       build_basis(c.T_set[i], c.t_f, bts[i]);
-      build_step1(bts[i], cw, c.t_f, s1[i]);
-      for (int m = 0; m < c.n_M; ++m) build_proj(bts[i], c.M_set[m], c.rho, pj[(size_t)i * c.n_M + m]);
+      const bool goals = c.behaviour == PLAN_BEHAV_GOALS;
+      build_step1(bts[i], cw, c.t_f, goals, s1[i]);
+      for (int m = 0; m < c.n_M; ++m)
+        build_proj(bts[i], c.M_set[m], c.rho, goals, pj[(size_t)i * c.n_M + m]);
     }
   } catch (const std::exception &e) {
     g_create_error = std::string("precompute failed: ") + e.what();

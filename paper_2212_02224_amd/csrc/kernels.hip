@@ -187,7 +187,8 @@ __device__ bool chol8(const double *A, double jitter, double *Lo) {
   return true;
 }
 
-// Exact moments of the structured initial sampler.
+// Exact moments of the structured initial sampler (the fixed grid
+// discretises the same distribution and uses them too).
 __device__ void structured_moments(const MethodParams &P, double *mu, double *sg) {
   double mc = (P.lane_c[0] + P.lane_c[1] + P.lane_c[2]) / 3.0;
   double vc = 0.0;
@@ -196,6 +197,14 @@ __device__ void structured_moments(const MethodParams &P, double *mu, double *sg
   double vm = 0.5 * (P.vd_lo + P.vd_hi);
   double vv = (P.vd_hi - P.vd_lo) * (P.vd_hi - P.vd_lo) / 12.0;
   for (int i = 0; i < 64; ++i) sg[i] = 0.0;
+  if (P.behaviour == PLAN_BEHAV_GOALS) {
+    for (int a = 0; a < 8; ++a) mu[a] = 0.0;
+    mu[0] = P.t_f * vm;
+    sg[0] = P.t_f * P.t_f * vv;
+    mu[1] = mc;
+    sg[9] = vc + P.lane_sigma * P.lane_sigma;
+    return;
+  }
   for (int a = 0; a < 4; ++a) {
     mu[a] = mc;
     mu[4 + a] = vm;
@@ -204,10 +213,62 @@ __device__ void structured_moments(const MethodParams &P, double *mu, double *sg
   }
 }
 
+// Behavioural inputs of sample j (of N) from its normals z, the words wb1 of
+// Philox block 1 and the lane word sel: the structured initial sampler, the
+// fixed grid, or N(mu, chol chol^T); with goal positions only p[0] (x_f - x0)
+// and p[1] (y_f) are drawn and the other slots are 0.
+__device__ __forceinline__ void finish_draw(const MethodParams &P, bool structured, int j, int N, uint32_t sel,
+                                            const float (&z)[8], const uint32_t (&wb1)[4], const double *mu,
+                                            const double *chol, float (&p)[8]) {
+  const bool goals = P.behaviour == PLAN_BEHAV_GOALS;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) p[a] = 0.f;
+  if (structured && P.sampler == PLAN_SAMPLER_GRID) {
+    const int nb = (N + 2) / 3;
+    const double lane = P.lane_c[j % 3];
+    const double v = P.vd_lo + (P.vd_hi - P.vd_lo) * ((double)(j / 3) + 0.5) / (double)nb;
+    if (goals) {
+      p[0] = (float)(P.t_f * v);
+      p[1] = (float)lane;
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        p[m] = (float)lane;
+        p[4 + m] = (float)v;
+      }
+    }
+  } else if (structured) {
+    const int ln = (int)(((uint64_t)sel * 3u) >> 32);
+    const double lc = P.lane_c[ln];
+    if (goals) {
+      const double u = (double)((wb1[0] >> 8) + 1u) * (1.0 / 16777216.0);
+      p[0] = (float)(P.t_f * (P.vd_lo + (P.vd_hi - P.vd_lo) * u));
+      p[1] = (float)(lc + P.lane_sigma * (double)z[0]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        p[m] = (float)(lc + P.lane_sigma * (double)z[m]);
+        const double u = (double)((wb1[m] >> 8) + 1u) * (1.0 / 16777216.0);
+        p[4 + m] = (float)(P.vd_lo + (P.vd_hi - P.vd_lo) * u);
+      }
+    }
+  } else {
+    const int nd = goals ? 2 : 8;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (a >= nd) continue;
+      double s = mu[a];
+#pragma unroll
+      for (int b = 0; b <= a; ++b) s += chol[a * 8 + b] * (double)z[b];
+      p[a] = (float)s;
+    }
+  }
+}
+
 // Sample j of upper iteration l, drawn by one wave: lanes 0-2 each run one
 // Philox block, lanes 0-3 one Box-Muller pair; the eight values are returned
 // uniform across the wave. mu/chol point to LDS (Gaussian draws only).
-__device__ void wave_draw(const MethodParams &P, uint64_t seed, int j, int l, bool structured,
+__device__ void wave_draw(const MethodParams &P, uint64_t seed, int j, int N, int l, bool structured,
                           const double *mu, const double *chol, int lane, float (&p)[8]) {
   uint32_t w[4];
   rng_block(seed, j, l, lane < 3 ? lane : 2, w);
@@ -224,26 +285,10 @@ __device__ void wave_draw(const MethodParams &P, uint64_t seed, int j, int l, bo
     z[2 * m] = bcast(n0, m);
     z[2 * m + 1] = bcast(n1, m);
   }
-  if (structured) {
-    const uint32_t sel = bcastu(w[0], 2);
-    const int ln = (int)(((uint64_t)sel * 3u) >> 32);
-    const double lc = P.lane_c[ln];
+  uint32_t wb1[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      p[m] = (float)(lc + P.lane_sigma * (double)z[m]);
-      const uint32_t wv = bcastu(w[m], 1);
-      const double u = (double)((wv >> 8) + 1u) * (1.0 / 16777216.0);
-      p[4 + m] = (float)(P.vd_lo + (P.vd_hi - P.vd_lo) * u);
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      double s = mu[a];
-#pragma unroll
-      for (int b = 0; b <= a; ++b) s += chol[a * 8 + b] * (double)z[b];
-      p[a] = (float)s;
-    }
-  }
+  for (int m = 0; m < 4; ++m) wb1[m] = bcastu(w[m], 1);
+  finish_draw(P, structured, j, N, bcastu(w[0], 2), z, wb1, mu, chol, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,15 +616,25 @@ __device__ __forceinline__ State6 fixed_part(const float *Bt, int Tp, int tt, co
 }
 
 // Step 1 (eq. over_3 through its affine map): free coefficient v of
-// z_bar = S p' + R b', p' = [y_d, v_d - vx0], b' = (ax0, y0, vy0, ay0).
-__device__ __forceinline__ float step1_coef(const float *S1, const ReqDesc &D, const float (&pin)[8], int v) {
+// z_bar = S p' + R b', b' = (ax0, y0, vy0, ay0), p' = [y_d, v_d - vx0]
+// (set-points) or [x_f - x0 - vx0 t_f, y_f, 0 ...] (goal positions: c10 of x
+// in the frame relative to x0 + vx0 t, and c9 = c10 of y).
+__device__ __forceinline__ float step1_coef(const float *S1, const ReqDesc &D, const MethodParams &P,
+                                            const float (&pin)[8], int v) {
   const float *R1 = S1 + 16 * 8;
   const double vx0 = D.ego[2];
   float pp[8];
+  if (P.behaviour == PLAN_BEHAV_GOALS) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    pp[m] = pin[m];
-    pp[4 + m] = (float)((double)pin[4 + m] - vx0);
+    for (int m = 0; m < 8; ++m) pp[m] = 0.f;
+    pp[0] = (float)((double)pin[0] - vx0 * P.t_f);
+    pp[1] = pin[1];
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      pp[m] = pin[m];
+      pp[4 + m] = (float)((double)pin[4 + m] - vx0);
+    }
   }
   const float bb[4] = {(float)D.ego[4], (float)D.ego[1], (float)D.ego[3], (float)D.ego[5]};
   float zb = 0.f;
@@ -699,7 +754,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 #pragma unroll
     for (int m = 0; m < 8; ++m) pin[m] = active ? A.p[(slot_off + j) * 8 + m] : 0.f;
   } else {
-    wave_draw(P, D.seed, j, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
+    wave_draw(P, D.seed, j, N, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
     if (active && wi == 0 && lane == 0) {
       float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
       dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
@@ -707,7 +762,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     }
   }
 
-  const float zb = step1_coef(A.step1 + (size_t)D.t_idx * kStep1Floats, D, pin, v);
+  const float zb = step1_coef(A.step1 + (size_t)D.t_idx * kStep1Floats, D, P, pin, v);
   float z = zb, mu = 0.f;
   float zs[15];
 #pragma unroll
@@ -882,7 +937,7 @@ __device__ __forceinline__ void coef_operands(f4 z, h4 &bx, h4 &by) {
 // Draw of Alg. 1 for the 16 samples of a wave: lane group g runs Philox block
 // min(g, 2) and Box-Muller pair g of its sample; the same values as
 // wave_draw.
-__device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int l, bool structured,
+__device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int N, int l, bool structured,
                            const double *mu, const double *chol, int lane, float (&p)[8]) {
   const int n = lane & 15, g = lane >> 4;
   uint32_t w[4];
@@ -903,24 +958,7 @@ __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int l, b
 #pragma unroll
   for (int m = 0; m < 4; ++m) wb1[m] = __shfl(w[m], n + 16, 64);
   const uint32_t sel = __shfl(w[0], n + 32, 64);
-  if (structured) {
-    const int ln = (int)(((uint64_t)sel * 3u) >> 32);
-    const double lc = P.lane_c[ln];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      p[m] = (float)(lc + P.lane_sigma * (double)z[m]);
-      const double u = (double)((wb1[m] >> 8) + 1u) * (1.0 / 16777216.0);
-      p[4 + m] = (float)(P.vd_lo + (P.vd_hi - P.vd_lo) * u);
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      double s = mu[a];
-#pragma unroll
-      for (int b = 0; b <= a; ++b) s += chol[a * 8 + b] * (double)z[b];
-      p[a] = (float)s;
-    }
-  }
+  finish_draw(P, structured, j, N, sel, z, wb1, mu, chol, p);
 }
 
 // Dynamic LDS of the matrix-core kernel: basis table [4 NT][kEvInstHalfs],
@@ -1018,7 +1056,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
 #pragma unroll
     for (int m = 0; m < 8; ++m) pin[m] = active ? A.p[(slot_off + j) * 8 + m] : 0.f;
   } else {
-    group_draw(P, D.seed, j, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
+    group_draw(P, D.seed, j, N, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
     if (active && wave == 0 && g == 0) {
       float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
       dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
@@ -1029,7 +1067,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   {
     const float *S1 = A.step1 + (size_t)D.t_idx * kStep1Floats;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) zb[u] = step1_coef(S1, D, pin, 4 * g + u);
+    for (int u = 0; u < 4; ++u) zb[u] = step1_coef(S1, D, P, pin, 4 * g + u);
   }
   f4 z = zb, mu = {0.f, 0.f, 0.f, 0.f};
 

@@ -96,6 +96,7 @@ struct MethodParams {
   double lane_c[3];
   double lane_sigma, vd_lo, vd_hi;
   int32_t K, L;
+  int32_t behaviour, sampler;  // plan_behaviour, plan_sampler_t
 };
 
 // Arguments of the lower-level kernel.

@@ -6,11 +6,15 @@
 //   basis   Bernstein polynomials of order 10 on tau = t / t_f and their first
 //           two time derivatives at t_k = k t_f / (T - 1) (eq. param).
 //   step1   affine map of the Step-1 QP of Alg. 1 restricted to the free
-//           coefficients: z_bar = S p' + R b', with p' = [y_d, v_d - vx0] and
+//           coefficients: z_bar = S p' + R b', with p' = [y_d, v_d - vx0]
+//           (set-points) or [x_f - x0 - vx0 t_f, y_f] (goal positions) and
 //           b' = (ax0, y0, vy0, ay0); x is taken relative to x0 + vx0 t.
 //   proj    inverse of A = N^T N + rho N^T (F^T F + G^T G) N (the xi-update
 //           of Alg. 2, eq. split_xy, in the free coordinates), block diagonal
-//           in x (8 x 8) and y (7 x 7), and D = diag(N^T N).
+//           in x (8 x 8) and y (7 x 7), and D = diag(N^T N). With goal
+//           positions the slots of c10 (x) and c9 = c10 (y) hold the goal:
+//           they are fixed, so their rows and columns of the inverse and
+//           their D are zero and the inverse is that of the reduced A.
 //   mfma    the same basis and inverse as FP16 high/low pairs, laid out as
 //           the per-lane operands of v_mfma_f32_16x16x16_f16 (reduced-
 //           precision lower level).
@@ -142,9 +146,88 @@ void build_basis(int T, double t_f, BasisTable &bt) {
   }
 }
 
+// Step-1 QP with goal positions: minimise sum_k w_s (xddot_k^2 + yddot_k^2)
+// over the coefficients left free by the initial conditions and the final
+// boundary (x, y, ydot)(t_f) = (x_f, y_f, 0) (eq. final_boundary): x c3..c9
+// (slots 0..6; slot 7 = c10 = x_f, relative), y c3..c8 (slots 8..13; slot
+// 14 = c9 = c10 = y_f).
+void build_step1_goals(const BasisTable &bt, const CostWeights &cw, double t_f, Step1Table &st) {
+  const int T = bt.T;
+  const double n = kDeg;
+  st.S.assign(16 * 8, 0.0);
+  st.R.assign(16 * 4, 0.0);
+  // ---- x axis (relative frame): c0 = c1 = 0, c2 = ax0 t_f^2 / 90, c10 = p'0
+  {
+    double H[49] = {0}, gx2[7] = {0}, gx10[7] = {0};
+    const double cfix2 = t_f * t_f / (n * (n - 1.0));
+    for (int k = 0; k < T; ++k) {
+      const double *Wdd = &bt.Wdd[k * kNC];
+      double n1[7];
+      for (int a = 0; a < 7; ++a) n1[a] = Wdd[3 + a];
+      for (int a = 0; a < 7; ++a) {
+        for (int b = 0; b < 7; ++b) H[a * 7 + b] += 2.0 * cw.w_s * n1[a] * n1[b];
+        gx2[a] += 2.0 * cw.w_s * n1[a] * Wdd[2] * cfix2;
+        gx10[a] += 2.0 * cw.w_s * n1[a] * Wdd[10];
+      }
+    }
+    spd_inverse(H, 7);
+    for (int a = 0; a < 7; ++a) {
+      double s0 = 0.0, s2 = 0.0;
+      for (int b = 0; b < 7; ++b) {
+        s0 -= H[a * 7 + b] * gx10[b];
+        s2 -= H[a * 7 + b] * gx2[b];
+      }
+      st.S[a * 8 + 0] = s0;
+      st.R[a * 4 + 0] = s2;
+    }
+    st.S[7 * 8 + 0] = 1.0;
+  }
+  // ---- y axis: c0..c2 = E (y0, vy0, ay0), c9 = c10 = p'1
+  {
+    double E[kNC * 3] = {0};
+    E[0 * 3 + 0] = 1.0;
+    E[1 * 3 + 0] = 1.0;
+    E[1 * 3 + 1] = t_f / n;
+    E[2 * 3 + 0] = 1.0;
+    E[2 * 3 + 1] = 2.0 * t_f / n;
+    E[2 * 3 + 2] = t_f * t_f / (n * (n - 1.0));
+    double H[36] = {0}, ge[6 * 3] = {0}, gf[6] = {0};
+    for (int k = 0; k < T; ++k) {
+      const double *Wdd = &bt.Wdd[k * kNC];
+      double n1[6], e1[3] = {0, 0, 0};
+      for (int a = 0; a < 6; ++a) n1[a] = Wdd[3 + a];
+      for (int m = 0; m < 3; ++m)
+        for (int i = 0; i < 3; ++i) e1[m] += Wdd[i] * E[i * 3 + m];
+      for (int a = 0; a < 6; ++a) {
+        for (int b = 0; b < 6; ++b) H[a * 6 + b] += 2.0 * cw.w_s * n1[a] * n1[b];
+        for (int m = 0; m < 3; ++m) ge[a * 3 + m] += 2.0 * cw.w_s * n1[a] * e1[m];
+        gf[a] += 2.0 * cw.w_s * n1[a] * (Wdd[9] + Wdd[10]);
+      }
+    }
+    spd_inverse(H, 6);
+    for (int a = 0; a < 6; ++a) {
+      double s1 = 0.0, r[3] = {0, 0, 0};
+      for (int b = 0; b < 6; ++b) {
+        s1 -= H[a * 6 + b] * gf[b];
+        for (int m = 0; m < 3; ++m) r[m] -= H[a * 6 + b] * ge[b * 3 + m];
+      }
+      st.S[(8 + a) * 8 + 1] = s1;
+      for (int m = 0; m < 3; ++m) st.R[(8 + a) * 4 + 1 + m] = r[m];
+    }
+    st.S[14 * 8 + 1] = 1.0;
+  }
+  st.table.resize(kStep1Floats);
+  for (int i = 0; i < 16 * 8; ++i) st.table[i] = (float)st.S[i];
+  for (int i = 0; i < 16 * 4; ++i) st.table[16 * 8 + i] = (float)st.R[i];
+}
+
 // Step-1 QP (Alg. 1, Sec. II-C cost) reduced to the free coefficients:
 // minimise sum_k w (a_k^T c - beta_k)^2 over c = N z + c_fix.
-void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, Step1Table &st) {
+void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, bool goals, Step1Table &st) {
+  if (goals) {
+    build_step1_goals(bt, cw, t_f, st);
+    return;
+  }
   const int T = bt.T;
   double Nx[kNC * 8], Ny[kNC * 7];
   null_x(Nx);
@@ -240,7 +323,7 @@ void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, Step1T
   for (int i = 0; i < 16 * 4; ++i) st.table[16 * 8 + i] = (float)st.R[i];
 }
 
-void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt) {
+void build_proj(const BasisTable &bt, int M, double rho, bool goals, ProjTable &pt) {
   const int T = bt.T;
   double WtW[kNC * kNC] = {0}, DtD[kNC * kNC] = {0}, AtA[kNC * kNC] = {0};
   for (int k = 0; k < T; ++k)
@@ -270,19 +353,27 @@ void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt) {
         if (a == b) Dout[a] = nn;
       }
   };
+  // goal positions fix the last slot of each axis: the free set is the
+  // first 7 (x) and 6 (y) columns of the selections
+  const int fx = goals ? 7 : 8, fy = goals ? 6 : 7;
+  double Nxr[kNC * 8], Nyr[kNC * 7];
+  for (int i = 0; i < kNC; ++i) {
+    for (int c = 0; c < fx; ++c) Nxr[i * fx + c] = Nx[i * 8 + c];
+    for (int c = 0; c < fy; ++c) Nyr[i * fy + c] = Ny[i * 7 + c];
+  }
   double Ax[64], Ay[49], Dx[8], Dy[7];
-  reduce(Hx, Nx, 8, Ax, Dx);
-  reduce(Hy, Ny, 7, Ay, Dy);
-  spd_inverse(Ax, 8);
-  spd_inverse(Ay, 7);
+  reduce(Hx, Nxr, fx, Ax, Dx);
+  reduce(Hy, Nyr, fy, Ay, Dy);
+  spd_inverse(Ax, fx);
+  spd_inverse(Ay, fy);
   pt.Ainv.assign(16 * 16, 0.0);
   pt.D.assign(16, 0.0);
-  for (int a = 0; a < 8; ++a) {
-    for (int b = 0; b < 8; ++b) pt.Ainv[a * 16 + b] = Ax[a * 8 + b];
+  for (int a = 0; a < fx; ++a) {
+    for (int b = 0; b < fx; ++b) pt.Ainv[a * 16 + b] = Ax[a * fx + b];
     pt.D[a] = Dx[a];
   }
-  for (int a = 0; a < 7; ++a) {
-    for (int b = 0; b < 7; ++b) pt.Ainv[(8 + a) * 16 + 8 + b] = Ay[a * 7 + b];
+  for (int a = 0; a < fy; ++a) {
+    for (int b = 0; b < fy; ++b) pt.Ainv[(8 + a) * 16 + 8 + b] = Ay[a * fy + b];
     pt.D[8 + a] = Dy[a];
   }
   pt.table.resize(kProjFloats);

@@ -29,8 +29,11 @@ struct ProjTable {
 };
 
 void build_basis(int T, double t_f, BasisTable &bt);
-void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, Step1Table &st);
-void build_proj(const BasisTable &bt, int M, double rho, ProjTable &pt);
+// goals: behavioural inputs are goal positions (final boundary rows, cost
+// c_s alone); the free slots 7 (c10 of x) and 14 (c9 = c10 of y) are then
+// fixed by the goal and the inverse acts on the other 13.
+void build_step1(const BasisTable &bt, const CostWeights &cw, double t_f, bool goals, Step1Table &st);
+void build_proj(const BasisTable &bt, int M, double rho, bool goals, ProjTable &pt);
 
 // FP16 bit patterns of the tables of the matrix-core lower level:
 //   basis   [4 ceil(T/4)][kEvInstHalfs] (layout in plan_internal.h)

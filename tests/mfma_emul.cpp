@@ -99,7 +99,7 @@ int main(int argc, char **argv) {
   BasisTable bt;
   build_basis(T, t_f, bt);
   ProjTable pt;
-  build_proj(bt, M, 1.0, pt);
+  build_proj(bt, M, 1.0, false, pt);
   std::vector<uint16_t> tab, inv;
   build_mfma_basis(bt, tab);
   build_mfma_inverse(pt, inv);
