@@ -23,7 +23,12 @@ oracle timed on host cores on a sample of the same scene. Beside the headline (F
             one's saturated rate, then the same Poisson arrivals at 0.5, 0.7
             and 0.9 of the FP32 saturated rate (p50/p99 latency),
   scale     1024 concurrent requests of N = 4096, T = 100, M = 20 in both
-            precisions.
+            precisions,
+  mpc       the receding-horizon closed loop (MPC-Bi-Level): 1 and 256
+            episodes replanning every 5 instants on synthetic traffic, loop
+            rate, QP-solves/s, collisions and average speed,
+  behaviours  the same plan with goal-position inputs (both precisions) and
+            one iteration from the fixed grid (MPC-Grid).
 """
 from __future__ import annotations
 
@@ -274,7 +279,7 @@ def precision_gap(pl, workload, c, n_samples=256):
             "definition": "bound on max over t of |position(fp16_split) - position(f32)|"}
 
 
-def time_plan(pl, torch, c, scene, precision, steps, warmup):
+def time_plan(pl, torch, c, scene, precision, steps, warmup, **cfg_over):
     """One staged plan launched warmup + steps times in an uninstrumented
     timed region (the throughput), then steps times with HIP events recorded
     by every dispatch (kernel durations; the events cost host time per
@@ -282,8 +287,9 @@ def time_plan(pl, torch, c, scene, precision, steps, warmup):
     s of the first region, kernel ms dict of the second, launch counts,
     result)."""
     N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
+    L = cfg_over.pop("upper_iters", L)
     cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=1,
-                              precision=precision)
+                              precision=precision, **cfg_over)
     ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
     stream = torch.cuda.current_stream()
     h = pl.plan_create(cfg, workspace=ws, stream=stream.cuda_stream)
@@ -320,6 +326,8 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP16-split plan and the accuracy check")
     ap.add_argument("--no-scale", action="store_true", help="skip the 1024-request measurement")
     ap.add_argument("--no-mpc", action="store_true", help="skip the receding-horizon closed loop")
+    ap.add_argument("--no-behaviours", action="store_true",
+                    help="skip the goal-position and fixed-grid (MPC-Grid) plans")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 512 MiB device-to-device three times (a "
                          "kernel of known traffic that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -381,6 +389,22 @@ def main() -> int:
                         "kernel_ms_per_step": {k: ms2[k] / args.steps for k in ms2},
                         "plan": {"best_index": res2.best_index, "cost_upper": res2.cost_upper}}
         out["mixed"]["gap_to_f32"] = precision_gap(pl, workload, c)
+    if not args.no_behaviours:
+        # the other behavioural inputs of eq. behaviour_param on the same scene
+        out["behaviours"] = {}
+        for name, prec, over, Lb in (("goals_f32", 0, dict(behaviour=pl.PLAN_BEHAV_GOALS), L),
+                                     ("goals_fp16_split", 1, dict(behaviour=pl.PLAN_BEHAV_GOALS), L),
+                                     ("grid_f32_L1", 0, dict(sampler=pl.PLAN_SAMPLER_GRID), 1),
+                                     ("grid_goals_f32_L1", 0, dict(sampler=pl.PLAN_SAMPLER_GRID,
+                                                                   behaviour=pl.PLAN_BEHAV_GOALS), 1)):
+            print(f"[bench] plan {name}", file=sys.stderr, flush=True)
+            elb, msb, cntb, resb = time_plan(pl, torch, c, scene, prec, args.steps, args.warmup, upper_iters=Lb,
+                                             **over)
+            out["behaviours"][name] = {"value": N * Lb * args.steps / elb, "unit": "QP-solves/s",
+                                       "ms_per_plan": 1e3 * elb / args.steps, "L": Lb,
+                                       "lower_avg_ms": msb["lower"] / max(1, cntb["lower"]),
+                                       "plan": {"best_index": resb.best_index, "p_best": list(resb.p_best[:2]),
+                                                "cost_upper": resb.cost_upper, "residual": resb.residual}}
     if args.copy_probe:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
