@@ -63,7 +63,9 @@ class Params(C.Structure):
 
 class _Scene(C.Structure):
     _fields_ = [("ego", C.c_double * 6), ("kappa_road", C.c_double),
-                ("obs", C.POINTER(C.c_double))]
+                ("obs", C.POINTER(C.c_double)),
+                ("n_road", C.c_int), ("road_x0", C.c_double), ("road_dx", C.c_double),
+                ("road", C.POINTER(C.c_double))]
 
 
 class _PlanOut(C.Structure):
@@ -153,10 +155,15 @@ def default_params(**over) -> Params:
 @dataclass
 class Scene:
     """Ego state b_0 = (x0, y0, vx0, vy0, ax0, ay0), neighbours (M x 4:
-    x, y, vx, vy at t = 0, constant velocity) and road curvature."""
+    x, y, vx, vy at t = 0, constant velocity) and the road: a constant
+    curvature, or a profile ``road`` (n x 3: kappa, y_lb, y_ub at knots
+    road_x0 + i road_dx, linear between them, constant beyond)."""
     ego: np.ndarray
     obs: np.ndarray
     kappa_road: float = 0.0
+    road: np.ndarray | None = None
+    road_x0: float = 0.0
+    road_dx: float = 1.0
     _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _Scene:
@@ -167,6 +174,16 @@ class Scene:
         s.ego = (C.c_double * 6)(*[float(v) for v in np.asarray(self.ego).ravel()])
         s.kappa_road = float(self.kappa_road)
         s.obs = _pd(obs)
+        if self.road is not None and np.size(self.road):
+            road = np.ascontiguousarray(_f64(self.road).reshape(-1, 3))
+            self._keep.append(road)
+            s.n_road = road.shape[0]
+            s.road = _pd(road)
+        else:
+            s.n_road = 0
+            s.road = None
+        s.road_x0 = float(self.road_x0)
+        s.road_dx = float(self.road_dx)
         return s
 
 
@@ -359,7 +376,8 @@ def closed_loop(par: Params, scene: Scene, seed: int, N: int, cycles: int, n_exe
     out["ego"][0] = ego
     m, S = mu0, Sigma0
     for c in range(cycles):
-        res = plan(par, Scene(ego, obs, scene.kappa_road), (int(seed) + c) % 2 ** 64, N, m, S)
+        res = plan(par, Scene(ego, obs, scene.kappa_road, scene.road, scene.road_x0, scene.road_dx),
+                   (int(seed) + c) % 2 ** 64, N, m, S)
         out["xi"][c], out["mu"][c], out["sigma"][c] = res.xi_best, res.mu, res.Sigma
         out["cost"][c] = (res.cost_upper, res.residual)
         ego, obs, hit = advance(par, res.xi_best, obs0, c, n_exec)

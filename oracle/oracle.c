@@ -83,6 +83,35 @@ void orc_default_params(orc_params *par) {
   par->sampler = 0;
 }
 
+/* Road at longitudinal position x: curvature and lane limits (see
+ * orc_scene), linear interpolation between knots, constant beyond. */
+static void road_at(const orc_params *par, const orc_scene *sc, double x, double *kappa,
+                    double *y_lb, double *y_ub) {
+  if (sc->n_road <= 0) {
+    *kappa = sc->kappa_road;
+    *y_lb = par->y_lb;
+    *y_ub = par->y_ub;
+    return;
+  }
+  const double *R = sc->road;
+  if (sc->n_road == 1) {
+    *kappa = R[0];
+    *y_lb = R[1];
+    *y_ub = R[2];
+    return;
+  }
+  double u = (x - sc->road_x0) / sc->road_dx;
+  int last = sc->n_road - 1;
+  if (u <= 0.0) u = 0.0;
+  if (u >= (double)last) u = (double)last;
+  int i = (int)floor(u);
+  if (i > last - 1) i = last - 1;
+  double f = u - (double)i;
+  *kappa = R[3 * i + 0] + f * (R[3 * (i + 1) + 0] - R[3 * i + 0]);
+  *y_lb = R[3 * i + 1] + f * (R[3 * (i + 1) + 1] - R[3 * i + 1]);
+  *y_ub = R[3 * i + 2] + f * (R[3 * (i + 1) + 2] - R[3 * i + 2]);
+}
+
 /* Equality rows: the 7 of the set-point reading, plus x(t_f) and y(t_f)
  * with goal positions. */
 static int neq_of(const orc_params *par) { return par->behaviour ? 9 : 7; }
@@ -430,7 +459,6 @@ typedef struct proj_t {
   int T, M, nF; /* nF = 2 (M+2) T rows of F */
   double *F;    /* nF x 22, eq. for F: blkdiag([F_o; Wd; Wdd]) */
   double *G;    /* 2T x 22, lane rows G xi <= e (eq. lane_reform) */
-  double *e;    /* 2T */
   double *xo, *yo; /* M x T neighbour trajectories */
   double *KP;   /* LU of [[I + rho F^T F + rho G^T G, A^T], [A, 0]] */
   int *piv;
@@ -462,17 +490,15 @@ static void proj_init(proj_t *P, const orc_params *par, const orc_scene *sc) {
             P->B.Wdd[k * NC + c];
       }
   }
-  /* Lane bounds y_lb <= y <= y_ub as G xi <= e with G = [W; -W] on c_y,
-   * e = [y_ub; -y_lb] (straight road: constant limits). */
+  /* Lane bounds y_lb(x) <= y <= y_ub(x) as G xi <= e with G = [W; -W] on
+   * c_y; e = [y_ub; -y_lb] at each instant, taken at x(t_k) of the iterate
+   * of the target pass (constant on a road without a profile). */
   P->G = (double *)calloc((size_t)2 * T * NX, sizeof(double));
-  P->e = (double *)malloc(sizeof(double) * 2 * T);
   for (int k = 0; k < T; ++k) {
     for (int c = 0; c < NC; ++c) {
       P->G[(size_t)k * NX + NC + c] = P->B.W[k * NC + c];
       P->G[(size_t)(T + k) * NX + NC + c] = -P->B.W[k * NC + c];
     }
-    P->e[k] = par->y_ub;
-    P->e[T + k] = -par->y_lb;
   }
   /* Neighbour trajectories x_o,i(t), y_o,i(t): constant velocity. */
   P->xo = (double *)malloc(sizeof(double) * (M > 0 ? M : 1) * T);
@@ -517,7 +543,6 @@ static void proj_init(proj_t *P, const orc_params *par, const orc_scene *sc) {
 static void proj_free(proj_t *P) {
   free(P->F);
   free(P->G);
-  free(P->e);
   free(P->xo);
   free(P->yo);
   free(P->KP);
@@ -546,7 +571,7 @@ static double clip(double v, double lo, double hi) {
  *     (|kappa| cos^2 alpha_v))) (v_max where the denominator is 0).
  *   - slack: s = max(0, e - G xi) from G xi - e + s = 0, s >= 0. */
 static void targets(const proj_t *P, const double *xi, const double *da_prev,
-                    double *h, double *s, double *da_out) {
+                    double *h, double *s, double *e, double *da_out) {
   const orc_params *par = P->par;
   int T = P->T, M = P->M;
   int rows_axis = (M + 2) * T;
@@ -578,8 +603,12 @@ static void targets(const proj_t *P, const double *xi, const double *da_prev,
     double vbar_min = par->v_min;
     double vcurv = sqrt(da_prev[k] * sabs / par->kappa_max);
     if (vcurv > vbar_min) vbar_min = vcurv;
+    double kappa, y_lb, y_ub;
+    road_at(par, P->sc, x, &kappa, &y_lb, &y_ub);
+    e[k] = y_ub; /* lane rows G xi <= e at this iterate's x(t_k) */
+    e[T + k] = -y_lb;
     double cva = cos(alpha_v);
-    double den = fabs(P->sc->kappa_road) * cva * cva;
+    double den = fabs(kappa) * cva * cva;
     double vbar_max = par->v_max;
     if (den > 0.0) {
       double vc = sqrt(par->c_max / den);
@@ -601,7 +630,7 @@ static void targets(const proj_t *P, const double *xi, const double *da_prev,
   for (int r = 0; r < 2 * T; ++r) {
     double g = 0;
     for (int c = 0; c < NX; ++c) g += P->G[(size_t)r * NX + c] * xi[c];
-    double v = P->e[r] - g;
+    double v = e[r] - g;
     s[r] = v > 0.0 ? v : 0.0;
   }
 }
@@ -610,7 +639,9 @@ void orc_targets(const orc_params *par, const orc_scene *sc, const double *xi,
                  const double *da_prev, double *h, double *s, double *da_out) {
   proj_t P;
   proj_init(&P, par, sc);
-  targets(&P, xi, da_prev, h, s, da_out);
+  double *e = (double *)malloc(sizeof(double) * 2 * par->T);
+  targets(&P, xi, da_prev, h, s, e, da_out);
+  free(e);
   proj_free(&P);
 }
 
@@ -640,13 +671,14 @@ static void project_one(const proj_t *P, const double *xi_bar, const double *p,
   double *da = (double *)malloc(sizeof(double) * T);
   double *da_prev = (double *)malloc(sizeof(double) * T);
   double *Fx = (double *)malloc(sizeof(double) * nF);
+  double *e = (double *)malloc(sizeof(double) * 2 * T);
   double xi[NX], lam[NX], rhs[NKKT_MAX], beq[NEQ_MAX];
   eq_rhs(par, P->sc, p, beq);
 
   memcpy(xi, xi_bar, sizeof(xi));
   memset(lam, 0, sizeof(lam));
   acc_norm_clip(P, xi, da_prev);
-  targets(P, xi, da_prev, h, s, da);
+  targets(P, xi, da_prev, h, s, e, da);
   memcpy(da_prev, da, sizeof(double) * T);
   if (xi_iter) memcpy(xi_iter, xi, sizeof(xi));
 
@@ -659,7 +691,7 @@ static void project_one(const proj_t *P, const double *xi_bar, const double *p,
       for (int i = 0; i < NX; ++i) rhs[i] += Fr[i] * hr;
     }
     for (int r = 0; r < 2 * T; ++r) {
-      double er = rho * (P->e[r] - s[r]);
+      double er = rho * (e[r] - s[r]);
       const double *Gr = P->G + (size_t)r * NX;
       for (int i = 0; i < NX; ++i) rhs[i] += Gr[i] * er;
     }
@@ -669,7 +701,7 @@ static void project_one(const proj_t *P, const double *xi_bar, const double *p,
     if (xi_iter) memcpy(xi_iter + (size_t)k * NX, xi, sizeof(xi));
 
     /* steps split_alpha_o .. update_slack */
-    targets(P, xi, da_prev, h, s, da);
+    targets(P, xi, da_prev, h, s, e, da);
     memcpy(da_prev, da, sizeof(double) * T);
 
     /* step update_lagrange (reading: the two penalty gradients are both
@@ -688,11 +720,12 @@ static void project_one(const proj_t *P, const double *xi_bar, const double *p,
       const double *Gr = P->G + (size_t)r * NX;
       double v = 0;
       for (int i = 0; i < NX; ++i) v += Gr[i] * xi[i];
-      v = v - P->e[r] + s[r];
+      v = v - e[r] + s[r];
       for (int i = 0; i < NX; ++i) lam[i] -= 0.5 * rho * Gr[i] * v;
     }
   }
   memcpy(xi_out, xi, sizeof(xi));
+  free(e);
   free(h);
   free(s);
   free(da);
@@ -764,11 +797,13 @@ void orc_residual_cost(const orc_params *par, const orc_scene *sc,
       double vd = v > par->v_eps ? v : par->v_eps;
       g = fabs(ydd * xd - xdd * yd) / (vd * vd * vd) - par->kappa_max;
       res += g > 0 ? g : 0;
-      g = fabs(xd * xd * sc->kappa_road) - par->c_max;
+      double kappa, y_lb, y_ub;
+      road_at(par, sc, x, &kappa, &y_lb, &y_ub);
+      g = fabs(xd * xd * kappa) - par->c_max;
       res += g > 0 ? g : 0;
-      g = y - par->y_ub;
+      g = y - y_ub;
       res += g > 0 ? g : 0;
-      g = par->y_lb - y;
+      g = y_lb - y;
       res += g > 0 ? g : 0;
       cost += (v - par->v_max) * (v - par->v_max);
     }

@@ -60,6 +60,14 @@ typedef struct orc_scene {
   double ego[6];
   double kappa_road;
   const double *obs; /* M x 4 */
+  /* Road profile along x (Table ineq_list: kappa(x(t)) of the centripetal
+   * row, lane limits y_lb(x(t)), y_ub(x(t))): n_road knots at road_x0 +
+   * i road_dx holding (kappa, y_lb, y_ub), linear between knots and constant
+   * beyond the ends. n_road = 0: the constant kappa_road and the parameters'
+   * y_lb, y_ub. */
+  int n_road;
+  double road_x0, road_dx;
+  const double *road; /* n_road x 3 */
 } orc_scene;
 
 /* Defaults of every reading the paper leaves open. */
