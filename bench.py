@@ -27,8 +27,9 @@ oracle timed on host cores on a sample of the same scene. Beside the headline (F
   mpc       the receding-horizon closed loop (MPC-Bi-Level): 1 and 256
             episodes replanning every 5 instants on synthetic traffic, loop
             rate, QP-solves/s, collisions and average speed,
-  behaviours  the same plan with goal-position inputs (both precisions) and
-            one iteration from the fixed grid (MPC-Grid).
+  behaviours  the same plan with goal-position inputs (both precisions),
+            one iteration from the fixed grid (MPC-Grid), and on a curved
+            road with a lane closure (both precisions).
 """
 from __future__ import annotations
 
@@ -279,13 +280,13 @@ def precision_gap(pl, workload, c, n_samples=256):
             "definition": "bound on max over t of |position(fp16_split) - position(f32)|"}
 
 
-def time_plan(pl, torch, c, scene, precision, steps, warmup, **cfg_over):
+def time_plan(pl, torch, c, scene, precision, steps, warmup, road=None, **cfg_over):
     """One staged plan launched warmup + steps times in an uninstrumented
     timed region (the throughput), then steps times with HIP events recorded
     by every dispatch (kernel durations; the events cost host time per
     launch, so this region is not used for the throughput). Returns (elapsed
     s of the first region, kernel ms dict of the second, launch counts,
-    result)."""
+    result). road: (profile, x0, dx) of a curved road, else the straight road."""
     N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
     L = cfg_over.pop("upper_iters", L)
     cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=1,
@@ -293,7 +294,8 @@ def time_plan(pl, torch, c, scene, precision, steps, warmup, **cfg_over):
     ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
     stream = torch.cuda.current_stream()
     h = pl.plan_create(cfg, workspace=ws, stream=stream.cuda_stream)
-    req = pl.Request(N=N, T=T, ego=scene.ego, obstacles=scene.obstacles, seed=scene.seed)
+    rk = {} if road is None else dict(road=road[0], road_x0=road[1], road_dx=road[2])
+    req = pl.Request(N=N, T=T, ego=scene.ego, obstacles=scene.obstacles, seed=scene.seed, **rk)
     pl.plan_stage(h, [req])  # inputs into HBM before the timed region
     for _ in range(warmup):
         pl.plan_launch(h)
@@ -327,7 +329,7 @@ def main() -> int:
     ap.add_argument("--no-scale", action="store_true", help="skip the 1024-request measurement")
     ap.add_argument("--no-mpc", action="store_true", help="skip the receding-horizon closed loop")
     ap.add_argument("--no-behaviours", action="store_true",
-                    help="skip the goal-position and fixed-grid (MPC-Grid) plans")
+                    help="skip the goal-position, fixed-grid (MPC-Grid) and curved-road plans")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 512 MiB device-to-device three times (a "
                          "kernel of known traffic that calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -391,15 +393,19 @@ def main() -> int:
         out["mixed"]["gap_to_f32"] = precision_gap(pl, workload, c)
     if not args.no_behaviours:
         # the other behavioural inputs of eq. behaviour_param on the same scene
+        # and on a curved road (curvature and lane limits along x)
         out["behaviours"] = {}
-        for name, prec, over, Lb in (("goals_f32", 0, dict(behaviour=pl.PLAN_BEHAV_GOALS), L),
-                                     ("goals_fp16_split", 1, dict(behaviour=pl.PLAN_BEHAV_GOALS), L),
-                                     ("grid_f32_L1", 0, dict(sampler=pl.PLAN_SAMPLER_GRID), 1),
-                                     ("grid_goals_f32_L1", 0, dict(sampler=pl.PLAN_SAMPLER_GRID,
-                                                                   behaviour=pl.PLAN_BEHAV_GOALS), 1)):
+        curve = workload.curved_road(CFG_ID, 0)
+        for name, prec, over, Lb, rd in (("goals_f32", 0, dict(behaviour=pl.PLAN_BEHAV_GOALS), L, None),
+                                         ("goals_fp16_split", 1, dict(behaviour=pl.PLAN_BEHAV_GOALS), L, None),
+                                         ("grid_f32_L1", 0, dict(sampler=pl.PLAN_SAMPLER_GRID), 1, None),
+                                         ("grid_goals_f32_L1", 0, dict(sampler=pl.PLAN_SAMPLER_GRID,
+                                                                       behaviour=pl.PLAN_BEHAV_GOALS), 1, None),
+                                         ("curved_road_f32", 0, {}, L, curve),
+                                         ("curved_road_fp16_split", 1, {}, L, curve)):
             print(f"[bench] plan {name}", file=sys.stderr, flush=True)
-            elb, msb, cntb, resb = time_plan(pl, torch, c, scene, prec, args.steps, args.warmup, upper_iters=Lb,
-                                             **over)
+            elb, msb, cntb, resb = time_plan(pl, torch, c, scene, prec, args.steps, args.warmup, road=rd,
+                                             upper_iters=Lb, **over)
             out["behaviours"][name] = {"value": N * Lb * args.steps / elb, "unit": "QP-solves/s",
                                        "ms_per_plan": 1e3 * elb / args.steps, "L": Lb,
                                        "lower_avg_ms": msb["lower"] / max(1, cntb["lower"]),

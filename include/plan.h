@@ -51,6 +51,7 @@ extern "C" {
 #define PLAN_MAX_M 32   /* neighbouring vehicles per request              */
 #define PLAN_MAX_N 4096 /* behavioural samples per request                */
 #define PLAN_MAX_L 16   /* upper-level iterations                         */
+#define PLAN_MAX_ROAD 64 /* knots of a road profile                       */
 
 typedef enum plan_status {
   PLAN_OK = 0,
@@ -184,7 +185,20 @@ typedef struct plan_config {
  *   ego          b_0 = (x0, y0, vx0, vy0, ax0, ay0) (eq. boundary_cond_initial).
  *   obstacles    host, M x 4 doubles: (x, y, vx, vy) at t = 0; neighbours move
  *                at constant velocity x_o(t) = x + vx t (Fig. learned_sampler).
- *   kappa_road   road curvature (0: straight road).
+ *   kappa_road   road curvature (0: straight road) when no profile is given.
+ *   n_road, road_x0, road_dx, road
+ *                road profile along x (Table ineq_list: the centripetal row's
+ *                kappa(x(t)) and the lane limits y_lb(x(t)), y_ub(x(t)), the
+ *                bound e(xi) of eq. lane_reform, taken at each iterate's
+ *                position): road is host, n_road x 3 doubles (kappa, y_lb,
+ *                y_ub) at x = road_x0 + i road_dx, x in the same coordinate
+ *                as ego[0] (not relative to it); linear between knots,
+ *                constant beyond them. Copied at the call; the caller keeps
+ *                ownership. n_road = 0: kappa_road and the config's y_lb,
+ *                y_ub. n_road <= PLAN_MAX_ROAD, road_dx > 0 if n_road > 1,
+ *                y_lb < y_ub at every knot, all finite; else the request
+ *                fails with PLAN_E_INVALID. Requests with a profile run in
+ *                lower-level launches of their own.
  *   mu0, sigma0  optional initial distribution (8, 8x8); if NULL the session
  *                warm start is used, else the structured initial sampler.
  *   first_iter   index of the first upper iteration (normally 0). It keys
@@ -203,6 +217,9 @@ typedef struct plan_request {
   const double *mu0;
   const double *sigma0;
   int32_t first_iter;
+  int32_t n_road;
+  double road_x0, road_dx;
+  const double *road;
 } plan_request;
 
 /*

@@ -22,8 +22,9 @@ PLAN_F_INFEASIBLE, PLAN_F_WARM = 1, 2
 PLAN_MPC_SAMPLER, PLAN_MPC_WARM = 0, 1
 PLAN_BEHAV_SETPOINTS, PLAN_BEHAV_GOALS = 0, 1
 PLAN_SAMPLER_RANDOM, PLAN_SAMPLER_GRID = 0, 1
+PLAN_MAX_ROAD = 64  # knots of a request's road profile
 NC, NX, NP = 11, 22, 8
-MAX_N, MAX_M, MAX_T = 4096, 32, 256
+MAX_N, MAX_M, MAX_T, MAX_ROAD = 4096, 32, 256, 64
 
 
 class PlanError(RuntimeError):
@@ -70,6 +71,8 @@ class plan_request(C.Structure):
         ("kappa_road", C.c_double),
         ("mu0", _PD), ("sigma0", _PD),
         ("first_iter", C.c_int32),
+        ("n_road", C.c_int32), ("road_x0", C.c_double), ("road_dx", C.c_double),
+        ("road", _PD),
     ]
 
 
@@ -168,6 +171,9 @@ class Request:
     mu0: np.ndarray | None = None
     sigma0: np.ndarray | None = None
     first_iter: int = 0
+    road: np.ndarray | None = None  # n x 3: kappa, y_lb, y_ub at road_x0 + i road_dx
+    road_x0: float = 0.0
+    road_dx: float = 1.0
 
     @property
     def M(self) -> int:
@@ -191,6 +197,13 @@ class _Marshalled:
             c.obstacles = _pd(obs) if obs.size else None
             c.kappa_road = float(r.kappa_road)
             c.first_iter = int(r.first_iter)
+            c.road_x0, c.road_dx = float(r.road_x0), float(r.road_dx)
+            if r.road is not None and np.size(r.road):
+                road = np.ascontiguousarray(np.asarray(r.road, np.float64).reshape(-1, 3))
+                self.keep.append(road)
+                c.n_road, c.road = road.shape[0], _pd(road)
+            else:
+                c.n_road, c.road = 0, None
             if r.mu0 is not None:
                 mu = np.ascontiguousarray(np.asarray(r.mu0, np.float64).reshape(8))
                 sg = np.ascontiguousarray(np.asarray(r.sigma0, np.float64).reshape(64))

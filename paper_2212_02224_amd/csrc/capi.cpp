@@ -29,10 +29,10 @@
 #include "precompute.h"
 
 namespace plan {
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, size_t lds, hipStream_t st,
-                        hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, int T, size_t lds,
-                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, bool road, size_t lds,
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, int T,
+                             size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1);
 hipError_t launch_advance(const AdvArgs &a, const MethodParams &p, int n, hipStream_t st);
@@ -110,9 +110,10 @@ struct LaunchSet {
   int n_act = 0, ngroups = 0;
   struct Group {
     int act_off = 0, n = 0, nblocks = 0, T = 0;
-    int ipl = 1;  // VALU kernel: instants per lane
+    int ipl = 1;        // VALU kernel: instants per lane
+    bool road = false;  // requests with a road profile
     size_t lds = 0;
-  } grp[4];
+  } grp[8];
 };
 
 struct DevBuf {
@@ -263,6 +264,7 @@ struct plan_handle {
   // batch mode: staged requests in slots 0..staged-1
   int staged = 0;
   LaunchSet ls;
+  std::vector<int> ls_slots;  // make_launch_set: slots ordered by road class
   std::vector<int> staged_req;
   std::vector<int> staged_status;
   int staged_total = 0;
@@ -360,6 +362,15 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   if ((r.mu0 == nullptr) != (r.sigma0 == nullptr)) return "mu0 and sigma0 must be given together";
   if (r.mu0 && (!finite_all(r.mu0, 8) || !finite_all(r.sigma0, 64))) return "non-finite mu0/sigma0";
   if (r.first_iter < 0 || r.first_iter > (1 << 20)) return "first_iter out of range";
+  if (r.n_road < 0 || r.n_road > PLAN_MAX_ROAD) return "n_road out of range";
+  if (r.n_road > 0) {
+    if (!r.road) return "road profile missing";
+    if (!finite_all(r.road, 3 * r.n_road) || !std::isfinite(r.road_x0) || !std::isfinite(r.road_dx))
+      return "non-finite road profile";
+    if (r.n_road > 1 && !(r.road_dx > 0)) return "road_dx must be > 0";
+    for (int i = 0; i < r.n_road; ++i)
+      if (!(r.road[3 * i + 1] < r.road[3 * i + 2])) return "road profile needs y_lb < y_ub at every knot";
+  }
   std::memset(&d, 0, sizeof(d));
   d.T = r.T;
   d.M = r.M;
@@ -374,6 +385,11 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   d.seed = r.seed;
   std::memcpy(d.ego, r.ego, sizeof(d.ego));
   d.kappa = r.kappa_road;
+  d.n_road = r.n_road;
+  d.road_x0 = r.road_x0;
+  d.road_dx = r.n_road > 1 ? r.road_dx : 1.0;
+  for (int i = 0; i < r.n_road; ++i)
+    for (int k = 0; k < 3; ++k) d.road[i][k] = r.road[3 * i + k];
   for (int i = 0; i < r.M; ++i)
     for (int k = 0; k < 4; ++k) d.obs[i][k] = r.obstacles[4 * i + k];
   if (r.mu0) {
@@ -491,14 +507,14 @@ plan_status timed(plan_handle *h, int kind, F &&launch, const char *what) {
   return PLAN_OK;
 }
 
-// Order the slots into launch groups and fill the host act / prefix arrays:
-// group k's slots at act[off..off+n), its workgroup prefix counts at
-// prefix[off + k .. off + k + n].
-void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
+// Launch groups of the slots slots[0..n), all with or all without a road
+// profile, appended to ls: group k's slots at act[off..off+n), its workgroup
+// prefix counts at prefix[off + k .. off + k + n].
+void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, LaunchSet &ls) {
+  if (n == 0) return;
   const bool mf = mfma_mode(h->cfg);
   int32_t *act = h->h_act, *prefix = h->h_act + h->cfg.max_requests;
-  ls = LaunchSet();
-  ls.n_act = n;
+  const int k0 = ls.ngroups, pos0 = ls.n_act;
   int keys[4];
   int nkeys = 0;
   for (int i = 0; i < n; ++i) {
@@ -508,14 +524,17 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
     if (!seen) keys[nkeys++] = key;
   }
   std::sort(keys, keys + nkeys);
-  int pos = 0;
-  for (int k = 0; k < nkeys; ++k) {
+  int pos = pos0;
+  for (int kk = 0; kk < nkeys; ++kk) {
+    const int k = k0 + kk;
     LaunchSet::Group &gr = ls.grp[k];
+    gr = LaunchSet::Group();
+    gr.road = road;
     gr.act_off = pos;
     int blocks = 0;
     for (int i = 0; i < n; ++i) {
       const ReqDesc &d = h->h_desc[slots[i]];
-      if ((mf ? d.T : t_class(d.T)) != keys[k]) continue;
+      if ((mf ? d.T : t_class(d.T)) != keys[kk]) continue;
       act[pos] = slots[i];
       prefix[pos + k] = blocks;
       blocks += blocks_for(d.N, d.T, mf);
@@ -525,8 +544,8 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
     gr.n = pos - gr.act_off;
     gr.nblocks = blocks;
     prefix[pos + k] = blocks;
-    gr.T = keys[k];
-    if (!mf && keys[k] == 2) {
+    gr.T = keys[kk];
+    if (!mf && keys[kk] == 2) {
       int blocks2 = 0;
       for (int i = gr.act_off; i < pos; ++i) {
         const ReqDesc &d = h->h_desc[act[i]];
@@ -545,51 +564,51 @@ void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
       }
     }
   }
-  ls.ngroups = nkeys;
-  // VALU mode: the horizon classes need launches of their own only when the
-  // longer class runs two instants per lane; otherwise one launch of one
-  // instant per lane takes every request, whatever its T.
-  if (!mf && nkeys > 1 && ls.grp[nkeys - 1].ipl == 1) {
-    LaunchSet::Group all;
-    all.act_off = 0;
-    all.n = n;
-    all.T = 1;
-    int blocks = 0;
-    for (int i = 0; i < n; ++i) {
-      const ReqDesc &d = h->h_desc[act[i]];
-      prefix[i] = blocks;
-      blocks += blocks_for(d.N, d.T, false, 1);
-      all.lds = std::max(all.lds, lds_bytes(d.M, d.T, false));
-    }
-    prefix[n] = blocks;
-    all.nblocks = blocks;
-    ls.grp[0] = all;
-    ls.ngroups = 1;
-    return;
-  }
-  // A light matrix-core load runs all horizons in one launch shaped for the
-  // longest (waves without a tile pair only join the barriers), so its
-  // groups do not wait for each other; the arithmetic per request is the
-  // same in any launch.
+  ls.n_act = pos;
+  ls.ngroups = k0 + nkeys;
+  // One launch for the whole class: VALU mode when the longer horizon class
+  // runs one instant per lane (then every request, whatever its T, fits a
+  // launch of one instant per lane); matrix-core mode when the load is light
+  // (the launch is shaped for the longest horizon, waves without a tile pair
+  // only join the barriers), so its groups do not wait for each other. The
+  // arithmetic per request is the same in any launch.
   int total = 0;
-  for (int k = 0; k < nkeys; ++k) total += ls.grp[k].nblocks;
-  if (mf && nkeys > 1 && total < 2 * h->n_cu) {
-    LaunchSet::Group all;
-    all.act_off = 0;
-    all.n = n;
-    all.T = ls.grp[nkeys - 1].T;
-    int blocks = 0;
-    for (int i = 0; i < n; ++i) {
-      const ReqDesc &d = h->h_desc[act[i]];
-      prefix[i] = blocks;
-      blocks += blocks_for(d.N, d.T, mf);
-      all.lds = std::max(all.lds, lds_bytes(d.M, d.T, mf));
-    }
-    prefix[n] = blocks;
-    all.nblocks = blocks;
-    ls.grp[0] = all;
-    ls.ngroups = 1;
+  for (int kk = 0; kk < nkeys; ++kk) total += ls.grp[k0 + kk].nblocks;
+  const bool merge = nkeys > 1 && (mf ? total < 2 * h->n_cu : ls.grp[k0 + nkeys - 1].ipl == 1);
+  if (!merge) return;
+  LaunchSet::Group all;
+  all.road = road;
+  all.act_off = pos0;
+  all.n = n;
+  all.T = mf ? ls.grp[k0 + nkeys - 1].T : 1;
+  int blocks = 0;
+  for (int i = pos0; i < pos0 + n; ++i) {
+    const ReqDesc &d = h->h_desc[act[i]];
+    prefix[i + k0] = blocks;
+    blocks += blocks_for(d.N, d.T, mf, 1);
+    all.lds = std::max(all.lds, lds_bytes(d.M, d.T, mf));
   }
+  prefix[pos0 + n + k0] = blocks;
+  all.nblocks = blocks;
+  ls.grp[k0] = all;
+  ls.ngroups = k0 + 1;
+}
+
+// Order the slots into launch groups and fill the host act / prefix arrays.
+// Requests with a road profile run in launches of their own (a kernel
+// variant with the profile lookup), after those without; the variant depends
+// on the request alone, so a request's results do not depend on its batch.
+void make_launch_set(plan_handle *h, const int *slots, int n, LaunchSet &ls) {
+  ls = LaunchSet();
+  int *flat = h->ls_slots.data();
+  int nf = 0;
+  for (int i = 0; i < n; ++i)
+    if (h->h_desc[slots[i]].n_road == 0) flat[nf++] = slots[i];
+  int nr = nf;
+  for (int i = 0; i < n; ++i)
+    if (h->h_desc[slots[i]].n_road != 0) flat[nr++] = slots[i];
+  add_launch_groups(h, flat, nf, false, ls);
+  add_launch_groups(h, flat + nf, n - nf, true, ls);
 }
 
 plan_status upload_launch_set(plan_handle *h, const LaunchSet &ls) {
@@ -616,8 +635,8 @@ plan_status launch_lower_set(plan_handle *h, const LaunchSet &ls, int l_uniform,
           // two tiles per wave while a launch cannot fill every CU with two
           // workgroups, else four (same arithmetic either way)
           const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
-          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.T, gr.lds, h->stream, a, b)
-                    : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.lds, h->stream, a, b);
+          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, gr.T, gr.lds, h->stream, a, b)
+                    : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, a, b);
         },
         mf ? "lower_mfma_kernel" : "lower_kernel");
     if (st != PLAN_OK) return st;
@@ -925,6 +944,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->sess_used.assign(max_sessions(c), 0);
   h->sess_valid.assign(max_sessions(c), 0);
   h->slot_busy.assign(S, 0);
+  h->ls_slots.assign(S, 0);
   h->free_rows[0] = h->rows;
   // ---- stream and pinned staging
   hipError_t e = hipSuccess;

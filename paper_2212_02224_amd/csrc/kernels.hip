@@ -305,7 +305,40 @@ struct Lane {
 struct Scal {
   float vx0, rho, ia, ib, ell_a, ell_b;
   float v_min, v_max, a_max, kmax, inv_kmax, c_max, kappa_abs, y_lb, y_ub, v_eps;
+  int n_road;                    // knots of the road profile (0: constant road)
+  float road_x0, road_idx, dt;   // first knot from x0, 1 / knot spacing, t_f / (T - 1)
 };
+
+// Road at one instant (Table ineq_list: the centripetal row's kappa(x(t)) and
+// the lane limits y_lb(x(t)), y_ub(x(t))).
+struct RoadAt {
+  float kappa_abs, y_lb, y_ub;
+};
+
+// The request's road profile (knots in LDS as (kappa, y_lb, y_ub, 0)) at the
+// trajectory's position x_rel + vx0 t_k from x0 (x_rel in the frame relative
+// to x0 + vx0 t), linear between knots and constant beyond; the constant road
+// without a profile. ROAD = false: launches whose requests have no profile
+// (the lookup compiles away).
+template <bool ROAD>
+__device__ __forceinline__ RoadAt road_at(const Scal &S, const float4 *__restrict__ road, float x_rel, int t) {
+  RoadAt r;
+  if (!ROAD || S.n_road == 0) {
+    r.kappa_abs = S.kappa_abs;
+    r.y_lb = S.y_lb;
+    r.y_ub = S.y_ub;
+    return r;
+  }
+  const float xe = fmaf(S.vx0, (float)t * S.dt, x_rel);
+  const float u = fminf(fmaxf((xe - S.road_x0) * S.road_idx, 0.f), (float)(S.n_road - 1));
+  const int i = min((int)u, max(S.n_road - 2, 0));
+  const float f = S.n_road > 1 ? u - (float)i : 0.f;
+  const float4 a = road[i], b = road[S.n_road > 1 ? i + 1 : i];
+  r.kappa_abs = fabsf(fmaf(f, b.x - a.x, a.x));
+  r.y_lb = fmaf(f, b.y - a.y, a.y);
+  r.y_ub = fmaf(f, b.z - a.z, a.z);
+  return r;
+}
 
 struct State6 {
   float x, xd, xdd, y, yd, ydd;
@@ -379,8 +412,8 @@ struct Corr {
 // trajectory state s there and the neighbour sums (ax, ay) of
 // neighbour_pass. da_prev carries d_a of the previous step. All differences
 // are zero where tv is false.
-__device__ __forceinline__ Corr targets_from(const State6 &s, const Scal &S, float ax, float ay, bool tv,
-                                             float &da_prev) {
+__device__ __forceinline__ Corr targets_from(const State6 &s, const Scal &S, const RoadAt &rd, float ax, float ay,
+                                             bool tv, float &da_prev) {
   float dox = ax * S.ell_a, doy = ay * S.ell_b;
   // velocity / acceleration polar variables and their clips
   const float v2 = fmaf(s.xd, s.xd, s.yd * s.yd);
@@ -396,9 +429,9 @@ __device__ __forceinline__ Corr targets_from(const State6 &s, const Scal &S, flo
   const float sig = fabsf(fmaf(s.ydd, ex, -fx * s.yd)) * (rv1 * ra1);
   const float vlo = fmaxf(S.v_min, fsqrt(da_prev * sig * S.inv_kmax));
   float vhi = S.v_max;
-  if (S.kappa_abs > 0.f) {
+  if (rd.kappa_abs > 0.f) {
     const float cv = ex * rv1;
-    const float den = S.kappa_abs * cv * cv;
+    const float den = rd.kappa_abs * cv * cv;
     if (den > 0.f) vhi = fminf(vhi, fsqrt(S.c_max * frcp(den)));
   }
   const float dv = fminf(fmaxf(vn, vlo), vhi);
@@ -412,27 +445,29 @@ __device__ __forceinline__ Corr targets_from(const State6 &s, const Scal &S, flo
   c.day = ka * s.ydd;
   if (tv) da_prev = dan;
   // lane bounds: e - s - G xi = clip(y, y_lb, y_ub) - y
-  c.wy = doy + (fminf(fmaxf(s.y, S.y_lb), S.y_ub) - s.y);
+  c.wy = doy + (fminf(fmaxf(s.y, rd.y_lb), rd.y_ub) - s.y);
   c.dox = dox;
   if (!tv) c.dox = c.wy = c.dvx = c.dvy = c.dax = c.day = 0.f;
   return c;
 }
 
+template <bool ROAD>
 __device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const float4 *__restrict__ obs,
-                                           int npair, int T, int t, bool tv, float &da_prev) {
+                                           const float4 *__restrict__ road, int npair, int T, int t, bool tv,
+                                           float &da_prev) {
   float ax, ay;
   neighbour_pass(obs, npair, T, t, s.x * S.ia, s.y * S.ib, ax, ay);
-  return targets_from(s, S, ax, ay, tv, da_prev);
+  return targets_from(s, S, road_at<ROAD>(S, road, s.x, t), ax, ay, tv, da_prev);
 }
 
 // One target pass over this lane's IPL instants (slots): the trajectory at
 // each, the neighbour sums of all slots in one loop over the neighbour pairs
 // (the slots' dependency chains interleave), then the targets of each slot.
-template <int IPL>
+template <int IPL, bool ROAD>
 __device__ __forceinline__ void target_pass(const Lane (&L)[IPL], const Scal &S, const float (&zs)[15],
-                                            const float4 *__restrict__ obs, int npair, int T,
-                                            const int (&tt)[IPL], const bool (&tv)[IPL], float (&da_prev)[IPL],
-                                            Corr (&cr)[IPL]) {
+                                            const float4 *__restrict__ obs, const float4 *__restrict__ road,
+                                            int npair, int T, const int (&tt)[IPL], const bool (&tv)[IPL],
+                                            float (&da_prev)[IPL], Corr (&cr)[IPL]) {
   State6 st[IPL];
   float xs[IPL], ys[IPL], ax[IPL], ay[IPL];
 #pragma unroll
@@ -464,7 +499,8 @@ __device__ __forceinline__ void target_pass(const Lane (&L)[IPL], const Scal &S,
     }
   }
 #pragma unroll
-  for (int u = 0; u < IPL; ++u) cr[u] = targets_from(st[u], S, ax[u], ay[u], tv[u], da_prev[u]);
+  for (int u = 0; u < IPL; ++u)
+    cr[u] = targets_from(st[u], S, road_at<ROAD>(S, road, st[u].x, tt[u]), ax[u], ay[u], tv[u], da_prev[u]);
 }
 
 // This lane's share of N^T g at one instant.
@@ -479,8 +515,11 @@ __device__ __forceinline__ void g_of(const Lane &L, const Corr &c, float (&g)[16
 
 // Residual r (sum of max(0, g) over Table ineq_list) and upper cost c_u at
 // one instant of the trajectory state s.
+template <bool ROAD>
 __device__ __forceinline__ void residual_at(const State6 &s, const Scal &S, const float4 *__restrict__ obs,
-                                            int npair, int T, int t, bool tv, float &res, float &cost) {
+                                            const float4 *__restrict__ road, int npair, int T, int t, bool tv,
+                                            float &res, float &cost) {
+  const RoadAt rd = road_at<ROAD>(S, road, s.x, t);
   const float xs = s.x * S.ia, ys = s.y * S.ib;
   float r = 0.f;
   for (int c = 0; c < npair; ++c) {
@@ -497,8 +536,8 @@ __device__ __forceinline__ void residual_at(const State6 &s, const Scal &S, cons
   const float vd = fmaxf(vn, S.v_eps);
   const float curv = fabsf(s.ydd * s.xd - s.xdd * s.yd) * frcp(vd * vd * vd);
   r += fmaxf(0.f, curv - S.kmax);
-  r += fmaxf(0.f, fabsf(s.xd * s.xd * S.kappa_abs) - S.c_max);
-  r += fmaxf(0.f, s.y - S.y_ub) + fmaxf(0.f, S.y_lb - s.y);
+  r += fmaxf(0.f, fabsf(s.xd * s.xd * rd.kappa_abs) - S.c_max);
+  r += fmaxf(0.f, s.y - rd.y_ub) + fmaxf(0.f, rd.y_lb - s.y);
   const float e = vn - S.v_max;
   res = tv ? r : 0.f;
   cost = tv ? e * e : 0.f;
@@ -544,6 +583,12 @@ __device__ void stage_neighbours(const ReqDesc &D, const MethodParams &P, float4
   }
 }
 
+// Road profile knots into LDS as (kappa, y_lb, y_ub, 0).
+__device__ void stage_road(const ReqDesc &D, float4 *s_road) {
+  for (int i = threadIdx.x; i < D.n_road; i += blockDim.x)
+    s_road[i] = make_float4((float)D.road[i][0], (float)D.road[i][1], (float)D.road[i][2], 0.f);
+}
+
 // Sampling distribution of upper iteration l into LDS (Gaussian draws only):
 // the request's or the session's at iteration 0 (factored here), else the
 // one the previous update left with its factor.
@@ -585,6 +630,10 @@ __device__ __forceinline__ Scal make_scal(const ReqDesc &D, const MethodParams &
   S.y_lb = (float)P.y_lb;
   S.y_ub = (float)P.y_ub;
   S.v_eps = (float)P.v_eps;
+  S.n_road = D.n_road;
+  S.road_x0 = (float)(D.road_x0 - D.ego[0]);
+  S.road_idx = (float)(1.0 / D.road_dx);
+  S.dt = (float)(P.t_f / (double)(D.T - 1));
   return S;
 }
 
@@ -679,11 +728,12 @@ __device__ __forceinline__ void write_xi(const ReqDesc &D, const MethodParams &P
 
 // IPL instants per lane: instant (wi IPL + u) 64 + lane in slot u of wave wi
 // of a sample; ceil(T / (64 IPL)) waves per sample.
-template <int IPL>
+template <int IPL, bool ROAD>
 __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_obs[];
   __shared__ float s_red[2][4 * IPL][16];
   __shared__ double s_mu[8], s_chol[64];
+  __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
 
   const int2 bi = block_slot(A);
   const ReqDesc &D = A.desc[bi.x];
@@ -708,6 +758,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   const size_t slot_off = (size_t)D.row_off;
 
   stage_neighbours(D, P, s_obs);
+  if constexpr (ROAD) stage_road(D, s_road);
   const bool forced = D.init_mode == kInitForced;
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
   if (!forced && !structured) load_distribution(A, D, P, bi.x, l, s_mu, s_chol);
@@ -803,7 +854,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   };
   Corr cr[IPL];
   auto pass = [&]() -> float {
-    target_pass<IPL>(L, S, zs, obs, npair, T, tt, tv, da_prev, cr);
+    target_pass<IPL, ROAD>(L, S, zs, obs, s_road, npair, T, tt, tv, da_prev, cr);
     float r[IPL];
 #pragma unroll
     for (int u = 0; u < IPL; ++u) {
@@ -841,7 +892,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   float rb[IPL], cb[IPL];
 #pragma unroll
   for (int u = 0; u < IPL; ++u) {
-    residual_at(eval_traj(L[u], zs, S.vx0), S, obs, npair, T, tt[u], tv[u], rb[u], cb[u]);
+    residual_at<ROAD>(eval_traj(L[u], zs, S.vx0), S, obs, s_road, npair, T, tt[u], tv[u], rb[u], cb[u]);
     rb[u] = wave_sum(rb[u]);
     cb[u] = wave_sum(cb[u]);
   }
@@ -964,11 +1015,12 @@ __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int N, i
 // Dynamic LDS of the matrix-core kernel: basis table [4 NT][kEvInstHalfs],
 // neighbours [pair of neighbours][T] (float4), fixed trajectory part [4 NT][2]
 // (float4), N^T g per tile pair [ceil(NT / 2)][64] (float4), total [64].
-template <int TPW>
+template <int TPW, bool ROAD>
 __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_dyn[];
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float s_rc[kMfmaMaxPairs][kMfmaSamples][2];
+  __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
 
   const int2 bi = block_slot(A);
   const int slot = bi.x;
@@ -996,6 +1048,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
     for (int i = threadIdx.x; i < tab_f4; i += blockDim.x) s_dyn[i] = src[i];
   }
   stage_neighbours(D, P, s_obs);
+  if constexpr (ROAD) stage_road(D, s_road);
   const bool forced = D.init_mode == kInitForced;
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
   if (!forced && !structured) load_distribution(A, D, P, slot, l, s_mu, s_chol);
@@ -1115,7 +1168,8 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
             const int t = 4 * tile + g;
             const State6 st = evaluate(tile, bx, by);
             if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-            acc = accumulate(tile, targets_at(st, S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, da[i]),
+            acc = accumulate(tile, targets_at<ROAD>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
+                                                    active && t < T, da[i]),
                              acc);
           }
         }
@@ -1179,7 +1233,8 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
           if (tile < NT) {
             const int t = 4 * tile + g;
             float r1, c1;
-            residual_at(evaluate(tile, bx, by), S, s_obs, npair, T, t < T ? t : T - 1, active && t < T, r1, c1);
+            residual_at<ROAD>(evaluate(tile, bx, by), S, s_obs, s_road, npair, T, t < T ? t : T - 1,
+                              active && t < T, r1, c1);
             rr += r1;
             cc += c1;
           }
@@ -1678,21 +1733,23 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   }
 }
 
-hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, size_t lds, hipStream_t st,
-                        hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, bool road, size_t lds,
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (ipl != 1 && ipl != 2) return hipErrorInvalidValue;
-  auto kern = ipl == 1 ? lower_kernel<1> : lower_kernel<2>;
+  auto kern = ipl == 1 ? (road ? lower_kernel<1, true> : lower_kernel<1, false>)
+                       : (road ? lower_kernel<2, true> : lower_kernel<2, false>);
   if (ev0)
     hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(kBlock), (uint32_t)lds, st, ev0, ev1, 0, a, p);
   else
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kBlock), lds, st, a, p);
   return hipGetLastError();
 }
-hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, int T, size_t lds,
-                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, int T,
+                             size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if ((tpw != 2 && tpw != 4) || T < 1 || T > kMfmaMaxT) return hipErrorInvalidValue;
   const int waves = (T + 4 * tpw - 1) / (4 * tpw);
-  auto kern = tpw == 2 ? lower_mfma_kernel<2> : lower_mfma_kernel<4>;
+  auto kern = tpw == 2 ? (road ? lower_mfma_kernel<2, true> : lower_mfma_kernel<2, false>)
+                       : (road ? lower_mfma_kernel<4, true> : lower_mfma_kernel<4, false>);
   if (ev0 != nullptr)
     hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(kWave * waves), (uint32_t)lds, st, ev0, ev1, 0, a, p);
   else

@@ -67,6 +67,9 @@ struct ReqDesc {
   double mu0[8];
   double sigma0[64];
   double obs[PLAN_MAX_M][4];
+  int32_t n_road;    // road profile: 0 = constant kappa and lane limits
+  double road_x0, road_dx;
+  double road[PLAN_MAX_ROAD][3];  // kappa, y_lb, y_ub per knot
 };
 
 // Sampling distribution of one slot (FP64).

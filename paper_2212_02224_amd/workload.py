@@ -14,6 +14,15 @@ neighbours moving along straight lines at constant speed in their lanes
                 than 1.0 to another neighbour at t = 0
     seeds       scene seed = 1000 * config + request index; the request's
                 sample-stream key is scene seed XOR 0x9E3779B9
+
+curved_road() gives a road profile for the same scenes (curvature and lane
+limits along x, in the road-aligned frame the neighbours' lanes follow):
+knots every 20 m from x = -40 to 280 m; the curvature ramps linearly from 0
+to +-U[0.01, 0.02] 1/m (radius 50..100 m) over 60 m from a start in
+U[0, 60] m, holds for 60 m and ramps back; with probability 1/2 the left
+lane closes (y_ub from 7 to 5.25 m over 40 m from a start in U[40, 120] m).
+At the scenes' speeds the centripetal row v^2 |kappa| <= c_max (c_max 4)
+is active inside the bend.
 """
 from __future__ import annotations
 
@@ -51,6 +60,23 @@ def scene(config: int, index: int, M: int) -> Scene:
         obs.append(o)
     obs = np.array(obs, dtype=np.float64).reshape(M, 4)
     return Scene(ego, obs, s ^ 0x9E3779B9)
+
+
+def curved_road(config: int, index: int):
+    """(road (n x 3: kappa, y_lb, y_ub), road_x0, road_dx) for scene
+    (config, index); an independent stream of the scene's seed."""
+    rng = np.random.default_rng([1000 * int(config) + int(index), 7])
+    x0, dx, n = -40.0, 20.0, 17
+    x = x0 + dx * np.arange(n)
+    k_c = rng.choice((-1.0, 1.0)) * rng.uniform(0.01, 0.02)
+    a = rng.uniform(0.0, 60.0)
+    kappa = k_c * np.clip(np.minimum((x - a) / 60.0, (a + 180.0 - x) / 60.0), 0.0, 1.0)
+    y_ub = np.full(n, 7.0)
+    if rng.uniform() < 0.5:
+        b = rng.uniform(40.0, 120.0)
+        y_ub = 7.0 - 1.75 * np.clip((x - b) / 40.0, 0.0, 1.0)
+    road = np.stack([kappa, np.full(n, -7.0), y_ub], axis=1)
+    return road, x0, dx
 
 
 # Workload configurations (sizes of the planning problem).

@@ -6,6 +6,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -110,3 +112,14 @@ def test_workload_scenes_are_seeded(pl):
     a, b = workload.scene(2, 5, 10), workload.scene(2, 5, 10)
     assert (a.ego == b.ego).all() and (a.obstacles == b.obstacles).all() and a.seed == b.seed
     assert a.obstacles.shape == (10, 4)
+
+
+def test_curved_road_profile_is_seeded_and_valid(pl):
+    from paper_2212_02224_amd import workload
+    a, b = workload.curved_road(6, 3), workload.curved_road(6, 3)
+    assert np.array_equal(a[0], b[0]) and a[1:] == b[1:]
+    road, x0, dx = a
+    assert road.shape == (17, 3) and dx > 0
+    assert np.all(road[:, 1] < road[:, 2]) and np.abs(road[:, 0]).max() <= 0.02
+    bends = [np.abs(workload.curved_road(6, i)[0][:, 0]).max() for i in range(20)]
+    assert min(bends) >= 0.01  # every profile has a bend of radius 50..100 m

@@ -60,14 +60,18 @@ def set_check(name, gpu_idx, orc_idx, orc_key, tol_of_key, exempt=None):
 
 
 def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e-4, behaviour=0, sampler=0,
-               L=None):
+               L=None, road=False):
     c = workload.CONFIGS[cfgid]
     N, T, M, K = c["N"], c["T"], c["M"], c["K"]
     L = c["L"] if L is None else L
     orc.set_threads(8)
     par = orc.default_params(T=T, M=M, K=K, L=L, behaviour=behaviour, sampler=sampler)
     s = workload.scene(cfgid, scene_idx, M)
-    sc = orc.Scene(s.ego, s.obstacles)
+    rk = {}
+    if road:
+        rp, rx0, rdx = workload.curved_road(cfgid, scene_idx)
+        rk = dict(road=rp, road_x0=rx0, road_dx=rdx)
+    sc = orc.Scene(s.ego, s.obstacles, **rk)
     ref = orc.plan(par, sc, s.seed, N, trace=True)
     tr = ref.trace
     n, q = orc.elite_sizes(par, N)
@@ -80,11 +84,11 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
     ct = lambda c: c_tol(c, tol_scale)  # noqa: E731
     for l in range(L):
         print(f"[plan parity] config {cfgid} scene {scene_idx} precision {precision} behaviour {behaviour} "
-              f"sampler {sampler} iteration {l}", flush=True)
+              f"sampler {sampler} road {road} iteration {l}", flush=True)
         kw = {}
         if l > 0:
             kw = dict(mu0=tr["mu"][l - 1], sigma0=tr["Sigma"][l - 1])
-        req = pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, first_iter=l, **kw)
+        req = pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, first_iter=l, **rk, **kw)
         res = pl.plan_solve_batch(h, [req])[0]
         assert res.status == 0, pl.plan_last_error(h)
         g = pl.plan_get_trace(h, 0, N, n, q)
@@ -92,8 +96,7 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
         dp = np.abs(g["p"][0] - tr["p"][l])
         assert np.all(dp <= 2e-5 + 1e-6 * np.abs(tr["p"][l])), dp.max()
         # residuals and costs
-        slow = ill_conditioned(orc, par, orc.Scene(s.ego, s.obstacles), tr["xi_bar"][l], tr["xi_star"][l],
-                               p=tr["p"][l])
+        slow = ill_conditioned(orc, par, sc, tr["xi_bar"][l], tr["xi_star"][l], p=tr["p"][l])
         ok = ~slow
         dr = np.abs(g["r"][0] - tr["r"][l])
         dc = np.abs(g["cu"][0] - tr["cu"][l])
