@@ -4,8 +4,10 @@ TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package. It shares no
 code with the HIP path (``paper_2212_02224_amd``) and never imports it.
 
-The arithmetic lives in ``oracle.c`` (plain C, FP64, literal). This module is
-the ctypes marshalling around it and its build step (``gcc``).
+The arithmetic lives in ``oracle.c`` (plain C, FP64, literal), except the
+decoder MLP of the learned sampler (``decoder_forward``: numpy FP64, layer by
+layer as App. A lists them). This module is the ctypes marshalling around the
+C code and its build step (``gcc``).
 
 Parity status: pinned by the CPU tests in ``tests/test_oracle_*.py`` except
 the values of the projection iterates at finite K (parity unpinned; their
@@ -113,6 +115,9 @@ def _load():
     lib.orc_plan.argtypes = [P, S, C.c_uint64, C.c_int, _PD, _PD,
                              C.POINTER(_PlanOut), C.POINTER(_Trace)]
     lib.orc_advance.argtypes = [P, _PD, _PD, C.c_int, C.c_int, C.c_int, _PD, _PD, _PI]
+    lib.orc_plan_p0.argtypes = [P, S, C.c_uint64, C.c_int, _PD, C.POINTER(_PlanOut), C.POINTER(_Trace)]
+    lib.orc_decoder_latent.argtypes = [C.c_uint64, C.c_int, _PD]
+    lib.orc_sample_moments.argtypes = [_PD, C.c_int, _PD, _PD]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_get_threads.restype = C.c_int
     _lib = lib
@@ -312,8 +317,10 @@ class PlanResult:
 
 
 def plan(par: Params, scene: Scene, seed: int, N: int, mu0=None, Sigma0=None,
-         trace: bool = False) -> PlanResult:
-    """Alg. 1 with the lower level of Alg. 2, FP64."""
+         trace: bool = False, p0=None) -> PlanResult:
+    """Alg. 1 with the lower level of Alg. 2, FP64. p0 (N x 8): samples of
+    the first iteration (the decoder sampler's, ``decoder_sample``); the
+    prior of the first update is then their sample moments."""
     n, q = elite_sizes(par, N)
     L = par.L
     out = _PlanOut()
@@ -331,15 +338,62 @@ def plan(par: Params, scene: Scene, seed: int, N: int, mu0=None, Sigma0=None,
     sc = scene.c()
     m0 = _f64(mu0) if mu0 is not None else None
     S0 = _f64(Sigma0) if Sigma0 is not None else None
-    rc = _load().orc_plan(C.byref(par), C.byref(sc), C.c_uint64(int(seed)), int(N),
-                          _pd(m0) if m0 is not None else None,
-                          _pd(S0) if S0 is not None else None,
-                          C.byref(out), C.byref(tr) if tr is not None else None)
+    if p0 is not None:
+        q0 = np.ascontiguousarray(_f64(p0).reshape(N, NP))
+        rc = _load().orc_plan_p0(C.byref(par), C.byref(sc), C.c_uint64(int(seed)), int(N), _pd(q0),
+                                 C.byref(out), C.byref(tr) if tr is not None else None)
+    else:
+        rc = _load().orc_plan(C.byref(par), C.byref(sc), C.c_uint64(int(seed)), int(N),
+                              _pd(m0) if m0 is not None else None,
+                              _pd(S0) if S0 is not None else None,
+                              C.byref(out), C.byref(tr) if tr is not None else None)
     if rc != 0:
         raise RuntimeError(f"oracle plan failed rc={rc}")
     return PlanResult(out.best_index, np.array(out.p_best), np.array(out.xi_best),
                       out.cost_upper, out.residual, np.array(out.mu),
                       np.array(out.Sigma).reshape(NP, NP), arrays)
+
+
+def decoder_latent(seed: int, N: int) -> np.ndarray:
+    """Latent draws z (N x 2, z ~ N(0, I) of App. A) of the decoder sampler:
+    Box-Muller of words 0, 1 of Philox block (j, 0, 0, 0) under the key seed."""
+    z = np.zeros((N, 2))
+    _load().orc_decoder_latent(C.c_uint64(int(seed)), int(N), _pd(z))
+    return z
+
+
+def sample_moments(p):
+    """Sample mean and covariance (normalised by N) of p (N x 8)."""
+    p = np.ascontiguousarray(_f64(p).reshape(-1, NP))
+    mu, S = np.zeros(NP), np.zeros((NP, NP))
+    _load().orc_sample_moments(_pd(p), p.shape[0], _pd(mu), _pd(S))
+    return mu, S
+
+
+def decoder_forward(dec, obs, z, behaviour: int = 0) -> np.ndarray:
+    """Decoder MLP of the CVAE (App. A, decoder table): the input [o, z]
+    (55 + 2) goes through five blocks of Linear, BatchNorm (inference form:
+    running mean and variance, eps, then gamma and beta) and ReLU with 1024,
+    1024, 1024, 1024 and 256 outputs, then a Linear layer to the 8
+    behavioural inputs p. FP64. ``dec`` holds W (6 weight matrices, out x
+    in), b (6 biases), gamma, beta, mean, var (5 each) and eps. With goal
+    positions (behaviour 1) only p[0], p[1] are inputs; the others are 0."""
+    z = _f64(z).reshape(-1, 2)
+    x = np.concatenate([np.broadcast_to(_f64(obs).reshape(1, -1), (z.shape[0], 55)), z], axis=1)
+    for i in range(5):
+        h = x @ _f64(dec.W[i]).T + _f64(dec.b[i])
+        h = (h - _f64(dec.mean[i])) / np.sqrt(_f64(dec.var[i]) + dec.eps) * _f64(dec.gamma[i]) + _f64(dec.beta[i])
+        x = np.maximum(h, 0.0)
+    p = x @ _f64(dec.W[5]).T + _f64(dec.b[5])
+    if behaviour:
+        p[:, 2:] = 0.0
+    return p
+
+
+def decoder_sample(par: Params, dec, obs, seed: int, N: int) -> np.ndarray:
+    """N samples of p from the decoder sampler (App. A inference: z drawn
+    from N(0, I), passed through the decoder MLP with the observation o)."""
+    return decoder_forward(dec, obs, decoder_latent(seed, N), par.behaviour)
 
 
 def advance(par: Params, xi, obs0, cycle: int, n_exec: int):

@@ -1049,14 +1049,64 @@ void orc_sample(const orc_params *par, uint64_t seed, int l, int N,
 /* ------------------------------------------------------------------ */
 /* Alg. 1.                                                               */
 
+/* Latent draws of the decoder sampler (App. A: z ~ N(0, I), 2-d): z_j is
+ * the Box-Muller pair of words 0, 1 of Philox block (j, 0, 0, 0), the block
+ * the structured sampler takes its first two normals from. */
+void orc_decoder_latent(uint64_t seed, int N, double *z) {
+  for (int j = 0; j < N; ++j) {
+    uint32_t w[4];
+    philox_block(seed, j, 0, 0, w);
+    box_muller(w[0], w[1], &z[2 * j], &z[2 * j + 1]);
+  }
+}
+
+/* Mean and covariance (normalised by N) of N samples p (N x 8), in two
+ * passes: the distribution the samples of a learned sampler come from, as
+ * far as N draws show it. */
+void orc_sample_moments(const double *p, int N, double *mu, double *Sigma) {
+  for (int a = 0; a < NP; ++a) {
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += p[(size_t)j * NP + a];
+    mu[a] = s / (double)N;
+  }
+  for (int a = 0; a < NP; ++a)
+    for (int b = 0; b < NP; ++b) {
+      double s = 0.0;
+      for (int j = 0; j < N; ++j)
+        s += (p[(size_t)j * NP + a] - mu[a]) * (p[(size_t)j * NP + b] - mu[b]);
+      Sigma[a * NP + b] = s / (double)N;
+    }
+}
+
+static int plan_impl(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
+                     const double *mu0, const double *Sigma0, const double *p0,
+                     orc_plan_out *out, orc_plan_trace *tr);
+
 int orc_plan(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
              const double *mu0, const double *Sigma0, orc_plan_out *out,
              orc_plan_trace *tr) {
+  return plan_impl(par, sc, seed, N, mu0, Sigma0, NULL, out, tr);
+}
+
+/* Alg. 1 started from given samples p0 (N x 8) instead of a draw: the first
+ * iteration evaluates p0 (the decoder sampler's output, App. A), and the
+ * distribution before the first update is their sample moments. */
+int orc_plan_p0(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
+                const double *p0, orc_plan_out *out, orc_plan_trace *tr) {
+  if (p0 == NULL) return -1;
+  return plan_impl(par, sc, seed, N, NULL, NULL, p0, out, tr);
+}
+
+static int plan_impl(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
+                     const double *mu0, const double *Sigma0, const double *p0,
+                     orc_plan_out *out, orc_plan_trace *tr) {
   int n, q;
   orc_elite_sizes(par, N, &n, &q);
   double mu[NP], Sigma[NP * NP], Lc[NP * NP];
-  int structured = (mu0 == NULL || Sigma0 == NULL);
-  if (structured) {
+  int structured = p0 == NULL && (mu0 == NULL || Sigma0 == NULL);
+  if (p0 != NULL) {
+    orc_sample_moments(p0, N, mu, Sigma);
+  } else if (structured) {
     orc_initial_moments(par, mu, Sigma);
   } else {
     memcpy(mu, mu0, sizeof(mu));
@@ -1073,13 +1123,17 @@ int orc_plan(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
   int rc = 0;
   for (int l = 0; l < par->L; ++l) {
     int draw_structured = structured && l == 0;
-    if (!draw_structured) {
-      if (orc_cholesky(Sigma, NP, par->cov_jitter, Lc) != 0) {
-        rc = -2;
-        break;
+    if (p0 != NULL && l == 0) {
+      memcpy(p, p0, sizeof(double) * N * NP);
+    } else {
+      if (!draw_structured) {
+        if (orc_cholesky(Sigma, NP, par->cov_jitter, Lc) != 0) {
+          rc = -2;
+          break;
+        }
       }
+      orc_sample(par, seed, l, N, draw_structured, mu, Lc, p);
     }
-    orc_sample(par, seed, l, N, draw_structured, mu, Lc, p);
     orc_step1(par, sc, p, N, xb);
     orc_project(par, sc, xb, p, N, xs, NULL);
     orc_residual_cost(par, sc, xs, N, r, cu);

@@ -158,6 +158,19 @@ int orc_plan(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
              const double *mu0, const double *Sigma0, orc_plan_out *out,
              orc_plan_trace *trace);
 
+/* Alg. 1 whose first iteration evaluates the given samples p0 (N x 8, the
+ * decoder sampler's output, App. A) and whose prior before the first update
+ * is their sample moments (orc_sample_moments). */
+int orc_plan_p0(const orc_params *par, const orc_scene *sc, uint64_t seed, int N,
+                const double *p0, orc_plan_out *out, orc_plan_trace *trace);
+
+/* Latent draws z (N x 2) of the decoder sampler: Box-Muller of words 0, 1 of
+ * Philox block (sample j, iteration 0, block 0). */
+void orc_decoder_latent(uint64_t seed, int N, double *z);
+
+/* Sample mean and covariance (normalised by N) of p (N x 8). */
+void orc_sample_moments(const double *p, int N, double *mu, double *Sigma);
+
 /* Threads used by the OpenMP loops over samples (1 = serial). */
 /* One step of the receding-horizon loop (MPC-Bi-Level, Sec. V-A): state of
  * xi at t_{n_exec} (x, y, xdot, ydot, xddot, yddot), the neighbours (M x 4,

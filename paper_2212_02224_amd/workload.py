@@ -23,6 +23,23 @@ U[0, 60] m, holds for 60 m and ramps back; with probability 1/2 the left
 lane closes (y_ub from 7 to 5.25 m over 40 m from a start in U[40, 120] m).
 At the scenes' speeds the centripetal row v^2 |kappa| <= c_max (c_max 4)
 is active inside the bend.
+
+observation() and decoder_weights() are the inputs of the decoder sampler
+(the CVAE decoder of App. A, whose trained weights are not published):
+    observation  55 values, scaled to O(1): ego heading, vx0 / 20, vy0 / 20;
+                 the 10 nearest neighbours (Euclidean at t = 0) as
+                 (dx / 50, dy / 7, vx / 20, vy / 20), missing ones at
+                 dx / 50 = 4, the rest 0; lane limits (y_lb - y0) / 7,
+                 (y_ub - y0) / 7 at the first 6 profile knots from x0 on (the
+                 constant limits without a profile)
+    weights      random: Linear weights N(0, 2 / fan_in) (the latent
+                 columns of the first layer x 4, so that z spreads the
+                 samples), biases U(-0.05, 0.05); BatchNorm gamma U(0.9, 1.1),
+                 beta, running mean U(-0.05, 0.05), running variance
+                 U(0.9, 1.1), eps 1e-5; the output layer scaled so that p
+                 spreads like behavioural inputs (lateral set-points about
+                 +-2 m around 0, velocity set-points about 15 +- 4 m/s; goals
+                 75 +- 20 m ahead, y_f about +-2 m)
 """
 from __future__ import annotations
 
@@ -77,6 +94,75 @@ def curved_road(config: int, index: int):
         y_ub = 7.0 - 1.75 * np.clip((x - b) / 40.0, 0.0, 1.0)
     road = np.stack([kappa, np.full(n, -7.0), y_ub], axis=1)
     return road, x0, dx
+
+
+OBS_DIM, LATENT_DIM = 55, 2
+DECODER_SIZES = (OBS_DIM + LATENT_DIM, 1024, 1024, 1024, 1024, 256, 8)
+
+
+@dataclass
+class Decoder:
+    W: list          # 6 weight matrices, out x in
+    b: list          # 6 biases
+    gamma: list      # BatchNorm of blocks 1-5
+    beta: list
+    mean: list
+    var: list
+    eps: float = 1e-5
+
+
+def observation(s: Scene, road=None, road_x0: float = 0.0, road_dx: float = 1.0,
+                y_lb: float = -7.0, y_ub: float = 7.0) -> np.ndarray:
+    """The 55-value observation of scene s (layout in the module docstring)."""
+    ego = np.asarray(s.ego, np.float64)
+    o = np.zeros(OBS_DIM)
+    o[0] = np.arctan2(ego[3], ego[2])
+    o[1], o[2] = ego[2] / 20.0, ego[3] / 20.0
+    obs = np.asarray(s.obstacles, np.float64).reshape(-1, 4)
+    order = np.argsort(np.hypot(obs[:, 0] - ego[0], obs[:, 1] - ego[1]), kind="stable")[:10]
+    for i in range(10):
+        k = 3 + 4 * i
+        if i < len(order):
+            q = obs[order[i]]
+            o[k:k + 4] = [(q[0] - ego[0]) / 50.0, (q[1] - ego[1]) / 7.0, q[2] / 20.0, q[3] / 20.0]
+        else:
+            o[k] = 4.0
+    lim = np.tile([y_lb, y_ub], (6, 1))
+    if road is not None and np.size(road):
+        r = np.asarray(road, np.float64).reshape(-1, 3)
+        first = int(np.clip(np.ceil((ego[0] - road_x0) / road_dx), 0, len(r) - 1))
+        idx = np.minimum(first + np.arange(6), len(r) - 1)
+        lim = r[idx, 1:3]
+    o[43:] = ((lim - ego[1]) / 7.0).ravel()
+    return o
+
+
+def decoder_weights(seed: int = 0, behaviour: int = 0) -> Decoder:
+    """Random decoder weights of the App. A sizes (recipe in the module
+    docstring); behaviour 1 shapes the output for goal positions."""
+    rng = np.random.default_rng([int(seed), 11])
+    W, b, g, be, m, v = [], [], [], [], [], []
+    for i in range(6):
+        fi, fo = DECODER_SIZES[i], DECODER_SIZES[i + 1]
+        Wi = rng.standard_normal((fo, fi)) * np.sqrt(2.0 / fi)
+        bi = rng.uniform(-0.05, 0.05, fo)
+        if i == 0:
+            Wi[:, OBS_DIM:] *= 4.0
+        if i == 5:
+            if behaviour:
+                scale, centre = np.r_[20.0, 2.0, np.zeros(6)], np.r_[75.0, np.zeros(7)]
+            else:
+                scale, centre = np.r_[np.full(4, 2.0), np.full(4, 4.0)], np.r_[np.zeros(4), np.full(4, 15.0)]
+            Wi *= (scale / np.sqrt(2.0 * 0.9))[:, None]
+            bi = bi + centre
+        W.append(Wi)
+        b.append(bi)
+        if i < 5:
+            g.append(rng.uniform(0.9, 1.1, fo))
+            be.append(rng.uniform(-0.05, 0.05, fo))
+            m.append(rng.uniform(-0.05, 0.05, fo))
+            v.append(rng.uniform(0.9, 1.1, fo))
+    return Decoder(W, b, g, be, m, v)
 
 
 # Workload configurations (sizes of the planning problem).

@@ -123,3 +123,18 @@ def test_curved_road_profile_is_seeded_and_valid(pl):
     assert np.all(road[:, 1] < road[:, 2]) and np.abs(road[:, 0]).max() <= 0.02
     bends = [np.abs(workload.curved_road(6, i)[0][:, 0]).max() for i in range(20)]
     assert min(bends) >= 0.01  # every profile has a bend of radius 50..100 m
+
+
+def test_decoder_inputs_are_seeded_and_shaped(pl):
+    from paper_2212_02224_amd import workload
+    s = workload.scene(2, 4, 10)
+    o = workload.observation(s)
+    assert o.shape == (55,) and np.array_equal(o, workload.observation(s))
+    # nearest neighbour first; a scene with fewer than 10 neighbours pads
+    d = np.hypot(o[3:43:4] * 50.0, o[4:43:4] * 7.0)
+    assert np.all(np.diff(d) >= -1e-12)
+    few = workload.observation(workload.scene(1, 0, 4))
+    assert np.all(few[3 + 16:43:4] == 4.0)
+    a, b = workload.decoder_weights(2), workload.decoder_weights(2)
+    assert all(np.array_equal(x, y) for x, y in zip(a.W, b.W))
+    assert [w.shape for w in a.W] == [(1024, 57), (1024, 1024), (1024, 1024), (1024, 1024), (256, 1024), (8, 256)]
