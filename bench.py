@@ -27,6 +27,8 @@ oracle timed on host cores on a sample of the same scene. Beside the headline (F
   mpc       the receding-horizon closed loop (MPC-Bi-Level): 1 and 256
             episodes replanning every 5 instants on synthetic traffic, loop
             rate, QP-solves/s, collisions and average speed,
+  decoder   the same plan with iteration 0 drawn by the decoder sampler
+            (App. A decoder MLP, random weights), both precisions,
   behaviours  the same plan with goal-position inputs (both precisions),
             one iteration from the fixed grid (MPC-Grid), and on a curved
             road with a lane closure (both precisions).
@@ -45,6 +47,13 @@ sys.path.insert(0, ROOT)
 METRIC = "lower-level QP solves/sec at ≤1e-4 m error; p99 plan latency (served)"
 CFG_ID = 2
 PEAK_ALU_TFLOPS = 78.6  # FP32 FMA without packed math: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+
+# Decoder sampler per sample: algorithmic flops of the App. A decoder (FMA =
+# 2): 57 -> 1024, three 1024 -> 1024, 1024 -> 256, 256 -> 8; and the flops the
+# matrix cores execute for blocks 2-5 in the FP16-split form (3 products).
+DECODER_FLOPS = 2 * (57 * 1024 + 3 * 1024 * 1024 + 1024 * 256 + 256 * 8)
+DECODER_MFMA_FLOPS = 3 * 2 * (3 * 1024 * 1024 + 1024 * 256)
 
 
 def lower_flops_per_sample(T: int, M: int, K: int) -> float:
@@ -280,21 +289,29 @@ def precision_gap(pl, workload, c, n_samples=256):
             "definition": "bound on max over t of |position(fp16_split) - position(f32)|"}
 
 
-def time_plan(pl, torch, c, scene, precision, steps, warmup, road=None, **cfg_over):
+def time_plan(pl, torch, c, scene, precision, steps, warmup, road=None, decoder=None, **cfg_over):
     """One staged plan launched warmup + steps times in an uninstrumented
     timed region (the throughput), then steps times with HIP events recorded
     by every dispatch (kernel durations; the events cost host time per
     launch, so this region is not used for the throughput). Returns (elapsed
     s of the first region, kernel ms dict of the second, launch counts,
-    result). road: (profile, x0, dx) of a curved road, else the straight road."""
+    result). road: (profile, x0, dx) of a curved road, else the straight road;
+    decoder: weights of the decoder sampler, which then draws iteration 0
+    from the scene's observation."""
     N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
     L = cfg_over.pop("upper_iters", L)
+    if decoder is not None:
+        cfg_over["sampler"] = pl.PLAN_SAMPLER_DECODER
     cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, max_requests=1,
                               precision=precision, **cfg_over)
     ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
     stream = torch.cuda.current_stream()
     h = pl.plan_create(cfg, workspace=ws, stream=stream.cuda_stream)
     rk = {} if road is None else dict(road=road[0], road_x0=road[1], road_dx=road[2])
+    if decoder is not None:
+        from paper_2212_02224_amd import workload
+        pl.plan_set_decoder(h, decoder)
+        rk["observation"] = workload.observation(scene, *(() if road is None else road))
     req = pl.Request(N=N, T=T, ego=scene.ego, obstacles=scene.obstacles, seed=scene.seed, **rk)
     pl.plan_stage(h, [req])  # inputs into HBM before the timed region
     for _ in range(warmup):
@@ -328,6 +345,7 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP16-split plan and the accuracy check")
     ap.add_argument("--no-scale", action="store_true", help="skip the 1024-request measurement")
     ap.add_argument("--no-mpc", action="store_true", help="skip the receding-horizon closed loop")
+    ap.add_argument("--no-decoder", action="store_true", help="skip the plan drawn by the decoder sampler")
     ap.add_argument("--no-behaviours", action="store_true",
                     help="skip the goal-position, fixed-grid (MPC-Grid) and curved-road plans")
     ap.add_argument("--copy-probe", action="store_true",
@@ -431,6 +449,21 @@ def main() -> int:
                                            ("fp16_split_256", 1, 256, 20, 0), ("f32_256_warm", 0, 256, 20, 1)):
             print(f"[bench] closed loop {name}: {eps} episodes x {cyc} cycles", file=sys.stderr, flush=True)
             out["mpc"][name] = mpc_bench(pl, workload, torch, prec, eps, cyc, c=c, init=init)
+    if not args.no_decoder:
+        # the decoder sampler (App. A decoder MLP, random weights) drawing
+        # iteration 0 of the headline plan
+        out["decoder"] = {}
+        dec = workload.decoder_weights(0)
+        for name, prec in (("f32", 0), ("fp16_split", 1)):
+            print(f"[bench] plan from the decoder sampler, {name}", file=sys.stderr, flush=True)
+            eld, msd, cntd, resd = time_plan(pl, torch, c, scene, prec, args.steps, args.warmup, decoder=dec)
+            dms = msd["decoder"] / max(1, cntd["decoder"])
+            out["decoder"][name] = {
+                "value": N * L * args.steps / eld, "unit": "QP-solves/s", "ms_per_plan": 1e3 * eld / args.steps,
+                "decoder_ms_per_plan": dms, "lower_avg_ms": msd["lower"] / max(1, cntd["lower"]),
+                "decoder_alg_tflops": N * DECODER_FLOPS / (dms * 1e-3) / 1e12,
+                "decoder_mfma_frac": N * DECODER_MFMA_FLOPS / (dms * 1e-3) / 2.5e15,
+                "plan": {"best_index": resd.best_index, "cost_upper": resd.cost_upper, "residual": resd.residual}}
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(scene, c, threads)

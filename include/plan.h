@@ -52,6 +52,10 @@ extern "C" {
 #define PLAN_MAX_N 4096 /* behavioural samples per request                */
 #define PLAN_MAX_L 16   /* upper-level iterations                         */
 #define PLAN_MAX_ROAD 64 /* knots of a road profile                       */
+#define PLAN_OBS_DIM 55    /* observation o of the decoder sampler (App. A) */
+#define PLAN_LATENT_DIM 2  /* latent z of the decoder sampler               */
+#define PLAN_DEC_HIDDEN 1024 /* outputs of decoder blocks 1-4               */
+#define PLAN_DEC_HIDDEN5 256 /* outputs of decoder block 5                  */
 
 typedef enum plan_status {
   PLAN_OK = 0,
@@ -109,9 +113,19 @@ typedef enum plan_precision {
  * (GRID: lane centre j mod 3, velocity at the midpoint of bin floor(j/3) of
  * ceil(N/3) equal bins of (vd_lo, vd_hi], held over the horizon). With
  * upper_iters = 1 the grid gives the MPC-Grid baseline of Sec. V-A.
+ * DECODER: the learned sampler of Sec. III-D / App. A at inference. Sample j
+ * is the decoder MLP (weights from plan_set_decoder) applied to [o, z_j],
+ * o the request's observation and z_j ~ N(0, I) (2-d: the Box-Muller pair of
+ * Philox block (j, 0, 0, 0) under the request's seed); with goal positions
+ * its p[2..7] are 0. The distribution before the first update is then the
+ * sample mean and covariance (normalised by N) of the N decoder samples.
  */
 typedef enum plan_behaviour { PLAN_BEHAV_SETPOINTS = 0, PLAN_BEHAV_GOALS = 1 } plan_behaviour;
-typedef enum plan_sampler_t { PLAN_SAMPLER_RANDOM = 0, PLAN_SAMPLER_GRID = 1 } plan_sampler_t;
+typedef enum plan_sampler_t {
+  PLAN_SAMPLER_RANDOM = 0,
+  PLAN_SAMPLER_GRID = 1,
+  PLAN_SAMPLER_DECODER = 2
+} plan_sampler_t;
 
 /*
  * Configuration. plan_config_init() fills the defaults; every point the paper
@@ -205,6 +219,12 @@ typedef struct plan_config {
  *                the sample stream, so a request started from the
  *                distribution of iteration l with first_iter = l draws the
  *                same samples as iteration l of a longer run.
+ *   observation  host, PLAN_OBS_DIM doubles: the observation o the decoder
+ *                sampler conditions on (Sec. V-A lists ego heading and
+ *                speeds, the ten nearest neighbours and the road boundary;
+ *                its layout and scaling are those the weights were trained
+ *                with). Required, and finite, when the config's sampler is
+ *                PLAN_SAMPLER_DECODER; ignored otherwise. Copied at the call.
  */
 typedef struct plan_request {
   uint64_t request_id;
@@ -220,6 +240,7 @@ typedef struct plan_request {
   int32_t n_road;
   double road_x0, road_dx;
   const double *road;
+  const double *observation;
 } plan_request;
 
 /*
@@ -385,13 +406,50 @@ plan_status plan_mpc_run(plan_handle *h, const plan_request *reqs, int32_t n,
                          int32_t cycles, int32_t n_exec, int32_t init,
                          plan_mpc_log *log, plan_result *out);
 
+/*
+ * Weights of the decoder sampler (App. A, decoder table: five blocks of
+ * Linear, BatchNorm and ReLU with 1024, 1024, 1024, 1024 and 256 outputs,
+ * then Linear to the PLAN_NP behavioural inputs; the input is [o, z],
+ * PLAN_OBS_DIM + PLAN_LATENT_DIM values). All host, row-major doubles:
+ *   W[i]   block i's Linear weights, out x in (W[0]: 1024 x 57, W[1..3]:
+ *          1024 x 1024, W[4]: 256 x 1024, W[5]: PLAN_NP x 256)
+ *   b[i]   its bias (out)
+ *   bn_gamma[i], bn_beta[i], bn_mean[i], bn_var[i]   BatchNorm of blocks
+ *          0..4 in inference form: gamma (h - mean) / sqrt(var + eps) + beta
+ *   bn_eps eps of that form (PyTorch's default is 1e-5)
+ */
+typedef struct plan_decoder {
+  const double *W[6];
+  const double *b[6];
+  const double *bn_gamma[5];
+  const double *bn_beta[5];
+  const double *bn_mean[5];
+  const double *bn_var[5];
+  double bn_eps;
+} plan_decoder;
+
+/* Load the decoder sampler's weights (needed before any request of a
+ * handle whose config has sampler = PLAN_SAMPLER_DECODER). The library
+ * folds each BatchNorm and bias into its Linear layer in FP64 and keeps the
+ * layers on the device: the first in FP32, blocks 2-5 as FP16 high/low
+ * pairs (three matrix-core products recover about 22 significant bits, as
+ * the lower level's FP16-split form does), the output layer in FP32. The
+ * arrays are copied; the call waits for the upload. PLAN_E_INVALID for a
+ * handle without the decoder sampler, a missing or non-finite array, a
+ * variance with var + eps <= 0, or weights beyond 1e30 in magnitude;
+ * PLAN_E_BUSY while served requests are in flight. Hidden activations must
+ * stay below 65504 in magnitude (FP16 range). */
+plan_status plan_set_decoder(plan_handle *h, const plan_decoder *dec);
+
 /* Kernel timing by HIP events recorded on the library's stream around every
- * launch of plan_launch / plan_solve_batch. enable != 0 starts recording (and
- * clears the totals); plan_profile_read waits for the stream and returns the
- * summed milliseconds and launch counts per kernel: [0] lower level
- * (sampling, Steps 1-2, residual/cost), [1] selection / update. */
+ * launch of plan_launch / plan_solve_batch / plan_progress. enable != 0
+ * starts recording (and clears the totals); plan_profile_read waits for the
+ * stream and returns the summed milliseconds and launch counts per part:
+ * [0] lower level (sampling, Steps 1-2, residual/cost), [1] selection /
+ * update, [2] decoder sampler (all of its kernels for one upper iteration
+ * count as one launch). */
 plan_status plan_profile(plan_handle *h, int32_t enable);
-plan_status plan_profile_read(plan_handle *h, double ms[2], int64_t count[2]);
+plan_status plan_profile_read(plan_handle *h, double ms[3], int64_t count[3]);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ PLAN_PREC_FP32, PLAN_PREC_FP16_SPLIT = 0, 1
 PLAN_F_INFEASIBLE, PLAN_F_WARM = 1, 2
 PLAN_MPC_SAMPLER, PLAN_MPC_WARM = 0, 1
 PLAN_BEHAV_SETPOINTS, PLAN_BEHAV_GOALS = 0, 1
-PLAN_SAMPLER_RANDOM, PLAN_SAMPLER_GRID = 0, 1
+PLAN_SAMPLER_RANDOM, PLAN_SAMPLER_GRID, PLAN_SAMPLER_DECODER = 0, 1, 2
+PLAN_OBS_DIM = 55  # observation of the decoder sampler
 PLAN_MAX_ROAD = 64  # knots of a request's road profile
 NC, NX, NP = 11, 22, 8
 MAX_N, MAX_M, MAX_T, MAX_ROAD = 4096, 32, 256, 64
@@ -73,6 +74,15 @@ class plan_request(C.Structure):
         ("first_iter", C.c_int32),
         ("n_road", C.c_int32), ("road_x0", C.c_double), ("road_dx", C.c_double),
         ("road", _PD),
+        ("observation", _PD),
+    ]
+
+
+class plan_decoder(C.Structure):
+    _fields_ = [
+        ("W", _PD * 6), ("b", _PD * 6),
+        ("bn_gamma", _PD * 5), ("bn_beta", _PD * 5), ("bn_mean", _PD * 5), ("bn_var", _PD * 5),
+        ("bn_eps", C.c_double),
     ]
 
 
@@ -129,9 +139,10 @@ def load():
     lib.plan_mpc_run.argtypes = [H, Req, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(plan_mpc_log), Res]
     lib.plan_profile.argtypes = [H, C.c_int32]
     lib.plan_profile_read.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.plan_set_decoder.argtypes = [H, C.POINTER(plan_decoder)]
     for name in ("plan_create", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
                  "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-                 "plan_mpc_run", "plan_profile", "plan_profile_read"):
+                 "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -141,7 +152,7 @@ def exported_symbols() -> list[str]:
     return ["plan_config_init", "plan_workspace_bytes", "plan_create", "plan_destroy",
             "plan_last_error", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
             "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-            "plan_mpc_run", "plan_profile", "plan_profile_read"]
+            "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder"]
 
 
 def _check(status: int, handle=None) -> int:
@@ -174,6 +185,7 @@ class Request:
     road: np.ndarray | None = None  # n x 3: kappa, y_lb, y_ub at road_x0 + i road_dx
     road_x0: float = 0.0
     road_dx: float = 1.0
+    observation: np.ndarray | None = None  # PLAN_OBS_DIM values (decoder sampler)
 
     @property
     def M(self) -> int:
@@ -211,6 +223,12 @@ class _Marshalled:
                 c.mu0, c.sigma0 = _pd(mu), _pd(sg)
             else:
                 c.mu0 = c.sigma0 = None
+            if r.observation is not None:
+                o = np.ascontiguousarray(np.asarray(r.observation, np.float64).reshape(PLAN_OBS_DIM))
+                self.keep.append(o)
+                c.observation = _pd(o)
+            else:
+                c.observation = None
 
 
 @dataclass
@@ -404,12 +422,31 @@ def plan_profile(h: Handle, enable: bool = True) -> None:
 
 
 def plan_profile_read(h: Handle):
-    """Returns ({'lower','select'}: total ms, same: launch count)."""
-    ms = (C.c_double * 2)()
-    cnt = (C.c_int64 * 2)()
+    """Returns ({'lower','select','decoder'}: total ms, same: launch count)."""
+    ms = (C.c_double * 3)()
+    cnt = (C.c_int64 * 3)()
     _check(load().plan_profile_read(h.ptr, ms, cnt), h.ptr)
-    names = ("lower", "select")
+    names = ("lower", "select", "decoder")
     return {k: ms[i] for i, k in enumerate(names)}, {k: cnt[i] for i, k in enumerate(names)}
+
+
+def plan_set_decoder(h: Handle, dec) -> None:
+    """Load the decoder sampler's weights. ``dec`` has W, b (6 each, W out x
+    in), gamma, beta, mean, var (5 each) and eps, as workload.Decoder."""
+    c = plan_decoder()
+    keep = []
+
+    def arr(v):
+        a = np.ascontiguousarray(np.asarray(v, np.float64))
+        keep.append(a)
+        return _pd(a)
+    for i in range(6):
+        c.W[i], c.b[i] = arr(dec.W[i]), arr(dec.b[i])
+    for i in range(5):
+        c.bn_gamma[i], c.bn_beta[i] = arr(dec.gamma[i]), arr(dec.beta[i])
+        c.bn_mean[i], c.bn_var[i] = arr(dec.mean[i]), arr(dec.var[i])
+    c.bn_eps = float(dec.eps)
+    _check(load().plan_set_decoder(h.ptr, C.byref(c)), h.ptr)
 
 
 def elite_sizes(cfg: plan_config, N: int) -> tuple[int, int]:

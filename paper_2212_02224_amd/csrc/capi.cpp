@@ -36,6 +36,8 @@ hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblo
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1);
 hipError_t launch_advance(const AdvArgs &a, const MethodParams &p, int n, hipStream_t st);
+hipError_t launch_decoder(const DecArgs &a, int total_rows, int n_cu, hipStream_t st, hipEvent_t ev0,
+                          hipEvent_t ev1);
 }  // namespace plan
 
 using namespace plan;
@@ -133,16 +135,37 @@ struct Layout {
   size_t desc = 0, dist = 0, result = 0, act = 0;
   size_t p = 0, zs = 0, rc = 0, sess = 0, xiout = 0;
   size_t tr_p = 0, tr_rc = 0, tr_idx = 0, tr_dist = 0;
+  size_t dec_tab = 0, dec_act = 0, dec_seg = 0;  // decoder sampler
   size_t total() const {
     size_t s = 0;
     for (size_t b : {basis, step1, proj, offs, mops, mainv, desc, dist, result, act, p, zs, rc, sess, xiout,
-                     tr_p, tr_rc, tr_idx, tr_dist})
+                     tr_p, tr_rc, tr_idx, tr_dist, dec_tab, dec_act, dec_seg})
       s += (b + 255) & ~(size_t)255;
     return s;
   }
 };
 
 int max_sessions(const plan_config &c) { return std::max(64, 2 * c.max_requests); }
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Pieces of the decoder tables, each taken 256-aligned, in carve order:
+// blocks 1-5 (W hi, W lo, shift), W6, b6.
+const int kDecNin[kDecLayers] = {kDecInPad, kDecHidden, kDecHidden, kDecHidden, kDecHidden};
+const int kDecNout[kDecLayers] = {kDecHidden, kDecHidden, kDecHidden, kDecHidden, kDecHidden5};
+constexpr int kDecPieces = 3 * kDecLayers + 2;
+size_t dec_piece(int i) {
+  if (i < 3 * kDecLayers) {
+    const int L = i / 3, part = i % 3;
+    return part < 2 ? (size_t)kDecNout[L] * kDecNin[L] * 2 : (size_t)kDecNout[L] * 4;
+  }
+  if (i == 3 * kDecLayers) return (size_t)PLAN_NP * kDecHidden5 * 4;
+  return (size_t)PLAN_NP * 4;
+}
+
+// Rows of the decoder's activation buffers: a chunk, rounded up to whole
+// 16-row blocks (the matrix-core layout stores the last partial block whole).
+int dec_chunk(int64_t rows) { return (int)((std::min<int64_t>(rows, kDecChunk) + 15) / 16 * 16); }
 
 Layout compute_layout(const plan_config &c) {
   Layout L;
@@ -173,6 +196,11 @@ Layout compute_layout(const plan_config &c) {
     L.tr_idx = S * Lit * (size_t)(n + q) * 4;
     L.tr_dist = S * Lit * 72 * 8;
   }
+  if (c.sampler == PLAN_SAMPLER_DECODER) {
+    for (int i = 0; i < kDecPieces; ++i) L.dec_tab += round256(dec_piece(i));
+    L.dec_act = 2 * round256((size_t)dec_chunk(R) * kDecInPad * 2) + 4 * round256((size_t)dec_chunk(R) * kDecHidden * 2);
+    L.dec_seg = S * sizeof(DecSeg);
+  }
   return L;
 }
 
@@ -200,7 +228,8 @@ const char *validate_config(const plan_config &c) {
   if (n > kMaxCes) return "ConstraintEliteSet larger than 1024 samples is not supported";
   if (q > kMaxEs) return "EliteSet larger than 256 samples is not supported";
   if (c.behaviour != PLAN_BEHAV_SETPOINTS && c.behaviour != PLAN_BEHAV_GOALS) return "unknown behaviour";
-  if (c.sampler != PLAN_SAMPLER_RANDOM && c.sampler != PLAN_SAMPLER_GRID) return "unknown sampler";
+  if (c.sampler != PLAN_SAMPLER_RANDOM && c.sampler != PLAN_SAMPLER_GRID && c.sampler != PLAN_SAMPLER_DECODER)
+    return "unknown sampler";
   if (c.behaviour == PLAN_BEHAV_GOALS && !(c.w_s > 0)) return "goal positions need w_s > 0 (the cost is c_s alone)";
   if (c.precision != PLAN_PREC_FP32 && c.precision != PLAN_PREC_FP16_SPLIT) return "unsupported precision";
   if (mfma_mode(c))
@@ -212,8 +241,8 @@ const char *validate_config(const plan_config &c) {
 // A queued request of the served mode, owning copies of its arrays.
 struct Pending {
   uint64_t ticket = 0;
-  plan_request req{};
-  std::vector<double> obs, mu0, sigma0;
+  plan_request req{};  // the scalars; every array it points to is copied into desc
+  ReqDesc desc{};      // validated at submit
   Clock::time_point submit;
 };
 
@@ -286,8 +315,17 @@ struct plan_handle {
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-  double prof_ms[2] = {0, 0};
-  int64_t prof_count[2] = {0, 0};
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_count[3] = {0, 0, 0};
+  // decoder sampler
+  bool dec_ready = false;
+  float *dec_w6 = nullptr, *dec_b6 = nullptr;
+  uint16_t *dec_whi[kDecLayers] = {}, *dec_wlo[kDecLayers] = {};
+  float *dec_shift[kDecLayers] = {};
+  float dec_inv_scale[kDecLayers] = {1, 1, 1, 1, 1};
+  uint16_t *dec_x[2] = {};    // input hi, lo
+  uint16_t *dec_act[4] = {};  // ping-pong: hi 0, lo 0, hi 1, lo 1
+  DecSeg *dec_seg = nullptr, *h_seg = nullptr;
 };
 
 namespace {
@@ -362,6 +400,11 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   if ((r.mu0 == nullptr) != (r.sigma0 == nullptr)) return "mu0 and sigma0 must be given together";
   if (r.mu0 && (!finite_all(r.mu0, 8) || !finite_all(r.sigma0, 64))) return "non-finite mu0/sigma0";
   if (r.first_iter < 0 || r.first_iter > (1 << 20)) return "first_iter out of range";
+  if (c.sampler == PLAN_SAMPLER_DECODER) {
+    if (!h->dec_ready) return "decoder weights not set (plan_set_decoder)";
+    if (!r.observation) return "observation missing (the decoder sampler needs one)";
+    if (!finite_all(r.observation, PLAN_OBS_DIM)) return "non-finite observation";
+  }
   if (r.n_road < 0 || r.n_road > PLAN_MAX_ROAD) return "n_road out of range";
   if (r.n_road > 0) {
     if (!r.road) return "road profile missing";
@@ -390,6 +433,8 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   d.road_dx = r.n_road > 1 ? r.road_dx : 1.0;
   for (int i = 0; i < r.n_road; ++i)
     for (int k = 0; k < 3; ++k) d.road[i][k] = r.road[3 * i + k];
+  if (c.sampler == PLAN_SAMPLER_DECODER)
+    for (int k = 0; k < PLAN_OBS_DIM; ++k) d.obsv[k] = r.observation[k];
   for (int i = 0; i < r.M; ++i)
     for (int k = 0; k < 4; ++k) d.obs[i][k] = r.obstacles[4 * i + k];
   if (r.mu0) {
@@ -694,10 +739,55 @@ plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int firs
   return upload_launch_set(h, h->ls);
 }
 
+// Decoder sampler: the samples of every listed slot that starts from the
+// initial sampler (no given distribution, no warm start) at this upper
+// iteration, written into the slots' sample rows before the lower level
+// reads them.
+plan_status decode_slots(plan_handle *h, const int *slots, int n) {
+  if (h->cfg.sampler != PLAN_SAMPLER_DECODER) return PLAN_OK;
+  int nseg = 0, rows = 0;
+  for (int i = 0; i < n; ++i) {
+    const ReqDesc &d = h->h_desc[slots[i]];
+    if (d.init_mode != kInitStructured) continue;
+    h->h_seg[nseg++] = DecSeg{slots[i], rows, d.N, 0};
+    rows += d.N;
+  }
+  if (nseg == 0) return PLAN_OK;
+  HIP_TRY(h, hipMemcpyAsync(h->dec_seg, h->h_seg, sizeof(DecSeg) * nseg, hipMemcpyHostToDevice, h->stream));
+  DecArgs a{};
+  a.desc = h->desc;
+  a.seg = h->dec_seg;
+  a.nseg = nseg;
+  for (int L = 0; L < kDecLayers; ++L)
+    a.layer[L] = DecLayer{h->dec_whi[L], h->dec_wlo[L], h->dec_shift[L], h->dec_inv_scale[L], kDecNin[L],
+                          kDecNout[L]};
+  a.x_hi = h->dec_x[0];
+  a.x_lo = h->dec_x[1];
+  a.w6 = h->dec_w6;
+  a.b6 = h->dec_b6;
+  a.act_hi[0] = h->dec_act[0];
+  a.act_lo[0] = h->dec_act[1];
+  a.act_hi[1] = h->dec_act[2];
+  a.act_lo[1] = h->dec_act[3];
+  a.p = h->p;
+  a.behaviour = h->cfg.behaviour;
+  return timed(
+      h, 2, [&](hipEvent_t e0, hipEvent_t e1) { return launch_decoder(a, rows, h->n_cu, h->stream, e0, e1); },
+      "decoder sampler");
+}
+
 plan_status launch_impl(plan_handle *h) {
   if (h->staged == 0) return PLAN_OK;
   plan_status st = PLAN_OK;
-  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) st = launch_iteration(h, h->ls, l);
+  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) {
+    if (l == 0 && h->cfg.sampler == PLAN_SAMPLER_DECODER) {
+      std::vector<int> slots(h->staged);  // batch requests hold slots 0..staged-1
+      for (int i = 0; i < h->staged; ++i) slots[i] = i;
+      st = decode_slots(h, slots.data(), h->staged);
+      if (st != PLAN_OK) break;
+    }
+    st = launch_iteration(h, h->ls, l);
+  }
   return st;
 }
 
@@ -790,6 +880,7 @@ void free_handle(plan_handle *h) {
   if (h->h_act) hipHostFree(h->h_act);
   if (h->h_result) hipHostFree(h->h_result);
   if (h->h_dist) hipHostFree(h->h_dist);
+  if (h->h_seg) hipHostFree(h->h_seg);
   delete h;
 }
 
@@ -935,7 +1026,22 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     h->tr_mu = (double *)h->mem.take(L.tr_dist);
     h->tr_sigma = h->tr_mu + S * c.upper_iters * 8;
   }
-  if (!h->xi_out || (c.trace && !h->tr_mu)) {
+  if (c.sampler == PLAN_SAMPLER_DECODER) {
+    void *piece[kDecPieces];
+    for (int i = 0; i < kDecPieces; ++i) piece[i] = h->mem.take(dec_piece(i));
+    for (int Lr = 0; Lr < kDecLayers; ++Lr) {
+      h->dec_whi[Lr] = (uint16_t *)piece[3 * Lr];
+      h->dec_wlo[Lr] = (uint16_t *)piece[3 * Lr + 1];
+      h->dec_shift[Lr] = (float *)piece[3 * Lr + 2];
+    }
+    h->dec_w6 = (float *)piece[3 * kDecLayers];
+    h->dec_b6 = (float *)piece[3 * kDecLayers + 1];
+    const int chunk = dec_chunk(R);
+    for (int i = 0; i < 2; ++i) h->dec_x[i] = (uint16_t *)h->mem.take((size_t)chunk * kDecInPad * 2);
+    for (int i = 0; i < 4; ++i) h->dec_act[i] = (uint16_t *)h->mem.take((size_t)chunk * kDecHidden * 2);
+    h->dec_seg = (DecSeg *)h->mem.take(L.dec_seg);
+  }
+  if (!h->xi_out || (c.trace && !h->tr_mu) || (c.sampler == PLAN_SAMPLER_DECODER && !h->dec_seg)) {
     g_create_error = "internal: workspace carve failed";
     free_handle(h);
     return PLAN_E_NOMEM;
@@ -964,6 +1070,8 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_act, sizeof(int32_t) * (2 * S + 8));
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_result, sizeof(ResultRec) * S);
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_dist, sizeof(DistState) * S);
+  if (e == hipSuccess && c.sampler == PLAN_SAMPLER_DECODER)
+    e = hipHostMalloc((void **)&h->h_seg, sizeof(DecSeg) * S);
   // ---- upload tables
   if (e == hipSuccess) {
     std::vector<float> basis_all;
@@ -1067,6 +1175,8 @@ plan_status plan_mpc_run(plan_handle *h, const plan_request *reqs, int32_t n, in
   if (n > h->cfg.max_requests) return fail(h, PLAN_E_INVALID, "more episodes than max_requests");
   if (cycles < 1 || cycles > (1 << 20)) return fail(h, PLAN_E_INVALID, "cycles out of range");
   if (init != PLAN_MPC_SAMPLER && init != PLAN_MPC_WARM) return fail(h, PLAN_E_INVALID, "unknown init mode");
+  if (h->cfg.sampler == PLAN_SAMPLER_DECODER)
+    return fail(h, PLAN_E_UNSUPPORTED, "the closed loop has no per-cycle observation for the decoder sampler");
   std::unordered_map<uint64_t, int> seen;
   for (int i = 0; i < n; ++i) {
     if (n_exec < 1 || n_exec > reqs[i].T - 1)
@@ -1243,17 +1353,14 @@ plan_status plan_get_trace(plan_handle *h, int32_t i, double *p, double *resid, 
 
 plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticket) {
   if (!h || !req || !ticket) return fail(h, PLAN_E_INVALID, "bad arguments");
-  ReqDesc tmp;
-  if (const char *why = check_request(h, *req, tmp)) return fail(h, PLAN_E_INVALID, why);
-  if (req->N > h->rows) return fail(h, PLAN_E_NOMEM, "request larger than the sample budget");
   Pending pd;
+  if (const char *why = check_request(h, *req, pd.desc)) return fail(h, PLAN_E_INVALID, why);
+  if (req->N > h->rows) return fail(h, PLAN_E_NOMEM, "request larger than the sample budget");
   pd.ticket = h->next_ticket++;
   pd.req = *req;
-  if (req->M > 0) pd.obs.assign(req->obstacles, req->obstacles + 4 * req->M);
-  if (req->mu0) {
-    pd.mu0.assign(req->mu0, req->mu0 + 8);
-    pd.sigma0.assign(req->sigma0, req->sigma0 + 64);
-  }
+  pd.req.obstacles = nullptr;
+  pd.req.mu0 = pd.req.sigma0 = nullptr;
+  pd.req.road = nullptr;
   pd.submit = Clock::now();
   *ticket = pd.ticket;
   h->queue.push_back(std::move(pd));
@@ -1276,12 +1383,9 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
       }
     int64_t off = 0;
     if (slot < 0 || !take_rows(h, pd.req.N, off)) break;
-    plan_request r = pd.req;
-    r.obstacles = pd.obs.empty() ? nullptr : pd.obs.data();
-    r.mu0 = pd.mu0.empty() ? nullptr : pd.mu0.data();
-    r.sigma0 = pd.sigma0.empty() ? nullptr : pd.sigma0.data();
+    const plan_request &r = pd.req;
     ReqDesc &d = h->h_desc[slot];
-    check_request(h, r, d);  // validated at submit
+    d = pd.desc;
     resolve_session(h, r.session_id, d, r.session_id != 0);
     d.row_off = off;
     d.cur_iter = 0;
@@ -1315,6 +1419,12 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
     LaunchSet ls;
     make_launch_set(h, slots.data(), n_act, ls);
     plan_status st = upload_launch_set(h, ls);
+    if (st == PLAN_OK && h->cfg.sampler == PLAN_SAMPLER_DECODER) {
+      std::vector<int> first;
+      for (int i = 0; i < n_act; ++i)
+        if (h->resident[i].iters == 0) first.push_back(h->resident[i].slot);
+      st = decode_slots(h, first.data(), (int)first.size());
+    }
     if (st == PLAN_OK) st = launch_iteration(h, ls, -1);
     if (st != PLAN_OK) return st;
     std::vector<int> finished;
@@ -1363,12 +1473,39 @@ plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out) {
   return fail(h, PLAN_E_INVALID, "unknown ticket");
 }
 
+plan_status plan_set_decoder(plan_handle *h, const plan_decoder *dec) {
+  if (!h || !dec) return fail(h, PLAN_E_INVALID, "bad arguments");
+  if (h->cfg.sampler != PLAN_SAMPLER_DECODER)
+    return fail(h, PLAN_E_INVALID, "the config's sampler is not PLAN_SAMPLER_DECODER");
+  if (!h->resident.empty() || !h->queue.empty())
+    return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them first");
+  DecoderTables t;
+  if (const char *why = build_decoder(*dec, t)) return fail(h, PLAN_E_INVALID, why);
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
+  };
+  hipError_t e = hipSuccess;
+  for (int L = 0; e == hipSuccess && L < kDecLayers; ++L) {
+    e = up(h->dec_whi[L], t.w_hi[L].data(), t.w_hi[L].size() * 2);
+    if (e == hipSuccess) e = up(h->dec_wlo[L], t.w_lo[L].data(), t.w_lo[L].size() * 2);
+    if (e == hipSuccess) e = up(h->dec_shift[L], t.shift[L].data(), t.shift[L].size() * 4);
+  }
+  if (e == hipSuccess) e = up(h->dec_w6, t.w6.data(), t.w6.size() * 4);
+  if (e == hipSuccess) e = up(h->dec_b6, t.b6.data(), t.b6.size() * 4);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "decoder upload");
+  for (int L = 0; L < kDecLayers; ++L) h->dec_inv_scale[L] = t.inv_scale[L];
+  h->dec_ready = true;
+  return PLAN_OK;
+}
+
 plan_status plan_profile(plan_handle *h, int32_t enable) {
   if (!h) return PLAN_E_INVALID;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   for (auto &e : h->ev_pending) h->ev_free.push_back(e.second);
   h->ev_pending.clear();
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     h->prof_ms[k] = 0.0;
     h->prof_count[k] = 0;
   }
@@ -1376,7 +1513,7 @@ plan_status plan_profile(plan_handle *h, int32_t enable) {
   return PLAN_OK;
 }
 
-plan_status plan_profile_read(plan_handle *h, double ms[2], int64_t count[2]) {
+plan_status plan_profile_read(plan_handle *h, double ms[3], int64_t count[3]) {
   if (!h || !ms || !count) return fail(h, PLAN_E_INVALID, "bad arguments");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   for (auto &e : h->ev_pending) {
@@ -1387,7 +1524,7 @@ plan_status plan_profile_read(plan_handle *h, double ms[2], int64_t count[2]) {
     h->ev_free.push_back(e.second);
   }
   h->ev_pending.clear();
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     ms[k] = h->prof_ms[k];
     count[k] = h->prof_count[k];
   }

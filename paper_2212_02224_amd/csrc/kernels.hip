@@ -38,6 +38,7 @@
 #include <stdint.h>
 
 #include "plan_internal.h"
+#include "rng.h"
 
 namespace plan {
 
@@ -126,47 +127,7 @@ __device__ __forceinline__ float reduce16(const float (&v)[16], int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the request
-// seed; counter (sample, upper iteration, block, 0). Box-Muller turns pairs of
-// uniforms in (0, 1] into normals.
-
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    uint32_t lo0 = 0xD2511F53u * c[0];
-    uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
-    uint32_t lo1 = 0xCD9E8D57u * c[2];
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
-    uint32_t n0 = hi1 ^ c[1] ^ k0;
-    uint32_t n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
-__device__ __forceinline__ void rng_block(uint64_t seed, int j, int l, int blk, uint32_t w[4]) {
-  w[0] = (uint32_t)j;
-  w[1] = (uint32_t)l;
-  w[2] = (uint32_t)blk;
-  w[3] = 0u;
-  philox4x32_10(w, (uint32_t)seed, (uint32_t)(seed >> 32));
-}
-
-__device__ __forceinline__ float u01(uint32_t x) {
-  return (float)((x >> 8) + 1u) * (1.0f / 16777216.0f);
-}
-
-__device__ __forceinline__ void normals2(uint32_t a, uint32_t b, float &n0, float &n1) {
-  float rad = sqrtf(-2.0f * logf(u01(a)));
-  float s, c;
-  sincospif(2.0f * u01(b), &s, &c);
-  n0 = rad * c;
-  n1 = rad * s;
-}
+// Random numbers: rng.h (Philox4x32-10 and Box-Muller).
 
 // Lower Cholesky factor of A + jitter I (8x8, FP64). Returns false if not
 // positive definite.
@@ -583,6 +544,12 @@ __device__ void stage_neighbours(const ReqDesc &D, const MethodParams &P, float4
   }
 }
 
+// Iteration 0 of a request that starts from the initial sampler when that is
+// the decoder sampler: its samples are in the rows, written by the decoder.
+__device__ __forceinline__ bool decoded_start(const ReqDesc &D, const MethodParams &P, int l) {
+  return l == 0 && D.init_mode == kInitStructured && P.sampler == PLAN_SAMPLER_DECODER;
+}
+
 // Road profile knots into LDS as (kappa, y_lb, y_ub, 0).
 __device__ void stage_road(const ReqDesc &D, float4 *s_road) {
   for (int i = threadIdx.x; i < D.n_road; i += blockDim.x)
@@ -759,7 +726,8 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 
   stage_neighbours(D, P, s_obs);
   if constexpr (ROAD) stage_road(D, s_road);
-  const bool forced = D.init_mode == kInitForced;
+  // samples in the rows already: the caller's, or the decoder sampler's
+  const bool forced = D.init_mode == kInitForced || decoded_start(D, P, l);
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
   if (!forced && !structured) load_distribution(A, D, P, bi.x, l, s_mu, s_chol);
   const Scal S = make_scal(D, P);
@@ -1049,7 +1017,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   }
   stage_neighbours(D, P, s_obs);
   if constexpr (ROAD) stage_road(D, s_road);
-  const bool forced = D.init_mode == kInitForced;
+  const bool forced = D.init_mode == kInitForced || decoded_start(D, P, l);
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
   if (!forced && !structured) load_distribution(A, D, P, slot, l, s_mu, s_chol);
   const Scal S = make_scal(D, P);
@@ -1518,6 +1486,74 @@ __device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t 
   __syncthreads();
 }
 
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sample mean and covariance (normalised by N) of the rows p[0..N) (x 8),
+// FP64, two passes: the prior of the first update when the samples come
+// from the decoder sampler. Thread t sums rows t, t + 256, ...; each wave
+// sums its lanes in a fixed butterfly order and the four wave sums meet in
+// LDS (part), so the result does not depend on timing.
+__device__ void sample_moments(const float *p, int N, double *s_mu, double *s_sig, double (*part)[64 + 8]) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  double m[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) m[a] = 0.0;
+  for (int i = tid; i < N; i += kSelBlock) {
+    const float4 u = reinterpret_cast<const float4 *>(p + (size_t)i * 8)[0];
+    const float4 v = reinterpret_cast<const float4 *>(p + (size_t)i * 8)[1];
+    const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) m[a] += (double)x[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) m[a] = wave_sum_d(m[a]);
+  if (lane == 0)
+    for (int a = 0; a < 8; ++a) part[w][a] = m[a];
+  __syncthreads();
+  if (tid < 8) s_mu[tid] = (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]) / (double)N;
+  __syncthreads();
+  double mu[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) mu[a] = s_mu[a];
+  double c[36];  // upper triangle, row by row
+#pragma unroll
+  for (int k = 0; k < 36; ++k) c[k] = 0.0;
+  for (int i = tid; i < N; i += kSelBlock) {
+    const float4 u = reinterpret_cast<const float4 *>(p + (size_t)i * 8)[0];
+    const float4 v = reinterpret_cast<const float4 *>(p + (size_t)i * 8)[1];
+    const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+    double d[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) d[a] = (double)x[a] - mu[a];
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = a; b < 8; ++b) c[k++] += d[a] * d[b];
+  }
+#pragma unroll
+  for (int k = 0; k < 36; ++k) c[k] = wave_sum_d(c[k]);
+  __syncthreads();  // part is read above
+  if (lane == 0)
+    for (int k = 0; k < 36; ++k) part[w][k] = c[k];
+  __syncthreads();
+  if (tid < 64) {
+    int a = tid >> 3, b = tid & 7;
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int k = a * 8 - a * (a - 1) / 2 + (b - a);
+    s_sig[tid] = (((part[0][k] + part[1][k]) + part[2][k]) + part[3][k]) / (double)N;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, MethodParams P) {
   __shared__ uint32_t s_key[PLAN_MAX_N];  // residual keys
   __shared__ float s_c[PLAN_MAX_N];       // c_u + r
@@ -1554,7 +1590,16 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
     s_c[i] = cc + rr;
   }
   // Distribution before this update: the prior at iteration 0.
-  if (l == 0) {
+  if (l == 0 && decoded_start(D, P, l)) {
+    sample_moments(p, N, s_mu, s_sig, s_part);
+    if (tid == 0) {
+      bool fin = true;
+      for (int i = 0; i < 8; ++i) fin &= isfinite(s_mu[i]);
+      for (int i = 0; i < 64; ++i) fin &= isfinite(s_sig[i]);
+      R.status = fin ? 0 : PLAN_E_INVALID;  // e.g. a decoder activation beyond the FP16 range
+      R.iterations = 0;
+    }
+  } else if (l == 0) {
     if (tid == 0) {
       int ok = 1;
       if (D.init_mode == kInitStructured) {

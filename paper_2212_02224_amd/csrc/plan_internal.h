@@ -70,6 +70,7 @@ struct ReqDesc {
   int32_t n_road;    // road profile: 0 = constant kappa and lane limits
   double road_x0, road_dx;
   double road[PLAN_MAX_ROAD][3];  // kappa, y_lb, y_ub per knot
+  double obsv[PLAN_OBS_DIM];      // observation of the decoder sampler
 };
 
 // Sampling distribution of one slot (FP64).
@@ -149,6 +150,46 @@ struct SelArgs {
   double *tr_mu;             // [slot][L][8]
   double *tr_sigma;          // [slot][L][64]
   int32_t max_N, max_ces, max_es;
+};
+
+// Decoder sampler (App. A decoder MLP at inference). Its samples are the
+// rows of the requests being decoded, concatenated: segment s covers
+// concatenated rows [row_begin, row_begin + n) = samples 0..n-1 of slot.
+// The kernels run on a chunk of at most kDecChunk concatenated rows at a
+// time: the input [o, z] padded to kDecInPad and the hidden activations live
+// in buffers of FP16 high/low pairs (row-major).
+constexpr int kDecIn = PLAN_OBS_DIM + PLAN_LATENT_DIM;  // 57
+constexpr int kDecInPad = 64;                           // K of block 1 on the matrix cores
+constexpr int kDecHidden = PLAN_DEC_HIDDEN;             // 1024
+constexpr int kDecHidden5 = PLAN_DEC_HIDDEN5;           // 256
+constexpr int kDecLayers = 5;                           // blocks on the matrix cores
+constexpr int kDecChunk = 16384;
+
+struct DecSeg {
+  int32_t slot, row_begin, n, pad;
+};
+
+// One block: out = relu(inv_scale * (W_scaled x) + shift), W_scaled = W' 2^e
+// split into FP16 high/low pairs (out x in, row-major), inv_scale = 2^-e,
+// W' and shift the Linear layer with its BatchNorm and bias folded in.
+struct DecLayer {
+  const uint16_t *w_hi, *w_lo;
+  const float *shift;
+  float inv_scale;
+  int32_t n_in, n_out;
+};
+
+struct DecArgs {
+  const ReqDesc *desc;
+  const DecSeg *seg;
+  int32_t nseg;
+  int32_t r0, nrows;          // chunk: concatenated rows [r0, r0 + nrows)
+  DecLayer layer[kDecLayers]; // blocks 1-5 (block 1: n_in = kDecInPad)
+  const float *w6, *b6;       // output layer [8][kDecHidden5], [8]
+  uint16_t *x_hi, *x_lo;      // input [kDecChunk][kDecInPad]
+  uint16_t *act_hi[2], *act_lo[2];  // hidden ping-pong [kDecChunk][kDecHidden]
+  float *p;                   // row pool [rows][8]
+  int32_t behaviour;
 };
 
 // Arguments of the closed-loop advance kernel (one workgroup per episode,

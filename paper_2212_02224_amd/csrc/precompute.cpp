@@ -431,4 +431,68 @@ void build_mfma_inverse(const ProjTable &pt, std::vector<uint16_t> &ops) {
     }
 }
 
+
+size_t dec_frag_half(int r, int k, int K) {
+  return ((((size_t)(r >> 4) * (K >> 5) + (k >> 5)) * 64 + (r & 15) + 16 * ((k >> 3) & 3)) << 3) + (k & 7);
+}
+
+const char *build_decoder(const plan_decoder &dec, DecoderTables &t) {
+  static const int n_in[6] = {kDecIn, kDecHidden, kDecHidden, kDecHidden, kDecHidden, kDecHidden5};
+  static const int n_out[6] = {kDecHidden, kDecHidden, kDecHidden, kDecHidden, kDecHidden5, PLAN_NP};
+  auto finite = [](const double *v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(v[i])) return false;
+    return true;
+  };
+  if (!std::isfinite(dec.bn_eps) || dec.bn_eps < 0) return "bn_eps must be finite and >= 0";
+  for (int i = 0; i < 6; ++i) {
+    if (!dec.W[i] || !dec.b[i]) return "decoder weights missing";
+    if (!finite(dec.W[i], (size_t)n_out[i] * n_in[i]) || !finite(dec.b[i], n_out[i]))
+      return "non-finite decoder weights";
+    if (i == 5) break;
+    if (!dec.bn_gamma[i] || !dec.bn_beta[i] || !dec.bn_mean[i] || !dec.bn_var[i]) return "BatchNorm arrays missing";
+    if (!finite(dec.bn_gamma[i], n_out[i]) || !finite(dec.bn_beta[i], n_out[i]) ||
+        !finite(dec.bn_mean[i], n_out[i]) || !finite(dec.bn_var[i], n_out[i]))
+      return "non-finite BatchNorm arrays";
+    for (int n = 0; n < n_out[i]; ++n)
+      if (!(dec.bn_var[i][n] + dec.bn_eps > 0)) return "BatchNorm var + eps must be > 0";
+  }
+  // folded block i: W' (out x in) and shift, FP64
+  auto fold = [&](int i, std::vector<double> &Wf, std::vector<double> &sh) {
+    Wf.assign((size_t)n_out[i] * n_in[i], 0.0);
+    sh.assign(n_out[i], 0.0);
+    for (int n = 0; n < n_out[i]; ++n) {
+      const double sc = dec.bn_gamma[i][n] / std::sqrt(dec.bn_var[i][n] + dec.bn_eps);
+      for (int k = 0; k < n_in[i]; ++k) Wf[(size_t)n * n_in[i] + k] = sc * dec.W[i][(size_t)n * n_in[i] + k];
+      sh[n] = sc * (dec.b[i][n] - dec.bn_mean[i][n]) + dec.bn_beta[i][n];
+    }
+  };
+  std::vector<double> Wf, sh;
+  for (int i = 0; i < kDecLayers; ++i) {
+    fold(i, Wf, sh);
+    double mx = 0.0;
+    for (double v : Wf) mx = std::max(mx, std::fabs(v));
+    if (mx > 1e30 || (mx > 0 && mx < 1e-30)) return "decoder weights out of range";
+    const int e = mx > 0 ? -((int)std::floor(std::log2(mx)) + 1) : 0;
+    const double s2 = std::ldexp(1.0, e);
+    const int kin = i == 0 ? kDecInPad : n_in[i];
+    t.w_hi[i].assign((size_t)n_out[i] * kin, 0);
+    t.w_lo[i].assign((size_t)n_out[i] * kin, 0);
+    for (int n = 0; n < n_out[i]; ++n)
+      for (int k = 0; k < n_in[i]; ++k) {
+        const size_t q = dec_frag_half(n, k, kin);
+        split_half(Wf[(size_t)n * n_in[i] + k] * s2, t.w_hi[i][q], t.w_lo[i][q]);
+      }
+    t.shift[i].assign(sh.begin(), sh.end());
+    t.inv_scale[i] = (float)std::ldexp(1.0, -e);
+  }
+  t.w6.assign((size_t)PLAN_NP * kDecHidden5, 0.f);
+  t.b6.assign(PLAN_NP, 0.f);
+  for (int a = 0; a < PLAN_NP; ++a) {
+    for (int k = 0; k < kDecHidden5; ++k) t.w6[(size_t)a * kDecHidden5 + k] = (float)dec.W[5][(size_t)a * kDecHidden5 + k];
+    t.b6[a] = (float)dec.b[5][a];
+  }
+  return nullptr;
+}
+
 }  // namespace plan

@@ -42,4 +42,24 @@ void build_proj(const BasisTable &bt, int M, double rho, bool goals, ProjTable &
 void build_mfma_basis(const BasisTable &bt, std::vector<uint16_t> &ops);
 void build_mfma_inverse(const ProjTable &pt, std::vector<uint16_t> &ops);
 
+// Device tables of the decoder sampler: each block's BatchNorm (inference
+// form) and bias folded into its Linear layer in FP64,
+//   W' = diag(gamma / sqrt(var + eps)) W,
+//   shift = gamma (b - mean) / sqrt(var + eps) + beta,
+// blocks 1-5 as FP16 high/low pairs of W' 2^e (e per layer, so that
+// max |W' 2^e| lies in [1/2, 1)) with inv_scale = 2^-e, block 1 with its 57
+// inputs padded to kDecInPad by zero columns; the output layer in FP32.
+// Returns nullptr, or why the weights are refused.
+// Weights are stored in the matrix-core operand layout of the decoder
+// kernels: half (r, k) of an R x K matrix at dec_frag_half(r, k, K), 16 x 32
+// fragments in the order one wave's loads read them.
+size_t dec_frag_half(int r, int k, int K);
+struct DecoderTables {
+  std::vector<uint16_t> w_hi[kDecLayers], w_lo[kDecLayers];  // out x in, fragment layout
+  std::vector<float> shift[kDecLayers];
+  float inv_scale[kDecLayers];
+  std::vector<float> w6, b6;                // PLAN_NP x kDecHidden5, PLAN_NP
+};
+const char *build_decoder(const plan_decoder &dec, DecoderTables &t);
+
 }  // namespace plan

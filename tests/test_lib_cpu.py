@@ -48,9 +48,11 @@ def test_struct_layout_matches_header(pl):
 #include <stddef.h>
 #include "plan.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(plan_config), sizeof(plan_request), sizeof(plan_result),
-         offsetof(plan_config, stream), offsetof(plan_request, first_iter), offsetof(plan_result, latency_s),
-         sizeof(plan_mpc_log), offsetof(plan_mpc_log, status));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(plan_config), sizeof(plan_request),
+         sizeof(plan_result), offsetof(plan_config, stream), offsetof(plan_request, first_iter),
+         offsetof(plan_result, latency_s), sizeof(plan_mpc_log), offsetof(plan_mpc_log, status),
+         offsetof(plan_request, road), offsetof(plan_request, observation), sizeof(plan_decoder),
+         offsetof(plan_decoder, bn_eps));
   return 0;
 }
 '''
@@ -64,7 +66,8 @@ int main(void) {
     b = pl.binding
     want = [C.sizeof(b.plan_config), C.sizeof(b.plan_request), C.sizeof(b.plan_result),
             b.plan_config.stream.offset, b.plan_request.first_iter.offset, b.plan_result.latency_s.offset,
-            C.sizeof(b.plan_mpc_log), b.plan_mpc_log.status.offset]
+            C.sizeof(b.plan_mpc_log), b.plan_mpc_log.status.offset, b.plan_request.road.offset,
+            b.plan_request.observation.offset, C.sizeof(b.plan_decoder), b.plan_decoder.bn_eps.offset]
     assert got == want
 
 

@@ -60,7 +60,7 @@ def set_check(name, gpu_idx, orc_idx, orc_key, tol_of_key, exempt=None):
 
 
 def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e-4, behaviour=0, sampler=0,
-               L=None, road=False):
+               L=None, road=False, decoder_seed=None, p0_tol=None):
     c = workload.CONFIGS[cfgid]
     N, T, M, K = c["N"], c["T"], c["M"], c["K"]
     L = c["L"] if L is None else L
@@ -72,13 +72,22 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
         rp, rx0, rdx = workload.curved_road(cfgid, scene_idx)
         rk = dict(road=rp, road_x0=rx0, road_dx=rdx)
     sc = orc.Scene(s.ego, s.obstacles, **rk)
-    ref = orc.plan(par, sc, s.seed, N, trace=True)
+    dec, ok_kw, p0 = None, {}, None
+    if decoder_seed is not None:
+        # the decoder sampler: the oracle plans from its own FP64 decoder samples
+        sampler = pl.PLAN_SAMPLER_DECODER
+        dec = workload.decoder_weights(decoder_seed, behaviour)
+        ok_kw = dict(observation=workload.observation(s, **rk))
+        p0 = orc.decoder_sample(par, dec, ok_kw["observation"], s.seed, N)
+    ref = orc.plan(par, sc, s.seed, N, trace=True, p0=p0)
     tr = ref.trace
     n, q = orc.elite_sizes(par, N)
     cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=1, max_N=N,
                               max_requests=1, trace=1, precision=precision, behaviour=behaviour,
                               sampler=sampler)
     h = pl.plan_create(cfg)
+    if dec is not None:
+        pl.plan_set_decoder(h, dec)
     swaps_total = 0
     rt = lambda r: r_tol(r, tol_scale)  # noqa: E731
     ct = lambda c: c_tol(c, tol_scale)  # noqa: E731
@@ -88,13 +97,17 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
         kw = {}
         if l > 0:
             kw = dict(mu0=tr["mu"][l - 1], sigma0=tr["Sigma"][l - 1])
-        req = pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, first_iter=l, **rk, **kw)
+        req = pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, first_iter=l, **rk, **ok_kw,
+                         **kw)
         res = pl.plan_solve_batch(h, [req])[0]
         assert res.status == 0, pl.plan_last_error(h)
         g = pl.plan_get_trace(h, 0, N, n, q)
         # samples
         dp = np.abs(g["p"][0] - tr["p"][l])
-        assert np.all(dp <= 2e-5 + 1e-6 * np.abs(tr["p"][l])), dp.max()
+        if l == 0 and p0_tol is not None:
+            assert np.all(dp <= p0_tol(tr["p"][l])), dp.max()
+        else:
+            assert np.all(dp <= 2e-5 + 1e-6 * np.abs(tr["p"][l])), dp.max()
         # residuals and costs
         slow = ill_conditioned(orc, par, sc, tr["xi_bar"][l], tr["xi_star"][l], p=tr["p"][l])
         ok = ~slow

@@ -178,3 +178,27 @@ def test_bad_road_profiles_rejected(pl):
                 dict(road=good, road_x0=np.inf)):
         assert pl.plan_solve_batch(h, [pl.Request(**base, **bad)])[0].status == pl.PLAN_E_INVALID, bad
     assert pl.plan_solve_batch(h, [pl.Request(**base, road=good, road_dx=30.0)])[0].status == 0
+
+
+def test_served_request_owns_its_road_profile(pl):
+    """plan_submit copies the profile: overwriting the caller's array before
+    the request is admitted changes nothing."""
+    kw = dict(T_set=[100], M_set=[10], proj_iters=8, upper_iters=2, max_N=256, max_requests=2)
+    s = workload.scene(6, 95, 10)
+    s.ego[2] = 20.0
+    rk = road_kw(6, 95)
+    alone = pl.plan_solve_batch(pl.plan_create(pl.plan_config_init(**kw)),
+                                [pl.Request(N=256, T=100, ego=s.ego, obstacles=s.obstacles, seed=s.seed, **rk)])[0]
+    h = pl.plan_create(pl.plan_config_init(**kw))
+    road = rk["road"].copy()
+    t = pl.plan_submit(h, pl.Request(N=256, T=100, ego=s.ego, obstacles=s.obstacles, seed=s.seed,
+                                     road=road, road_x0=rk["road_x0"], road_dx=rk["road_dx"]))
+    road[:] = 0.0  # y_lb = y_ub = 0: an invalid profile, if it were read now
+    got = None
+    for _ in range(10):
+        pl.plan_progress(h)
+        got = pl.plan_poll(h, t)
+        if got is not None:
+            break
+    assert got is not None and got.status == alone.status == 0
+    assert got.best_index == alone.best_index and np.array_equal(got.xi_best, alone.xi_best)
