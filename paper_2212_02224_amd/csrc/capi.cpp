@@ -326,6 +326,7 @@ struct plan_handle {
   uint16_t *dec_x[2] = {};    // input hi, lo
   uint16_t *dec_act[4] = {};  // ping-pong: hi 0, lo 0, hi 1, lo 1
   DecSeg *dec_seg = nullptr, *h_seg = nullptr;
+  int dec_nseg = 0, dec_rows = 0;  // segment table on the device
 };
 
 namespace {
@@ -702,8 +703,11 @@ plan_status launch_iteration(plan_handle *h, const LaunchSet &ls, int l_uniform)
   return st;
 }
 
+plan_status upload_dec_segments(plan_handle *h, const int *slots, int n);
+
 // Batch mode: stage requests into slots 0..k-1 with consecutive rows.
 plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int first) {
+  h->dec_nseg = h->dec_rows = 0;
   if (!h->resident.empty() || !h->queue.empty())
     return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them before batch calls");
   h->staged = 0;
@@ -736,24 +740,35 @@ plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int firs
   if (h->staged == 0) return PLAN_OK;
   make_launch_set(h, slots.data(), h->staged, h->ls);
   HIP_TRY(h, hipMemcpyAsync(h->desc, h->h_desc, sizeof(ReqDesc) * h->staged, hipMemcpyHostToDevice, h->stream));
-  return upload_launch_set(h, h->ls);
+  plan_status st = upload_launch_set(h, h->ls);
+  if (st == PLAN_OK) st = upload_dec_segments(h, slots.data(), h->staged);
+  return st;
 }
 
-// Decoder sampler: the samples of every listed slot that starts from the
-// initial sampler (no given distribution, no warm start) at this upper
-// iteration, written into the slots' sample rows before the lower level
-// reads them.
-plan_status decode_slots(plan_handle *h, const int *slots, int n) {
+// Decoder sampler, segment table: every listed slot that starts from the
+// initial sampler (no given distribution, no warm start) gets its rows; the
+// table is uploaded on the stream (the caller keeps h_seg untouched until
+// the stream has passed the copy: staging and the served tick synchronise).
+plan_status upload_dec_segments(plan_handle *h, const int *slots, int n) {
+  h->dec_nseg = h->dec_rows = 0;
   if (h->cfg.sampler != PLAN_SAMPLER_DECODER) return PLAN_OK;
-  int nseg = 0, rows = 0;
   for (int i = 0; i < n; ++i) {
     const ReqDesc &d = h->h_desc[slots[i]];
     if (d.init_mode != kInitStructured) continue;
-    h->h_seg[nseg++] = DecSeg{slots[i], rows, d.N, 0};
-    rows += d.N;
+    h->h_seg[h->dec_nseg++] = DecSeg{slots[i], h->dec_rows, d.N, 0};
+    h->dec_rows += d.N;
   }
-  if (nseg == 0) return PLAN_OK;
-  HIP_TRY(h, hipMemcpyAsync(h->dec_seg, h->h_seg, sizeof(DecSeg) * nseg, hipMemcpyHostToDevice, h->stream));
+  if (h->dec_nseg > 0)
+    HIP_TRY(h, hipMemcpyAsync(h->dec_seg, h->h_seg, sizeof(DecSeg) * h->dec_nseg, hipMemcpyHostToDevice,
+                              h->stream));
+  return PLAN_OK;
+}
+
+// Decoder sampler: the samples of the uploaded segments, written into the
+// slots' sample rows before the lower level reads them.
+plan_status launch_dec_segments(plan_handle *h) {
+  if (h->cfg.sampler != PLAN_SAMPLER_DECODER || h->dec_nseg == 0) return PLAN_OK;
+  const int nseg = h->dec_nseg, rows = h->dec_rows;
   DecArgs a{};
   a.desc = h->desc;
   a.seg = h->dec_seg;
@@ -780,10 +795,8 @@ plan_status launch_impl(plan_handle *h) {
   if (h->staged == 0) return PLAN_OK;
   plan_status st = PLAN_OK;
   for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) {
-    if (l == 0 && h->cfg.sampler == PLAN_SAMPLER_DECODER) {
-      std::vector<int> slots(h->staged);  // batch requests hold slots 0..staged-1
-      for (int i = 0; i < h->staged; ++i) slots[i] = i;
-      st = decode_slots(h, slots.data(), h->staged);
+    if (l == 0) {
+      st = launch_dec_segments(h);  // table uploaded at staging
       if (st != PLAN_OK) break;
     }
     st = launch_iteration(h, h->ls, l);
@@ -1423,7 +1436,8 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
       std::vector<int> first;
       for (int i = 0; i < n_act; ++i)
         if (h->resident[i].iters == 0) first.push_back(h->resident[i].slot);
-      st = decode_slots(h, first.data(), (int)first.size());
+      st = upload_dec_segments(h, first.data(), (int)first.size());
+      if (st == PLAN_OK) st = launch_dec_segments(h);
     }
     if (st == PLAN_OK) st = launch_iteration(h, ls, -1);
     if (st != PLAN_OK) return st;
