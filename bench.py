@@ -159,17 +159,20 @@ def _run_served(pl, h, reqs, arrivals):
 
 
 def served_bench(pl, workload, torch, n_req=256, slots=64, loads=(0.5, 0.7, 0.9)):
-    """The served stream in both precisions: the saturated rate of each (all
-    requests at t = 0), then the same Poisson arrival sequences for both at
-    the given fractions of the FP32 saturated rate; p50/p99 latency."""
+    """The served stream in both precisions, each with the host waiting for
+    every iteration (served_run_ahead 0, the default) and with one iteration
+    enqueued ahead: the saturated rate of each (all requests at t = 0), then
+    the same Poisson arrival sequences for all at the given fractions of the
+    FP32 saturated rate; p50/p99 latency."""
     import numpy as np
     L, K = 5, 20
     reqs = served_stream(pl, workload, n_req)
     solves = sum(r.N for r in reqs) * L
     handles, out = {}, {}
-    for name, prec in (("f32", 0), ("fp16_split", 1)):
+    for name, prec, ahead in (("f32", 0, 0), ("fp16_split", 1, 0), ("f32_run_ahead1", 0, 1),
+                              ("fp16_split_run_ahead1", 1, 1)):
         cfg = pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=K, upper_iters=L, max_N=2048,
-                                  max_requests=slots, precision=prec)
+                                  max_requests=slots, precision=prec, served_run_ahead=ahead)
         ws = torch.empty(pl.plan_workspace_bytes(cfg), dtype=torch.uint8, device="cuda:0")
         h = pl.plan_create(cfg, workspace=ws, stream=torch.cuda.current_stream().cuda_stream)
         run_served(pl, h, reqs[:16], np.zeros(16))  # warm-up

@@ -139,6 +139,14 @@ typedef enum plan_sampler_t {
  *                   residual, cost: 104 bytes each) shared by the resident
  *                   requests; a request takes N contiguous rows. With
  *                   max_requests this is the HBM budget of admission.
+ *   served_run_ahead  served mode, 0..3: how many upper iterations the host
+ *                   may enqueue beyond the one the GPU is running. 0 (the
+ *                   default): plan_progress prepares the next iteration
+ *                   while the GPU runs the current one and enqueues it when
+ *                   that one has finished, so a request submitted meanwhile
+ *                   joins it. Larger values keep the GPU busier (more
+ *                   throughput) but a new request waits behind the
+ *                   iterations already enqueued (more latency).
  *   proj_iters      K, iterations of Alg. 2 (its maxiter).
  *   upper_iters     L, iterations of Alg. 1 (its N).
  *   frac_ces/es     n = max(q, round(frac_ces N)), q = max(1, round(frac_es N))
@@ -181,6 +189,7 @@ typedef struct plan_config {
   int32_t trace; /* nonzero: keep per-iteration elite sets and mu, Sigma */
   int32_t behaviour; /* plan_behaviour */
   int32_t sampler;   /* plan_sampler_t: initial sampler */
+  int32_t served_run_ahead; /* served mode: iterations enqueued ahead (0..3) */
   int64_t sample_budget; /* sample rows resident at once (0: max_requests * max_N) */
   void *device_workspace;
   size_t workspace_bytes;
@@ -321,15 +330,25 @@ plan_status plan_get_trace(plan_handle *h, int32_t i, double *p, double *resid,
  * of Alg. 1. plan_submit validates and queues a request (copying everything
  * it points to) and returns a ticket. Each plan_progress call admits queued
  * requests, first come first served, while a request slot and N contiguous
- * sample rows of the budget are free; runs one upper iteration for every
- * resident request at once (whatever their sizes and iteration indices, in
- * the same kernel launches); and retires the requests that finished their L
- * iterations. plan_poll returns PLAN_E_BUSY until the ticket's request is
- * done, then its result (latency_s: submit to completion) and forgets the
+ * sample rows of the budget are free; and enqueues one upper iteration for
+ * every resident request at once (whatever their sizes and iteration
+ * indices, in the same kernel launches). The host waits for the GPU only
+ * as far as plan_config.served_run_ahead asks, so its own work overlaps the
+ * GPU's. A request whose L-th iteration is enqueued has its result copied
+ * back; it is retired (result ready, slot and rows free) by the first
+ * plan_progress or plan_poll call after the copy has arrived. A
+ * plan_progress call with nothing to enqueue waits for the oldest pending
+ * result instead, so every call makes progress. plan_poll returns
+ * PLAN_E_BUSY until the ticket's request is done, then its result
+ * (latency_s: submit to the call that saw it complete) and forgets the
  * ticket. A request's arithmetic does not depend on what else is resident,
- * so its result equals the one of plan_solve_batch bit for bit.
- * *n_active / *n_queued (nullable) receive the resident and waiting counts.
- * plan_submit fails with PLAN_E_INVALID for a bad request.
+ * so its result equals the one of plan_solve_batch bit for bit. A session's
+ * warm start is available to requests admitted after the previous request
+ * of the session was retired. *n_active / *n_queued (nullable) receive the
+ * in-flight (resident or retiring) and waiting counts. plan_submit fails
+ * with PLAN_E_INVALID for a bad request. The batch calls (plan_solve_batch,
+ * plan_stage, plan_mpc_run, plan_set_decoder) return PLAN_E_BUSY while any
+ * served request is queued or in flight.
  */
 plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticket);
 plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued);

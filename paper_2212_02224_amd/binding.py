@@ -52,7 +52,7 @@ class plan_config(C.Structure):
         ("lane_c", C.c_double * 3),
         ("lane_sigma", C.c_double), ("vd_lo", C.c_double), ("vd_hi", C.c_double),
         ("precision", C.c_int32), ("trace", C.c_int32),
-        ("behaviour", C.c_int32), ("sampler", C.c_int32),
+        ("behaviour", C.c_int32), ("sampler", C.c_int32), ("served_run_ahead", C.c_int32),
         ("sample_budget", C.c_int64),
         ("device_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("stream", C.c_void_p),

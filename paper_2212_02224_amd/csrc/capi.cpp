@@ -145,6 +145,12 @@ struct Layout {
   }
 };
 
+// Pinned host staging of the served ticks (launch-set arrays, decoder
+// segments) in a ring: a tick need not wait for the GPU, so the buffers of
+// tick t are reused only once the event recorded after tick t - kRing has
+// passed.
+constexpr int kRing = 4;
+
 int max_sessions(const plan_config &c) { return std::max(64, 2 * c.max_requests); }
 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -230,6 +236,7 @@ const char *validate_config(const plan_config &c) {
   if (c.behaviour != PLAN_BEHAV_SETPOINTS && c.behaviour != PLAN_BEHAV_GOALS) return "unknown behaviour";
   if (c.sampler != PLAN_SAMPLER_RANDOM && c.sampler != PLAN_SAMPLER_GRID && c.sampler != PLAN_SAMPLER_DECODER)
     return "unknown sampler";
+  if (c.served_run_ahead < 0 || c.served_run_ahead > kRing - 1) return "served_run_ahead must be in [0, 3]";
   if (c.behaviour == PLAN_BEHAV_GOALS && !(c.w_s > 0)) return "goal positions need w_s > 0 (the cost is c_s alone)";
   if (c.precision != PLAN_PREC_FP32 && c.precision != PLAN_PREC_FP16_SPLIT) return "unsupported precision";
   if (mfma_mode(c))
@@ -255,6 +262,16 @@ struct Resident {
   int session_wb = -1;
   Clock::time_point submit;
 };
+
+// A served request whose last iteration is on the stream; it is retired
+// (result filled, slot and rows freed) once `ev`, recorded after the copies
+// of its result, has passed.
+struct Retiring {
+  Resident rs;
+  hipEvent_t ev = nullptr;
+};
+
+
 
 }  // namespace
 
@@ -287,7 +304,13 @@ struct plan_handle {
   int max_ces = 0, max_es = 0;
   // host staging (pinned)
   ReqDesc *h_desc = nullptr;
-  int32_t *h_act = nullptr;  // act_slots then blk_prefix
+  int32_t *h_act = nullptr;  // act_slots then blk_prefix (the current ring entry)
+  int32_t *h_act_ring[kRing] = {};
+  DecSeg *h_seg_ring[kRing] = {};
+  hipEvent_t ring_ev[kRing] = {};
+  int64_t tick = 0;  // served iterations enqueued so far (tick t stages in ring entry t % kRing)
+  std::vector<Retiring> retiring;
+  std::vector<hipEvent_t> sync_ev_free;  // events without timing, for retirement
   ResultRec *h_result = nullptr;
   DistState *h_dist = nullptr;
   // batch mode: staged requests in slots 0..staged-1
@@ -330,6 +353,11 @@ struct plan_handle {
 };
 
 namespace {
+
+// Served requests queued, resident, or with their last copies on the stream.
+bool served_in_flight(const plan_handle *h) {
+  return !h->resident.empty() || !h->queue.empty() || !h->retiring.empty();
+}
 
 plan_status fail(plan_handle *h, plan_status st, const std::string &msg) {
   if (h) h->err = msg;
@@ -708,7 +736,7 @@ plan_status upload_dec_segments(plan_handle *h, const int *slots, int n);
 // Batch mode: stage requests into slots 0..k-1 with consecutive rows.
 plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int first) {
   h->dec_nseg = h->dec_rows = 0;
-  if (!h->resident.empty() || !h->queue.empty())
+  if (served_in_flight(h))
     return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them before batch calls");
   h->staged = 0;
   h->ls = LaunchSet();
@@ -876,6 +904,65 @@ void give_rows(plan_handle *h, int64_t off, int N) {
   h->free_rows[b] = e;
 }
 
+// Retire the served requests whose result copies have arrived: fill their
+// results (latency measured now), free their slots and rows.
+plan_status retire_done(plan_handle *h) {
+  for (size_t i = 0; i < h->retiring.size();) {
+    const hipError_t q = hipEventQuery(h->retiring[i].ev);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    if (q != hipSuccess) return hip_fail(h, q, "served result copy");
+    const Resident rs = h->retiring[i].rs;
+    plan_result o;
+    fill_result(o, h->h_result[rs.slot], h->h_dist[rs.slot],
+                std::chrono::duration<double>(Clock::now() - rs.submit).count());
+    if (o.status == 0 && rs.session_wb >= 0) h->sess_valid[rs.session_wb] = 1;
+    h->done[rs.ticket] = o;
+    h->slot_busy[rs.slot] = 0;
+    give_rows(h, rs.row_off, rs.N);
+    h->sync_ev_free.push_back(h->retiring[i].ev);
+    h->retiring.erase(h->retiring.begin() + i);
+  }
+  return PLAN_OK;
+}
+
+// Served admission: first come first served while a slot and N contiguous
+// rows are free; appends the admitted slots.
+void admit_queued(plan_handle *h, std::vector<int> &admitted) {
+  const int S = h->cfg.max_requests;
+  while (!h->queue.empty()) {
+    Pending &pd = h->queue.front();
+    int slot = -1;
+    for (int s = 0; s < S; ++s)
+      if (!h->slot_busy[s]) {
+        slot = s;
+        break;
+      }
+    int64_t off = 0;
+    if (slot < 0 || !take_rows(h, pd.req.N, off)) break;
+    const plan_request &r = pd.req;
+    ReqDesc &d = h->h_desc[slot];
+    d = pd.desc;
+    resolve_session(h, r.session_id, d, r.session_id != 0);
+    d.row_off = off;
+    d.cur_iter = 0;
+    h->slot_busy[slot] = 1;
+    Resident rs;
+    rs.ticket = pd.ticket;
+    rs.slot = slot;
+    rs.row_off = off;
+    rs.N = r.N;
+    rs.T = r.T;
+    rs.session_wb = d.session_wb;
+    rs.submit = pd.submit;
+    h->resident.push_back(rs);
+    admitted.push_back(slot);
+    h->queue.pop_front();
+  }
+}
+
 void free_handle(plan_handle *h) {
   if (!h) return;
   if (h->stream) hipStreamSynchronize(h->stream);
@@ -890,10 +977,15 @@ void free_handle(plan_handle *h) {
   if (h->own_mem && h->mem.base) hipFree(h->mem.base);
   if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
   if (h->h_desc) hipHostFree(h->h_desc);
-  if (h->h_act) hipHostFree(h->h_act);
+  for (int r = 0; r < kRing; ++r) {
+    if (h->h_act_ring[r]) hipHostFree(h->h_act_ring[r]);
+    if (h->h_seg_ring[r]) hipHostFree(h->h_seg_ring[r]);
+    if (h->ring_ev[r]) hipEventDestroy(h->ring_ev[r]);
+  }
+  for (auto &rt : h->retiring) hipEventDestroy(rt.ev);
+  for (hipEvent_t e : h->sync_ev_free) hipEventDestroy(e);
   if (h->h_result) hipHostFree(h->h_result);
   if (h->h_dist) hipHostFree(h->h_dist);
-  if (h->h_seg) hipHostFree(h->h_seg);
   delete h;
 }
 
@@ -1080,11 +1172,16 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     h->own_stream = e == hipSuccess;
   }
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_desc, sizeof(ReqDesc) * S);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_act, sizeof(int32_t) * (2 * S + 8));
+  for (int r = 0; e == hipSuccess && r < kRing; ++r) {
+    e = hipHostMalloc((void **)&h->h_act_ring[r], sizeof(int32_t) * (2 * S + 8));
+    if (e == hipSuccess && c.sampler == PLAN_SAMPLER_DECODER)
+      e = hipHostMalloc((void **)&h->h_seg_ring[r], sizeof(DecSeg) * S);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ring_ev[r], hipEventDisableTiming);
+  }
+  h->h_act = h->h_act_ring[0];
+  h->h_seg = h->h_seg_ring[0];
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_result, sizeof(ResultRec) * S);
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_dist, sizeof(DistState) * S);
-  if (e == hipSuccess && c.sampler == PLAN_SAMPLER_DECODER)
-    e = hipHostMalloc((void **)&h->h_seg, sizeof(DecSeg) * S);
   // ---- upload tables
   if (e == hipSuccess) {
     std::vector<float> basis_all;
@@ -1282,7 +1379,7 @@ plan_status plan_mpc_run(plan_handle *h, const plan_request *reqs, int32_t n, in
 plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const double *p, int32_t N,
                              double *xi_bar, double *xi_star, double *resid, double *cost_upper) {
   if (!h || !req || !p) return fail(h, PLAN_E_INVALID, "bad arguments");
-  if (!h->resident.empty() || !h->queue.empty())
+  if (served_in_flight(h))
     return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them before batch calls");
   plan_request r = *req;
   r.N = N;
@@ -1383,39 +1480,26 @@ plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticke
 plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) {
   if (!h) return PLAN_E_INVALID;
   h->staged = 0;  // batch slots are reused
-  const int S = h->cfg.max_requests;
-  // Admission: first come first served while a slot and the rows are free.
+  // Run-ahead limit: tick t is enqueued once tick t - 1 - run_ahead has
+  // finished (which also frees ring entry t % kRing, last used by tick
+  // t - kRing).
+  const int ra = h->cfg.served_run_ahead;
+  if (h->tick >= 1 + ra) HIP_TRY(h, hipEventSynchronize(h->ring_ev[(h->tick - 1 - ra) % kRing]));
+  // Requests whose results have arrived free their slots and rows first.
+  plan_status st = retire_done(h);
+  if (st != PLAN_OK) return st;
   std::vector<int> admitted;
-  while (!h->queue.empty()) {
-    Pending &pd = h->queue.front();
-    int slot = -1;
-    for (int s = 0; s < S; ++s)
-      if (!h->slot_busy[s]) {
-        slot = s;
-        break;
-      }
-    int64_t off = 0;
-    if (slot < 0 || !take_rows(h, pd.req.N, off)) break;
-    const plan_request &r = pd.req;
-    ReqDesc &d = h->h_desc[slot];
-    d = pd.desc;
-    resolve_session(h, r.session_id, d, r.session_id != 0);
-    d.row_off = off;
-    d.cur_iter = 0;
-    h->slot_busy[slot] = 1;
-    Resident rs;
-    rs.ticket = pd.ticket;
-    rs.slot = slot;
-    rs.row_off = off;
-    rs.N = r.N;
-    rs.T = r.T;
-    rs.session_wb = d.session_wb;
-    rs.submit = pd.submit;
-    h->resident.push_back(rs);
-    admitted.push_back(slot);
-    h->queue.pop_front();
+  admit_queued(h, admitted);
+  if (h->resident.empty() && !h->retiring.empty()) {
+    // nothing to launch: wait for the oldest result instead (the stream
+    // completes them in order), so that every call makes progress
+    HIP_TRY(h, hipEventSynchronize(h->retiring.front().ev));
+    st = retire_done(h);
+    if (st != PLAN_OK) return st;
+    admit_queued(h, admitted);
   }
   // descriptors of the admitted slots, one copy per run of consecutive slots
+  // (a slot's host descriptor is written again only after the slot retired)
   std::sort(admitted.begin(), admitted.end());
   for (size_t a = 0; a < admitted.size();) {
     size_t b = a + 1;
@@ -1426,12 +1510,16 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
   }
   const int n_act = (int)h->resident.size();
   if (n_act > 0) {
-    // One upper iteration for every resident request.
+    // One upper iteration for every resident request, staged through the
+    // next ring entry of pinned host memory.
+    const int rg = (int)(h->tick % kRing);
+    h->h_act = h->h_act_ring[rg];
+    h->h_seg = h->h_seg_ring[rg];
     std::vector<int> slots(n_act);
     for (int i = 0; i < n_act; ++i) slots[i] = h->resident[i].slot;
     LaunchSet ls;
     make_launch_set(h, slots.data(), n_act, ls);
-    plan_status st = upload_launch_set(h, ls);
+    st = upload_launch_set(h, ls);
     if (st == PLAN_OK && h->cfg.sampler == PLAN_SAMPLER_DECODER) {
       std::vector<int> first;
       for (int i = 0; i < n_act; ++i)
@@ -1441,39 +1529,40 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
     }
     if (st == PLAN_OK) st = launch_iteration(h, ls, -1);
     if (st != PLAN_OK) return st;
-    std::vector<int> finished;
-    for (int i = 0; i < n_act; ++i) {
+    HIP_TRY(h, hipEventRecord(h->ring_ev[rg], h->stream));
+    ++h->tick;
+    // Requests that ran their last iteration: copy their results back and
+    // retire them once the copies have arrived (retire_done); the host does
+    // not wait for the GPU here.
+    for (int i = n_act - 1; i >= 0; --i) {
       Resident &rs = h->resident[i];
-      if (++rs.iters == h->cfg.upper_iters) {
-        finished.push_back(i);
-        HIP_TRY(h, hipMemcpyAsync(h->h_result + rs.slot, h->result + rs.slot, sizeof(ResultRec),
-                                  hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(h, hipMemcpyAsync(h->h_dist + rs.slot, h->dist + rs.slot, sizeof(DistState),
-                                  hipMemcpyDeviceToHost, h->stream));
+      if (++rs.iters < h->cfg.upper_iters) continue;
+      HIP_TRY(h, hipMemcpyAsync(h->h_result + rs.slot, h->result + rs.slot, sizeof(ResultRec),
+                                hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(h->h_dist + rs.slot, h->dist + rs.slot, sizeof(DistState), hipMemcpyDeviceToHost,
+                                h->stream));
+      Retiring rt;
+      rt.rs = rs;
+      if (!h->sync_ev_free.empty()) {
+        rt.ev = h->sync_ev_free.back();
+        h->sync_ev_free.pop_back();
+      } else {
+        HIP_TRY(h, hipEventCreateWithFlags(&rt.ev, hipEventDisableTiming));
       }
-    }
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    const auto now = Clock::now();
-    for (int k = (int)finished.size() - 1; k >= 0; --k) {
-      const int i = finished[k];
-      const Resident rs = h->resident[i];
-      plan_result o;
-      fill_result(o, h->h_result[rs.slot], h->h_dist[rs.slot],
-                  std::chrono::duration<double>(now - rs.submit).count());
-      if (o.status == 0 && rs.session_wb >= 0) h->sess_valid[rs.session_wb] = 1;
-      h->done[rs.ticket] = o;
-      h->slot_busy[rs.slot] = 0;
-      give_rows(h, rs.row_off, rs.N);
+      HIP_TRY(h, hipEventRecord(rt.ev, h->stream));
+      h->retiring.push_back(rt);
       h->resident.erase(h->resident.begin() + i);
     }
   }
-  if (n_active) *n_active = (int32_t)h->resident.size();
+  if (n_active) *n_active = (int32_t)(h->resident.size() + h->retiring.size());
   if (n_queued) *n_queued = (int32_t)h->queue.size();
   return PLAN_OK;
 }
 
 plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out) {
   if (!h || !out) return fail(h, PLAN_E_INVALID, "bad arguments");
+  plan_status st = retire_done(h);
+  if (st != PLAN_OK) return st;
   auto it = h->done.find(ticket);
   if (it != h->done.end()) {
     *out = it->second;
@@ -1482,6 +1571,8 @@ plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out) {
   }
   for (const auto &rs : h->resident)
     if (rs.ticket == ticket) return PLAN_E_BUSY;
+  for (const auto &rt : h->retiring)
+    if (rt.rs.ticket == ticket) return PLAN_E_BUSY;
   for (const auto &pd : h->queue)
     if (pd.ticket == ticket) return PLAN_E_BUSY;
   return fail(h, PLAN_E_INVALID, "unknown ticket");
@@ -1491,11 +1582,12 @@ plan_status plan_set_decoder(plan_handle *h, const plan_decoder *dec) {
   if (!h || !dec) return fail(h, PLAN_E_INVALID, "bad arguments");
   if (h->cfg.sampler != PLAN_SAMPLER_DECODER)
     return fail(h, PLAN_E_INVALID, "the config's sampler is not PLAN_SAMPLER_DECODER");
-  if (!h->resident.empty() || !h->queue.empty())
+  if (served_in_flight(h))
     return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them first");
   DecoderTables t;
   if (const char *why = build_decoder(*dec, t)) return fail(h, PLAN_E_INVALID, why);
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->dec_ready = false;  // until every table of the new weights is on the device
   auto up = [&](void *dst, const void *src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
   };

@@ -42,15 +42,19 @@ def alone_results(pl, reqs):
 
 
 def drain(pl, h, tickets, max_ticks=200):
+    """Drive plan_progress and poll every ticket until all are done; the
+    counts are those of one more plan_progress call (results can also be
+    retired by plan_poll)."""
     got = {}
     for _ in range(max_ticks):
-        act, q = pl.plan_progress(h)
+        pl.plan_progress(h)
         for t in tickets:
             if t not in got:
                 r = pl.plan_poll(h, t)
                 if r is not None:
                     got[t] = r
         if len(got) == len(tickets):
+            act, q = pl.plan_progress(h)
             return got, act, q
     raise AssertionError("requests did not finish")
 
@@ -84,6 +88,27 @@ def test_served_staggered_arrivals_equal_alone(pl):
     assert act == 0 and q == 0
     for i, t in enumerate(tickets):
         assert same(got[t], ref[i]), i
+
+
+@pytest.mark.parametrize("ahead", [1, 3])
+def test_served_run_ahead_equals_alone(pl, ahead):
+    """With iterations enqueued ahead of the GPU (served_run_ahead), arrivals
+    during the run still give each request its result alone, bit for bit,
+    and every request retires."""
+    reqs = reqs_of(pl)
+    ref = alone_results(pl, reqs)
+    h = pl.plan_create(cfg_of(pl, served_run_ahead=ahead))
+    tickets = []
+    for i, r in enumerate(reqs):
+        tickets.append(pl.plan_submit(h, r))
+        if i % 2 == 1:
+            pl.plan_progress(h)
+    got, act, q = drain(pl, h, tickets)
+    assert act == 0 and q == 0
+    for i, t in enumerate(tickets):
+        assert same(got[t], ref[i]), i
+    # the handle is idle again: batch calls work
+    assert pl.plan_solve_batch(h, [reqs[0]])[0].status == 0
 
 
 def test_served_admission_respects_sample_budget(pl):
