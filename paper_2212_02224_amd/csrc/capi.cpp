@@ -204,7 +204,7 @@ Layout compute_layout(const plan_config &c) {
   }
   if (c.sampler == PLAN_SAMPLER_DECODER) {
     for (int i = 0; i < kDecPieces; ++i) L.dec_tab += round256(dec_piece(i));
-    L.dec_act = 2 * round256((size_t)dec_chunk(R) * kDecInPad * 2) + 4 * round256((size_t)dec_chunk(R) * kDecHidden * 2);
+    L.dec_act = 4 * round256((size_t)dec_chunk(R) * kDecHidden * 2);
     L.dec_seg = S * sizeof(DecSeg);
   }
   return L;
@@ -346,7 +346,6 @@ struct plan_handle {
   uint16_t *dec_whi[kDecLayers] = {}, *dec_wlo[kDecLayers] = {};
   float *dec_shift[kDecLayers] = {};
   float dec_inv_scale[kDecLayers] = {1, 1, 1, 1, 1};
-  uint16_t *dec_x[2] = {};    // input hi, lo
   uint16_t *dec_act[4] = {};  // ping-pong: hi 0, lo 0, hi 1, lo 1
   DecSeg *dec_seg = nullptr, *h_seg = nullptr;
   int dec_nseg = 0, dec_rows = 0;  // segment table on the device
@@ -804,8 +803,6 @@ plan_status launch_dec_segments(plan_handle *h) {
   for (int L = 0; L < kDecLayers; ++L)
     a.layer[L] = DecLayer{h->dec_whi[L], h->dec_wlo[L], h->dec_shift[L], h->dec_inv_scale[L], kDecNin[L],
                           kDecNout[L]};
-  a.x_hi = h->dec_x[0];
-  a.x_lo = h->dec_x[1];
   a.w6 = h->dec_w6;
   a.b6 = h->dec_b6;
   a.act_hi[0] = h->dec_act[0];
@@ -1142,7 +1139,6 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     h->dec_w6 = (float *)piece[3 * kDecLayers];
     h->dec_b6 = (float *)piece[3 * kDecLayers + 1];
     const int chunk = dec_chunk(R);
-    for (int i = 0; i < 2; ++i) h->dec_x[i] = (uint16_t *)h->mem.take((size_t)chunk * kDecInPad * 2);
     for (int i = 0; i < 4; ++i) h->dec_act[i] = (uint16_t *)h->mem.take((size_t)chunk * kDecHidden * 2);
     h->dec_seg = (DecSeg *)h->mem.take(L.dec_seg);
   }

@@ -6,9 +6,9 @@
 // The rows being decoded (every sample of every request that starts from
 // the decoder at this upper iteration) are processed in chunks of up to
 // kDecChunk rows, as one batch for all requests (the weights are shared):
-//   input     [o, z] (57, padded to 64) split into FP16 high/low halves
 //   blocks 1-5  64 -> 1024, 1024 -> 1024 (three times), 1024 -> 256: matrix
-//             cores. Every
+//             cores; block 1 builds its input [o, z] (57, padded to 64)
+//             while loading its operands. Every
 //             operand is an FP16 high/low pair and each product is
 //             hi*hi + hi*lo + lo*hi with FP32 accumulation
 //             (v_mfma_f32_16x16x32_f16), about 22 significant bits. The
@@ -79,30 +79,36 @@ __device__ __forceinline__ size_t frag_half(int r, int k, int K) {
 // samples (and fail the request there) instead of being cut to 0.
 __device__ __forceinline__ float relu_keep_nan(float v) { return v > 0.f ? v : (v == v ? 0.f : v); }
 
-// Input of block 1, one thread per (row, k): [o, z_j] of the row's request
-// and sample, zero-padded to kDecInPad, split into FP16 high/low halves.
-__global__ void __launch_bounds__(256) dec_input_kernel(DecArgs A) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const int rl = e / kDecInPad, k = e - rl * kDecInPad;
-  if (rl >= A.nrows) return;
-  const int r = A.r0 + rl;
-  const DecSeg sg = A.seg[find_seg(A.seg, A.nseg, r)];
-  const ReqDesc &D = A.desc[sg.slot];
-  float v = 0.f;
-  if (k < PLAN_OBS_DIM) {
-    v = (float)D.obsv[k];
-  } else if (k < kDecIn) {
+// Where block 1's input comes from: the requests' observations and the
+// latent draws of their samples (rows r0.. of the chunk).
+struct DecIn {
+  const ReqDesc *desc;
+  const DecSeg *seg;
+  int nseg, r0;
+};
+
+// Halves k0 .. k0 + 7 of block 1's input for chunk row rl: [o, z_j] of the
+// row's request and sample (z_j the Box-Muller pair of Philox block
+// (j, 0, 0, 0)), zero past the 57 inputs, split into FP16 high/low.
+__device__ __forceinline__ void input_h8(const DecIn &in, int rl, int k0, h8 &hi, h8 &lo) {
+  const int r = in.r0 + rl;
+  const DecSeg sg = in.seg[find_seg(in.seg, in.nseg, r)];
+  const ReqDesc &D = in.desc[sg.slot];
+  float z0 = 0.f, z1 = 0.f;
+  if (k0 + 8 > PLAN_OBS_DIM && k0 < kDecIn) {
     uint32_t w[4];
     rng_block(D.seed, r - sg.row_begin, 0, 0, w);
-    float n0, n1;
-    normals2(w[0], w[1], n0, n1);
-    v = k == PLAN_OBS_DIM ? n0 : n1;
+    normals2(w[0], w[1], z0, z1);
   }
-  _Float16 h, l;
-  split_act(v, h, l);
-  const size_t o = frag_half(rl, k, kDecInPad);
-  reinterpret_cast<_Float16 *>(A.x_hi)[o] = h;
-  reinterpret_cast<_Float16 *>(A.x_lo)[o] = l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int k = k0 + e;
+    const float v = k < PLAN_OBS_DIM ? (float)D.obsv[k] : (k == PLAN_OBS_DIM ? z0 : (k < kDecIn ? z1 : 0.f));
+    _Float16 h, l;
+    split_act(v, h, l);
+    hi[e] = h;
+    lo[e] = l;
+  }
 }
 
 // Blocks 1-5: out = relu(inv_scale (W x) + shift) as C^T = W X^T on the
@@ -115,10 +121,11 @@ __global__ void __launch_bounds__(256) dec_input_kernel(DecArgs A) {
 // wave 0 adds them in wave order (((w0 + w1) + w2) + w3) before the
 // epilogue (more waves per tile hide the operand loads at small row counts).
 // The summation order depends on KSPLIT only, never on the tile shape. The
-// next D K-steps' operands are loaded while a step's products run.
-template <int TN, int TM, int KSTEPS, int KSPLIT>
+// next D K-steps' operands are loaded while a step's products run. INPUT:
+// block 1, whose input operand is built from the requests while loading.
+template <int TN, int TM, int KSTEPS, int KSPLIT, bool INPUT>
 __global__ void __launch_bounds__(256) dec_gemm_kernel(DecLayer Ly, const uint16_t *in_hi, const uint16_t *in_lo,
-                                                       uint16_t *out_hi, uint16_t *out_lo, int nrows) {
+                                                       DecIn in, uint16_t *out_hi, uint16_t *out_lo, int nrows) {
   constexpr int KW = KSTEPS / KSPLIT;  // K-steps of one wave
   constexpr int D = 2;
   __shared__ f4 s_part[KSPLIT > 1 ? KSPLIT - 1 : 1][TN][TM][kWave];
@@ -140,8 +147,8 @@ __global__ void __launch_bounds__(256) dec_gemm_kernel(DecLayer Ly, const uint16
   for (int bm = 0; bm < TM; ++bm) {
     const int mb = min((m_base >> 4) + bm, mb_last);
     const size_t off = ((size_t)mb * KSTEPS + s0) * 64 + lane;
-    xh[bm] = xhi + off;
-    xl[bm] = xlo + off;
+    xh[bm] = INPUT ? nullptr : xhi + off;  // block 1 reads no input buffer
+    xl[bm] = INPUT ? nullptr : xlo + off;
   }
 #pragma unroll
   for (int bn = 0; bn < TN; ++bn) {
@@ -164,8 +171,13 @@ __global__ void __launch_bounds__(256) dec_gemm_kernel(DecLayer Ly, const uint16
     }
 #pragma unroll
     for (int bm = 0; bm < TM; ++bm) {
-      bh[d][bm] = xh[bm][o];
-      bl[d][bm] = xl[bm][o];
+      if constexpr (INPUT) {
+        // block 1 builds its input operand from the requests (KSPLIT = 1)
+        input_h8(in, min(m_base + 16 * bm + i16, nrows - 1), 32 * step + 8 * g, bh[d][bm], bl[d][bm]);
+      } else {
+        bh[d][bm] = xh[bm][o];
+        bl[d][bm] = xl[bm][o];
+      }
     }
   };
 #pragma unroll
@@ -264,13 +276,14 @@ __global__ void __launch_bounds__(256) dec_out_kernel(DecArgs A, const uint16_t 
   }
 }
 
-template <int TN, int TM, int KSTEPS, int KSPLIT>
-hipError_t gemm_launch(const DecLayer &Ly, const uint16_t *ih, const uint16_t *il, uint16_t *oh, uint16_t *ol,
-                       int nrows, hipStream_t st) {
+template <int TN, int TM, int KSTEPS, int KSPLIT, bool INPUT = false>
+hipError_t gemm_launch(const DecLayer &Ly, const uint16_t *ih, const uint16_t *il, const DecIn &in, uint16_t *oh,
+                       uint16_t *ol, int nrows, hipStream_t st) {
   constexpr int tn = (KSPLIT == 1 ? 32 : 16) * TN, tm = (KSPLIT == 1 ? 32 : 16) * TM;
   if (Ly.n_in != 32 * KSTEPS || Ly.n_out % tn != 0) return hipErrorInvalidValue;
   const dim3 grid(Ly.n_out / tn, (nrows + tm - 1) / tm);
-  hipLaunchKernelGGL((dec_gemm_kernel<TN, TM, KSTEPS, KSPLIT>), grid, dim3(256), 0, st, Ly, ih, il, oh, ol, nrows);
+  hipLaunchKernelGGL((dec_gemm_kernel<TN, TM, KSTEPS, KSPLIT, INPUT>), grid, dim3(256), 0, st, Ly, ih, il, in, oh, ol,
+                     nrows);
   return hipGetLastError();
 }
 
@@ -279,15 +292,15 @@ hipError_t gemm_launch(const DecLayer &Ly, const uint16_t *ih, const uint16_t *i
 // 32 x 64 while that gives two workgroups per CU, else 32 x 32 while it
 // fills each CU once, else 32 x 16 (measured at 1000 and 16384 rows: 15 and
 // 179 us for 1024 -> 1024, 6.3 us for 1024 -> 256 at 1000 rows).
-hipError_t gemm_layer(const DecLayer &Ly, const uint16_t *ih, const uint16_t *il, uint16_t *oh, uint16_t *ol,
-                      int nrows, int n_cu, hipStream_t st) {
-  if (Ly.n_in == kDecInPad) return gemm_launch<2, 1, kDecInPad / 32, 1>(Ly, ih, il, oh, ol, nrows, st);
+hipError_t gemm_layer(const DecLayer &Ly, const uint16_t *ih, const uint16_t *il, const DecIn &in, uint16_t *oh,
+                      uint16_t *ol, int nrows, int n_cu, hipStream_t st) {
+  if (Ly.n_in == kDecInPad) return gemm_launch<2, 1, kDecInPad / 32, 1, true>(Ly, ih, il, in, oh, ol, nrows, st);
   if (Ly.n_in != kDecHidden) return hipErrorInvalidValue;
   auto wgs = [&](int tn, int tm) { return (long)(Ly.n_out / (16 * tn)) * ((nrows + 16 * tm - 1) / (16 * tm)); };
   constexpr int KS = kDecHidden / 32;
-  if (wgs(2, 4) >= 2L * n_cu) return gemm_launch<2, 4, KS, 4>(Ly, ih, il, oh, ol, nrows, st);
-  if (wgs(2, 2) >= (long)n_cu) return gemm_launch<2, 2, KS, 4>(Ly, ih, il, oh, ol, nrows, st);
-  return gemm_launch<2, 1, KS, 4>(Ly, ih, il, oh, ol, nrows, st);
+  if (wgs(2, 4) >= 2L * n_cu) return gemm_launch<2, 4, KS, 4>(Ly, ih, il, in, oh, ol, nrows, st);
+  if (wgs(2, 2) >= (long)n_cu) return gemm_launch<2, 2, KS, 4>(Ly, ih, il, in, oh, ol, nrows, st);
+  return gemm_launch<2, 1, KS, 4>(Ly, ih, il, in, oh, ol, nrows, st);
 }
 
 }  // namespace
@@ -308,14 +321,12 @@ hipError_t launch_decoder(const DecArgs &a0, int total_rows, int n_cu, hipStream
     DecArgs a = a0;
     a.r0 = r0;
     a.nrows = total_rows - r0 < kDecChunk ? total_rows - r0 : kDecChunk;
-    hipLaunchKernelGGL(dec_input_kernel, dim3((a.nrows * kDecInPad + 255) / 256), dim3(256), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess)
-      e = gemm_layer(a.layer[0], a.x_hi, a.x_lo, a.act_hi[0], a.act_lo[0], a.nrows, n_cu, st);
+    const DecIn in{a.desc, a.seg, a.nseg, a.r0};
+    hipError_t e = gemm_layer(a.layer[0], nullptr, nullptr, in, a.act_hi[0], a.act_lo[0], a.nrows, n_cu, st);
     int cur = 0;
     for (int i = 1; e == hipSuccess && i < kDecLayers; ++i) {
-      e = gemm_layer(a.layer[i], a.act_hi[cur], a.act_lo[cur], a.act_hi[cur ^ 1], a.act_lo[cur ^ 1], a.nrows, n_cu,
-                     st);
+      e = gemm_layer(a.layer[i], a.act_hi[cur], a.act_lo[cur], in, a.act_hi[cur ^ 1], a.act_lo[cur ^ 1], a.nrows,
+                     n_cu, st);
       cur ^= 1;
     }
     if (e != hipSuccess) return e;

@@ -156,8 +156,9 @@ struct SelArgs {
 // rows of the requests being decoded, concatenated: segment s covers
 // concatenated rows [row_begin, row_begin + n) = samples 0..n-1 of slot.
 // The kernels run on a chunk of at most kDecChunk concatenated rows at a
-// time: the input [o, z] padded to kDecInPad and the hidden activations live
-// in buffers of FP16 high/low pairs (row-major).
+// time: the hidden activations live in two buffers of FP16 high/low pairs
+// (the matrix-core operand layout); block 1 builds its input [o, z], padded
+// to kDecInPad, from the requests as it loads it.
 constexpr int kDecIn = PLAN_OBS_DIM + PLAN_LATENT_DIM;  // 57
 constexpr int kDecInPad = 64;                           // K of block 1 on the matrix cores
 constexpr int kDecHidden = PLAN_DEC_HIDDEN;             // 1024
@@ -186,7 +187,6 @@ struct DecArgs {
   int32_t r0, nrows;          // chunk: concatenated rows [r0, r0 + nrows)
   DecLayer layer[kDecLayers]; // blocks 1-5 (block 1: n_in = kDecInPad)
   const float *w6, *b6;       // output layer [8][kDecHidden5], [8]
-  uint16_t *x_hi, *x_lo;      // input [kDecChunk][kDecInPad]
   uint16_t *act_hi[2], *act_lo[2];  // hidden ping-pong [kDecChunk][kDecHidden]
   float *p;                   // row pool [rows][8]
   int32_t behaviour;
