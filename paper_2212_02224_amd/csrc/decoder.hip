@@ -124,7 +124,7 @@ __device__ __forceinline__ void input_h8(const DecIn &in, int rl, int k0, h8 &hi
 // next D K-steps' operands are loaded while a step's products run. INPUT:
 // block 1, whose input operand is built from the requests while loading.
 template <int TN, int TM, int KSTEPS, int KSPLIT, bool INPUT>
-__global__ void __launch_bounds__(256) dec_gemm_kernel(DecLayer Ly, const uint16_t *in_hi, const uint16_t *in_lo,
+__global__ void __launch_bounds__(kWave *(KSPLIT > 4 ? KSPLIT : 4)) dec_gemm_kernel(DecLayer Ly, const uint16_t *in_hi, const uint16_t *in_lo,
                                                        DecIn in, uint16_t *out_hi, uint16_t *out_lo, int nrows) {
   constexpr int KW = KSTEPS / KSPLIT;  // K-steps of one wave
   constexpr int D = 2;
@@ -282,8 +282,8 @@ hipError_t gemm_launch(const DecLayer &Ly, const uint16_t *ih, const uint16_t *i
   constexpr int tn = (KSPLIT == 1 ? 32 : 16) * TN, tm = (KSPLIT == 1 ? 32 : 16) * TM;
   if (Ly.n_in != 32 * KSTEPS || Ly.n_out % tn != 0) return hipErrorInvalidValue;
   const dim3 grid(Ly.n_out / tn, (nrows + tm - 1) / tm);
-  hipLaunchKernelGGL((dec_gemm_kernel<TN, TM, KSTEPS, KSPLIT, INPUT>), grid, dim3(256), 0, st, Ly, ih, il, in, oh, ol,
-                     nrows);
+  hipLaunchKernelGGL((dec_gemm_kernel<TN, TM, KSTEPS, KSPLIT, INPUT>), grid, dim3(kWave * (KSPLIT > 4 ? KSPLIT : 4)),
+                     0, st, Ly, ih, il, in, oh, ol, nrows);
   return hipGetLastError();
 }
 

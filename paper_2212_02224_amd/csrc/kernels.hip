@@ -1707,13 +1707,14 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   }
   __syncthreads();
   // eq. cov_update around the new mean: one thread per entry, elites in
-  // order. c_ab and c_ba come out bitwise equal (products commute), so the
-  // symmetrised entry 0.5 (new_ab + new_ba) is formed by the same thread.
+  // order. Each term is w_i (d_a d_b) with the differences multiplied first,
+  // so c_ab and c_ba are bitwise equal (a product commutes), and the
+  // symmetrised 0.5 (new_ab + new_ba) is exactly symmetric.
   if (tid < 64) {
     const int a = tid >> 3, b = tid & 7;
     const double ma = s_mun[a], mb = s_mun[b];
     double c = 0.0;
-    for (int i = 0; i < q; ++i) c += s_w[i] * ((double)s_p[i][a] - ma) * ((double)s_p[i][b] - mb);
+    for (int i = 0; i < q; ++i) c += s_w[i] * (((double)s_p[i][a] - ma) * ((double)s_p[i][b] - mb));
     const double cs = P.eta * c / s_sum;
     const double nab = (1.0 - P.eta) * s_sig[a * 8 + b] + cs, nba = (1.0 - P.eta) * s_sig[b * 8 + a] + cs;
     const double sym = 0.5 * (nab + nba);

@@ -192,6 +192,7 @@ def test_full_plan_consistency_and_determinism(orc, pl):
     for l in range(L):
         assert set(ga["es"][l]) <= set(ga["ces"][l])
         assert np.all(np.linalg.eigvalsh(ga["sigma"][l]) > -1e-12)
+        assert np.array_equal(ga["sigma"][l], ga["sigma"][l].T)  # exactly symmetric as formed
         # ConstraintEliteSet holds the n lowest residuals of the GPU's own r
         kth = np.sort(ga["r"][l])[n - 1]
         assert np.all(ga["r"][l][ga["ces"][l]] <= kth)
