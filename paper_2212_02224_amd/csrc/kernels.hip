@@ -1249,10 +1249,29 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   }
 }
 
+// Value v of lane `lane` (a constant) on every lane, FP64 as two 32-bit reads.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 1 / sqrt(x) for x > 0 in FP64: the hardware estimate refined by two Newton
+// steps y <- y + (y / 2)(1 - x y^2), each at least squaring the relative
+// error, so the result is within a few units of the last place.
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 // Lower Cholesky factor of A + jitter I (8x8, FP64) by lanes 0..7 of a
 // wave, lane i owning row i: column j is finished by lane j (diagonal) and
-// lanes i > j (below it) in parallel. Every lane of the wave must call it;
-// returns false on all lanes if A + jitter I is not positive definite.
+// lanes i > j (below it) in parallel, with row j of L read from lane j. Every
+// lane of the wave must call it; returns false on all lanes if A + jitter I
+// is not positive definite.
 __device__ bool chol8_wave(const double *A, double jitter, double *Lo, int lane) {
   const int i = lane & 7;
   double row[8], Lr[8];
@@ -1264,19 +1283,15 @@ __device__ bool chol8_wave(const double *A, double jitter, double *Lo, int lane)
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    // row j of L so far, from lane j
-    double Lj[8];
-#pragma unroll
-    for (int k = 0; k < j; ++k) Lj[k] = __shfl(Lr[k], j, 64);
     double s = row[j];
 #pragma unroll
-    for (int k = 0; k < j; ++k) s -= Lr[k] * Lj[k];
+    for (int k = 0; k < j; ++k) s -= Lr[k] * readlane_d(Lr[k], j);
     // lane j: s is the pivot; lanes i > j: s is the numerator of L[i][j]
-    const double piv = __shfl(s, j, 64);
+    const double piv = readlane_d(s, j);
     ok = ok && piv > 0.0;
-    const double l = ok ? sqrt(piv) : 1.0, il = 1.0 / l;
-    if (i == j) Lr[j] = l;
-    else if (i > j) Lr[j] = s * il;
+    const double y = ok ? rsqrt_d(piv) : 1.0;
+    if (i == j) Lr[j] = piv * y;
+    else if (i > j) Lr[j] = s * y;
   }
   if (lane < 8)
 #pragma unroll
@@ -1344,10 +1359,12 @@ __device__ __forceinline__ uint32_t block_exscan1(uint32_t x, uint32_t *s_w, uin
 // s_k[0..cnt) = (key << 32) | position by counting, for each key, the keys
 // below it (its rank); thread t ranks position t. The positions of the
 // selected keys go to s_out[0..want) in increasing order and the position of
-// rank 0 to *s_first. s_k holds an even number of entries (a last ~0 pads an
-// odd cnt); cnt <= kSelBlock. Uses s_tmp[0..4) and two barriers.
-__device__ void rank_select(const unsigned long long *s_k, int cnt, int want, uint32_t *s_out, uint32_t *s_first,
-                            uint32_t *s_tmp) {
+// rank 0 to *s_first (written before the first barrier). s_k holds an even
+// number of entries (a last ~0 pads an odd cnt); cnt <= kSelBlock. Uses
+// s_tmp[0..4) and two barriers. Returns the thread's index in s_out, or -1 if
+// its key is not selected.
+__device__ int rank_select(const unsigned long long *s_k, int cnt, int want, uint32_t *s_out, uint32_t *s_first,
+                           uint32_t *s_tmp) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = (cnt + 1) >> 1;
   const ulonglong2 *s_k2 = reinterpret_cast<const ulonglong2 *>(s_k);
@@ -1368,8 +1385,10 @@ __device__ void rank_select(const unsigned long long *s_k, int cnt, int want, ui
   __syncthreads();
   uint32_t before = 0;
   for (int w = 0; w < wave; ++w) before += s_tmp[w];
-  if (sel) s_out[before + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)tid;
+  const int pos = sel ? (int)(before + __popcll(bal & ((1ull << lane) - 1ull))) : -1;
+  if (sel) s_out[pos] = (uint32_t)tid;
   __syncthreads();
+  return pos;
 }
 
 // Select the `want` smallest (key, position) pairs of s_key[0..cnt) (ties to
@@ -1378,9 +1397,11 @@ __device__ void rank_select(const unsigned long long *s_k, int cnt, int want, ui
 // the first `want` of those. Otherwise a radix select on the 32-bit keys,
 // 8 bits per pass, narrows a prefix until the keys matching it are exactly
 // the ones still wanted or all bits are fixed; one scan then ranks the
-// members equal to the prefix by position. cnt <= PLAN_MAX_N.
+// members equal to the prefix by position. cnt <= PLAN_MAX_N. If s_wmin is
+// given it holds the minima of s_key over the four waves' shares (written
+// before a barrier), and the first pass over the keys is skipped.
 __device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t *s_out, uint32_t *s_hist,
-                             uint32_t *s_tmp) {
+                             uint32_t *s_tmp, const uint32_t *s_wmin) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // Positions are split into contiguous chunks, one per thread, so the scans
   // below run in position order.
@@ -1388,13 +1409,16 @@ __device__ void block_select(const uint32_t *s_key, int cnt, int want, uint32_t 
   const int p0 = min(cnt, tid * chunk), p1 = min(cnt, p0 + chunk);
   // smallest key and its multiplicity
   uint32_t kmin = 0xFFFFFFFFu;
-  for (int i = p0; i < p1; ++i) kmin = min(kmin, s_key[i]);
+  if (s_wmin == nullptr) {
+    for (int i = p0; i < p1; ++i) kmin = min(kmin, s_key[i]);
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
-  if (lane == 0) s_tmp[wave] = kmin;
-  __syncthreads();
-  kmin = s_tmp[0];
-  for (int w = 1; w < kSelBlock / kWave; ++w) kmin = min(kmin, s_tmp[w]);
+    for (int d = 32; d >= 1; d >>= 1) kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
+    if (lane == 0) s_tmp[wave] = kmin;
+    __syncthreads();
+    s_wmin = s_tmp;
+  }
+  kmin = s_wmin[0];
+  for (int w = 1; w < kSelBlock / kWave; ++w) kmin = min(kmin, s_wmin[w]);
   uint32_t nmin = 0;
   for (int i = p0; i < p1; ++i) nmin += s_key[i] == kmin;
   uint32_t tot_min;
@@ -1563,11 +1587,12 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   __shared__ uint32_t s_es[kMaxCes];
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_tmp[32];
+  __shared__ uint32_t s_wmin[kSelBlock / kWave];
   __shared__ double s_w[kMaxEs];
-  __shared__ float s_p[kMaxEs][8];
-  __shared__ double s_mu[8], s_mun[8], s_sig[64];
+  __shared__ __align__(16) float s_p[kMaxEs][8];
+  __shared__ double s_mu[8], s_sig[64];
   __shared__ double s_part[4][64 + 8];
-  __shared__ double s_sum;
+  __shared__ double s_wsum[4];
   __shared__ uint32_t s_first;
 
   const int slot = A.slots[blockIdx.x];
@@ -1582,13 +1607,20 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   const float *p = A.p + base * 8;
   const bool last = (l == P.L - 1);
 
-  // Residual keys and costs c_u + r of all samples into LDS.
+  // Residual keys and costs c_u + r of all samples into LDS, and the
+  // smallest key of each wave's share.
+  uint32_t kmin = 0xFFFFFFFFu;
 #pragma unroll 4
   for (int i = tid; i < N; i += kSelBlock) {
     const float rr = r[i], cc = cu[i];
-    s_key[i] = order_key(rr);
+    const uint32_t k = order_key(rr);
+    s_key[i] = k;
     s_c[i] = cc + rr;
+    kmin = min(kmin, k);
   }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
+  if ((tid & 63) == 0) s_wmin[tid >> 6] = kmin;
   // Distribution before this update: the prior at iteration 0.
   if (l == 0 && decoded_start(D, P, l)) {
     sample_moments(p, N, s_mu, s_sig, s_part);
@@ -1628,24 +1660,39 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
   if (R.status != 0) return;
 
   // ConstraintEliteSet: the n smallest (r_j, j).
-  block_select(s_key, N, n, s_ces, s_hist, s_tmp);
+  block_select(s_key, N, n, s_ces, s_hist, s_tmp, s_wmin);
   // EliteSet: the q smallest (c_u + r, j) over the ConstraintEliteSet, whose
   // members are listed in increasing sample index, so the CES position
   // breaks ties as the sample index does. Up to one member per thread they
   // are ranked by counting (the member of rank 0 is the lowest cost of the
   // EliteSet, ties: lower index); larger sets go through the radix select
   // on the cost keys (s_key is free again) and a minimum over the set.
+  // The EliteSet's rows go to s_p and their weights
+  // s_j = exp(-(c_j - c_min) / gamma), FP64, to s_w, in EliteSet order.
   uint32_t jbest;
   if (n <= kSelBlock) {
-    for (int i = tid; i < n; i += kSelBlock) {
-      const uint32_t j = s_ces[i];
-      s_key2[i] = ((unsigned long long)order_key(s_c[j]) << 32) | (unsigned long long)i;
-      if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)j;
+    // Thread t owns CES member t: its row is loaded while the ranks are
+    // counted, and written where the member lands in the EliteSet.
+    float4 row0 = make_float4(0.f, 0.f, 0.f, 0.f), row1 = row0;
+    uint32_t jown = 0;
+    if (tid < n) {
+      jown = s_ces[tid];
+      s_key2[tid] = ((unsigned long long)order_key(s_c[jown]) << 32) | (unsigned long long)tid;
+      if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + tid] = (int32_t)jown;
+      const float4 *pr = reinterpret_cast<const float4 *>(p + (size_t)jown * 8);
+      row0 = pr[0];
+      row1 = pr[1];
     }
     if (tid == 0 && (n & 1)) s_key2[n] = ~0ull;
     __syncthreads();
-    rank_select(s_key2, n, q, s_es, &s_first, s_tmp);
+    const int pos = rank_select(s_key2, n, q, s_es, &s_first, s_tmp);
     jbest = s_ces[s_first];
+    if (pos >= 0) {
+      reinterpret_cast<float4 *>(s_p[pos])[0] = row0;
+      reinterpret_cast<float4 *>(s_p[pos])[1] = row1;
+      s_w[pos] = exp(-((double)s_c[jown] - (double)s_c[jbest]) / P.gamma);
+      if (A.tr_es) A.tr_es[((size_t)slot * P.L + l) * A.max_es + pos] = (int32_t)jown;
+    }
   } else {
     for (int i = tid; i < n; i += kSelBlock) {
       const uint32_t j = s_ces[i];
@@ -1653,7 +1700,7 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       if (A.tr_ces) A.tr_ces[((size_t)slot * P.L + l) * A.max_ces + i] = (int32_t)j;
     }
     __syncthreads();
-    block_select(s_key, n, q, s_es, s_hist, s_tmp);
+    block_select(s_key, n, q, s_es, s_hist, s_tmp, nullptr);
     unsigned long long best = ~0ull;
     for (int i = tid; i < q; i += kSelBlock) {
       const uint32_t pos = s_es[i];
@@ -1668,67 +1715,72 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
     __syncthreads();
     for (int w = 0; w < kSelBlock / kWave; ++w) best = min(best, s_bestw[w]);
     jbest = s_ces[(uint32_t)(best & 0xFFFFFFFFull)];
-  }
-
-  // Elite rows (issued first: the loads overlap the weights) and the weights
-  // s_j = exp(-(c_j - c_min) / gamma), in FP64.
-  for (int e = tid; e < q * 8; e += kSelBlock) {
-    const int i = e >> 3, a = e & 7;
-    s_p[i][a] = p[(size_t)s_ces[s_es[i]] * 8 + a];
-  }
-  const double cmin = (double)s_c[jbest];
-  for (int i = tid; i < q; i += kSelBlock) {
-    const uint32_t j = s_ces[s_es[i]];
-    s_w[i] = exp(-((double)s_c[j] - cmin) / P.gamma);
-    if (A.tr_es) A.tr_es[((size_t)slot * P.L + l) * A.max_es + i] = (int32_t)j;
+    // all loads first, then the LDS writes (q <= kMaxEs)
+    constexpr int kRowIt = kMaxEs * 8 / kSelBlock;
+    float pv[kRowIt];
+#pragma unroll
+    for (int u = 0; u < kRowIt; ++u) {
+      const int e = tid + u * kSelBlock;
+      pv[u] = e < q * 8 ? p[(size_t)s_ces[s_es[e >> 3]] * 8 + (e & 7)] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowIt; ++u) {
+      const int e = tid + u * kSelBlock;
+      if (e < q * 8) s_p[e >> 3][e & 7] = pv[u];
+    }
+    const double cmin = (double)s_c[jbest];
+    for (int i = tid; i < q; i += kSelBlock) {
+      const uint32_t j = s_ces[s_es[i]];
+      s_w[i] = exp(-((double)s_c[j] - cmin) / P.gamma);
+      if (A.tr_es) A.tr_es[((size_t)slot * P.L + l) * A.max_es + i] = (int32_t)j;
+    }
   }
   __syncthreads();
-  // eq. mean_update: 32 threads, 4 partial sums per component in a fixed
-  // order, then combined.
-  if (tid < 32) {
-    const int a = tid & 7, part = tid >> 3;
-    double m = 0.0, ssum = 0.0;
+  // eq. mean_update and eq. cov_update in one pass over the EliteSet,
+  // about the current mean mu: with d_i = p_i - mu, S = sum s_i,
+  // u = sum s_i d_i / S and C = sum s_i d_i d_i^T, the new mean is
+  // mu + eta u and the weighted scatter about it is C + S (eta^2 - 2 eta) u u^T.
+  // Wave w sums elites w, w + 4, ...; lane e the entry (e / 8, e % 8), each
+  // term s_i (d_a d_b) with the differences multiplied first, so C_ab and C_ba
+  // are bitwise equal. The four partial sums are added in wave order.
+  {
+    const int e = tid & 63, part = tid >> 6, a = e >> 3, b = e & 7;
+    const double mua = s_mu[a], mub = s_mu[b];
+    double c = 0.0, sa = 0.0, ss = 0.0;
+#pragma unroll 4
     for (int i = part; i < q; i += 4) {
-      m += s_w[i] * (double)s_p[i][a];
-      ssum += s_w[i];
+      const double w = s_w[i];
+      const double da = (double)s_p[i][a] - mua, db = (double)s_p[i][b] - mub;
+      c += w * (da * db);
+      sa += w * da;
+      ss += w;
     }
-    s_part[part][a] = m;
-    s_part[part][64 + a] = ssum;
+    s_part[part][e] = c;
+    if (b == 0) s_part[part][64 + a] = sa;
+    if (e == 0) s_wsum[part] = ss;
   }
   __syncthreads();
-  if (tid < 8) {
-    double m = 0.0, ssum = 0.0;
-    for (int part = 0; part < 4; ++part) {
-      m += s_part[part][tid];
-      ssum += s_part[part][64 + tid];
-    }
-    s_mun[tid] = (1.0 - P.eta) * s_mu[tid] + P.eta * m / ssum;
-    if (tid == 0) s_sum = ssum;
-  }
-  __syncthreads();
-  // eq. cov_update around the new mean: one thread per entry, elites in
-  // order. Each term is w_i (d_a d_b) with the differences multiplied first,
-  // so c_ab and c_ba are bitwise equal (a product commutes), and the
-  // symmetrised 0.5 (new_ab + new_ba) is exactly symmetric.
   if (tid < 64) {
     const int a = tid >> 3, b = tid & 7;
-    const double ma = s_mun[a], mb = s_mun[b];
-    double c = 0.0;
-    for (int i = 0; i < q; ++i) c += s_w[i] * (((double)s_p[i][a] - ma) * ((double)s_p[i][b] - mb));
-    const double cs = P.eta * c / s_sum;
+    const double S = ((s_wsum[0] + s_wsum[1]) + s_wsum[2]) + s_wsum[3];
+    const double C = ((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid];
+    const double ua = (((s_part[0][64 + a] + s_part[1][64 + a]) + s_part[2][64 + a]) + s_part[3][64 + a]) / S;
+    const double ub = (((s_part[0][64 + b] + s_part[1][64 + b]) + s_part[2][64 + b]) + s_part[3][64 + b]) / S;
+    const double cs = P.eta * (C / S + P.eta * (P.eta - 2.0) * (ua * ub));
     const double nab = (1.0 - P.eta) * s_sig[a * 8 + b] + cs, nba = (1.0 - P.eta) * s_sig[b * 8 + a] + cs;
     const double sym = 0.5 * (nab + nba);
-    s_part[0][tid] = sym;
+    s_part[0][tid] = sym;  // each thread reads only its own entry of row 0 above
     Sd.sigma[tid] = sym;
     if (A.tr_sigma) A.tr_sigma[((size_t)slot * P.L + l) * 64 + tid] = sym;
+    const double mun = s_mu[b] + P.eta * ub;  // component b (threads 0..7: a = 0)
     if (tid < 8) {
-      Sd.mu[tid] = s_mun[tid];
-      if (A.tr_mu) A.tr_mu[((size_t)slot * P.L + l) * 8 + tid] = s_mun[tid];
+      Sd.mu[tid] = mun;
+      if (A.tr_mu) A.tr_mu[((size_t)slot * P.L + l) * 8 + tid] = mun;
     }
     if (D.session_wb >= 0 && last) {
       double *st = A.sess + (size_t)D.session_wb * 72;
       st[8 + tid] = sym;
-      if (tid < 8) st[tid] = s_mun[tid];
+      if (tid < 8) st[tid] = mun;
     }
   }
   __syncthreads();
@@ -1740,18 +1792,20 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       if (A.l_uniform < 0) D.cur_iter = l + 1;
     }
   }
-  if (last && tid < 64) {
-    // Return: lowest c_u + r in the final EliteSet (ties: lower index).
+  if (last && tid >= 64 && tid < 128) {
+    // Return: lowest c_u + r in the final EliteSet (ties: lower index),
+    // written by wave 1 while wave 0 factors the covariance.
+    const int t = tid - 64;
     const uint32_t b = jbest;
     const double n10 = 10.0, tf = P.t_f;
     const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
     const double ax0 = D.ego[4], ay0 = D.ego[5];
     const float *zb = A.zs + (base + b) * kZ;
-    if (tid < 8) R.p[tid] = (double)p[(size_t)b * 8 + tid];
-    if (tid < 8) R.xi[3 + tid] = (double)zb[tid] + x0 + vx0 * tf * (double)(3 + tid) / n10;
-    if (tid >= 8 && tid < 14) R.xi[14 + (tid - 8)] = (double)zb[tid];
-    if (tid == 14) R.xi[20] = R.xi[21] = (double)zb[14];
-    if (tid == 15) {
+    if (t < 8) R.p[t] = (double)p[(size_t)b * 8 + t];
+    if (t < 8) R.xi[3 + t] = (double)zb[t] + x0 + vx0 * tf * (double)(3 + t) / n10;
+    if (t >= 8 && t < 14) R.xi[14 + (t - 8)] = (double)zb[t];
+    if (t == 14) R.xi[20] = R.xi[21] = (double)zb[14];
+    if (t == 15) {
       R.xi[0] = x0;
       R.xi[1] = x0 + vx0 * tf / n10;
       R.xi[2] = x0 + 2.0 * vx0 * tf / n10 + ax0 * tf * tf / (n10 * (n10 - 1.0));
@@ -1759,7 +1813,7 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       R.xi[12] = y0 + vy0 * tf / n10;
       R.xi[13] = y0 + 2.0 * vy0 * tf / n10 + ay0 * tf * tf / (n10 * (n10 - 1.0));
     }
-    if (tid == 16) {
+    if (t == 16) {
       R.best = (int32_t)b;
       R.cost_upper = (double)cu[b];
       R.residual = (double)r[b];
