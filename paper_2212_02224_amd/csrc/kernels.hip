@@ -635,10 +635,28 @@ __device__ __forceinline__ State6 fixed_part(const float *Bt, int Tp, int tt, co
 // z_bar = S p' + R b', b' = (ax0, y0, vy0, ay0), p' = [y_d, v_d - vx0]
 // (set-points) or [x_f - x0 - vx0 t_f, y_f, 0 ...] (goal positions: c10 of x
 // in the frame relative to x0 + vx0 t, and c9 = c10 of y).
-__device__ __forceinline__ float step1_coef(const float *S1, const ReqDesc &D, const MethodParams &P,
-                                            const float (&pin)[8], int v) {
+// Inputs of step1_coef that do not depend on the sample: row v of the two
+// step-1 tables and the ego terms (loaded before the sample is drawn).
+struct Step1In {
+  float s1[8], r1[4], bb[4];
+  double vx0;
+};
+__device__ __forceinline__ Step1In step1_inputs(const float *S1, const ReqDesc &D, int v) {
+  Step1In t;
   const float *R1 = S1 + 16 * 8;
-  const double vx0 = D.ego[2];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) t.s1[m] = S1[v * 8 + m];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) t.r1[m] = R1[v * 4 + m];
+  t.bb[0] = (float)D.ego[4];
+  t.bb[1] = (float)D.ego[1];
+  t.bb[2] = (float)D.ego[3];
+  t.bb[3] = (float)D.ego[5];
+  t.vx0 = D.ego[2];
+  return t;
+}
+__device__ __forceinline__ float step1_coef(const Step1In &t, const MethodParams &P, const float (&pin)[8]) {
+  const double vx0 = t.vx0;
   float pp[8];
   if (P.behaviour == PLAN_BEHAV_GOALS) {
 #pragma unroll
@@ -652,12 +670,11 @@ __device__ __forceinline__ float step1_coef(const float *S1, const ReqDesc &D, c
       pp[4 + m] = (float)((double)pin[4 + m] - vx0);
     }
   }
-  const float bb[4] = {(float)D.ego[4], (float)D.ego[1], (float)D.ego[3], (float)D.ego[5]};
   float zb = 0.f;
 #pragma unroll
-  for (int m = 0; m < 8; ++m) zb = fmaf(S1[v * 8 + m], pp[m], zb);
+  for (int m = 0; m < 8; ++m) zb = fmaf(t.s1[m], pp[m], zb);
 #pragma unroll
-  for (int m = 0; m < 4; ++m) zb = fmaf(R1[v * 4 + m], bb[m], zb);
+  for (int m = 0; m < 4; ++m) zb = fmaf(t.r1[m], t.bb[m], zb);
   return zb;
 }
 
@@ -764,6 +781,8 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     for (int c = 0; c < 16; ++c) arow[c] = Pj[v * 16 + c];
     Dv = Pj[256 + v];
   }
+  const uint64_t seed = D.seed;
+  const int draw_iter = D.first_iter + l;
   __syncthreads();  // neighbour table and distribution ready
 
   // Sample p_j (Alg. 1: draw from N(mu, Sigma); iteration 0 may use the
@@ -773,15 +792,16 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 #pragma unroll
     for (int m = 0; m < 8; ++m) pin[m] = active ? A.p[(slot_off + j) * 8 + m] : 0.f;
   } else {
-    wave_draw(P, D.seed, j, N, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
-    if (active && wi == 0 && lane == 0) {
-      float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
-      dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
-      dst[1] = make_float4(pin[4], pin[5], pin[6], pin[7]);
-    }
+    wave_draw(P, seed, j, N, draw_iter, structured, s_mu, s_chol, lane, pin);
   }
-
-  const float zb = step1_coef(A.step1 + (size_t)D.t_idx * kStep1Floats, D, P, pin, v);
+  // the step-1 rows are read before the sample is stored, so that store
+  // cannot hold their loads back
+  const float zb = step1_coef(step1_inputs(A.step1 + (size_t)D.t_idx * kStep1Floats, D, v), P, pin);
+  if (!forced && active && wi == 0 && lane == 0) {
+    float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
+    dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
+    dst[1] = make_float4(pin[4], pin[5], pin[6], pin[7]);
+  }
   float z = zb, mu = 0.f;
   float zs[15];
 #pragma unroll
@@ -1070,6 +1090,8 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
 #pragma unroll
     for (int u = 0; u < 4; ++u) Dv[u] = Pj[256 + 4 * g + u];
   }
+  const uint64_t seed = D.seed;
+  const int draw_iter = D.first_iter + l;
   __syncthreads();  // basis table, neighbours, fixed part and distribution ready
 
   float pin[8];
@@ -1077,18 +1099,20 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
 #pragma unroll
     for (int m = 0; m < 8; ++m) pin[m] = active ? A.p[(slot_off + j) * 8 + m] : 0.f;
   } else {
-    group_draw(P, D.seed, j, N, D.first_iter + l, structured, s_mu, s_chol, lane, pin);
-    if (active && wave == 0 && g == 0) {
-      float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
-      dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
-      dst[1] = make_float4(pin[4], pin[5], pin[6], pin[7]);
-    }
+    group_draw(P, seed, j, N, draw_iter, structured, s_mu, s_chol, lane, pin);
   }
+  // the step-1 rows are read before the sample is stored, so that store
+  // cannot hold their loads back
   f4 zb;
   {
     const float *S1 = A.step1 + (size_t)D.t_idx * kStep1Floats;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) zb[u] = step1_coef(S1, D, P, pin, 4 * g + u);
+    for (int u = 0; u < 4; ++u) zb[u] = step1_coef(step1_inputs(S1, D, 4 * g + u), P, pin);
+  }
+  if (!forced && active && wave == 0 && g == 0) {
+    float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
+    dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
+    dst[1] = make_float4(pin[4], pin[5], pin[6], pin[7]);
   }
   f4 z = zb, mu = {0.f, 0.f, 0.f, 0.f};
 

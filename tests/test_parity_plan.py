@@ -169,6 +169,15 @@ def test_plan_parity_per_iteration(orc, pl, cfgid, scene_idx):
     run_config(orc, pl, cfgid, scene_idx)
 
 
+def test_plan_parity_large_elite_sets(orc, pl):
+    """One request of the 1024-request workload's size, N = 4096, T = 100,
+    M = 20, two iterations: ConstraintEliteSet of 614 and EliteSet of 205
+    members, more than one per thread of the selection workgroup, so the
+    EliteSet takes the radix select, its rows the batched loads, and the
+    update sums about 51 elites per wave."""
+    run_config(orc, pl, 5, 0, L=2)
+
+
 def test_full_plan_consistency_and_determinism(orc, pl):
     """Full L-iteration plan on the GPU: the first iteration equals the
     teacher-forced one bit for bit, the trace is self-consistent, and two runs
