@@ -289,6 +289,7 @@ struct plan_handle {
   // tables
   float *basis = nullptr, *step1 = nullptr, *proj = nullptr;
   int32_t *basis_off = nullptr, *basis_tpad = nullptr, *mops_off = nullptr;
+  std::vector<int32_t> table_offs;  // host copy of basis_off / basis_tpad / mops_off
   uint16_t *mops = nullptr, *mainv = nullptr;
   // slots and the row pool
   ReqDesc *desc = nullptr;
@@ -449,6 +450,9 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   elite_sizes(c, r.N, d.n_ces, d.n_es);
   d.t_idx = ti;
   d.tm_idx = ti * c.n_M + mi;
+  d.basis_off = h->table_offs[ti];
+  d.basis_tpad = h->table_offs[c.n_T + ti];
+  d.mops_off = h->table_offs[2 * c.n_T + ti];
   d.session = -1;
   d.session_wb = -1;
   d.first_iter = r.first_iter;
@@ -1204,6 +1208,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     e = hipMemcpyAsync(h->basis, basis_all.data(), basis_all.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(h->basis_off, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, h->stream);
+    h->table_offs = offs;
     if (e == hipSuccess)
       e = hipMemcpyAsync(h->step1, s1all.data(), s1all.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)

@@ -750,8 +750,8 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   const Scal S = make_scal(D, P);
 
   // Basis rows of this lane's instants and the fixed part of the trajectory.
-  const float *Bt = A.basis + A.basis_off[D.t_idx];
-  const int Tp = A.basis_tpad[D.t_idx];
+  const float *Bt = A.basis + D.basis_off;
+  const int Tp = D.basis_tpad;
   Lane L[IPL];
 #pragma unroll
   for (int u = 0; u < IPL; ++u) {
@@ -1032,7 +1032,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   float4 *s_G = s_part + NPr * kWave;
 
   {
-    const float4 *src = reinterpret_cast<const float4 *>(A.mops + A.mops_off[D.t_idx]);
+    const float4 *src = reinterpret_cast<const float4 *>(A.mops + D.mops_off);
     for (int i = threadIdx.x; i < tab_f4; i += blockDim.x) s_dyn[i] = src[i];
   }
   stage_neighbours(D, P, s_obs);
@@ -1044,8 +1044,8 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   {
     // fixed part per instant: (x, xd + vx0, xdd, 0), (y, yd, ydd, 0); zero
     // beyond the horizon
-    const float *Bt = A.basis + A.basis_off[D.t_idx];
-    const int Tp = A.basis_tpad[D.t_idx];
+    const float *Bt = A.basis + D.basis_off;
+    const int Tp = D.basis_tpad;
     for (int t = threadIdx.x; t < 4 * NT; t += blockDim.x) {
       float4 fx = make_float4(0.f, 0.f, 0.f, 0.f), fy = fx;
       if (t < T) {

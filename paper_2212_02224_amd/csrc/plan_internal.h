@@ -55,6 +55,9 @@ struct ReqDesc {
   int32_t T, M, N, n_ces, n_es;
   int32_t t_idx;     // index into the per-T tables
   int32_t tm_idx;    // index into the per-(T, M) tables
+  int32_t basis_off;  // float offset of the basis table of t_idx (copied at staging,
+  int32_t basis_tpad; //   so the kernels reach the table without another load)
+  int32_t mops_off;   // FP16 offset of the matrix-core table of t_idx, or 0
   int32_t init_mode; // InitMode
   int32_t session;    // session store index read at iteration 0, or -1
   int32_t session_wb; // session store index written after the last update, or -1
