@@ -6,7 +6,7 @@
 //                         affine map (Sec. III-C, eq. over_3), K iterations of
 //                         Alg. 2, then r_j and c_u,j.
 //   select_update_kernel  ConstraintEliteSet / EliteSet (Alg. 1) by radix
-//                         selection, the update of eqs. mean_update,
+//                         selection or rank counting, the update of eqs. mean_update,
 //                         cov_update, s_formula (FP64) and the Cholesky factor
 //                         used by the next draw.
 //
@@ -27,8 +27,8 @@
 // The x axis is carried relative to the line x0 + vx0 t (exact in the basis),
 // which keeps FP32 magnitudes small; obstacle positions are shifted alike.
 //
-// Layout: a workgroup of 4 waves serves one request; each sample takes
-// ceil(T/64) waves, one horizon instant per lane. The neighbours' positions
+// Layout: a workgroup of 4 waves serves samples of one request; each sample
+// takes ceil(T/(64 IPL)) waves, IPL horizon instants per lane. The neighbours' positions
 // at every instant are staged in LDS once per workgroup. The 15 sums over
 // time of N^T g are formed by a transpose-reduction across the wave (17
 // shuffles), the small A^-1 product by broadcasting through scalar
@@ -1324,7 +1324,7 @@ __device__ bool chol8_wave(const double *A, double jitter, double *Lo, int lane)
 }
 
 // ---------------------------------------------------------------------------
-// Selection and update: one 1024-thread workgroup per request.
+// Selection and update: one 4-wave workgroup per request.
 
 __device__ __forceinline__ uint32_t order_key(float f) {
   uint32_t b = __float_as_uint(f);
