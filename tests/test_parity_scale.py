@@ -1,0 +1,95 @@
+"""GPU parity at the full size of the 1024-request workload: 1024 concurrent
+requests of N = 4096, T = 100, M = 20, K = 20, all resident, in the launch
+shapes the scale measurement times (one lower launch over all 4.19M samples:
+two instants per lane in FP32, four tiles per wave in FP16 split).
+
+The oracle cannot follow 4.19M projections, so outputs are sampled and
+computed one by one (Alg. 1, first upper iteration, structured sampler):
+  * every sample p of a dozen requests against the oracle's own draw;
+  * r and c_u of 24 random samples and of the returned best sample of each
+    of those requests, against the oracle's projection of its own samples
+    (bars of the plan parity: r within 1e-3 + 1e-4 r, c_u within 1e-4
+    relative, ten times wider in FP16 split; ill-conditioned samples are
+    counted, not held to the bar);
+  * each checked request's returned trajectory against the oracle's
+    projection of the same sample: 1e-4 m FP32, 1e-3 m FP16 split;
+  * request 0 of the full batch against the same request solved alone in a
+    launch of its own (other launch shape): bit for bit.
+Inputs flow only from the oracle side to the comparison, never back."""
+import numpy as np
+import pytest
+
+from paper_2212_02224_amd import workload
+from parity_common import ill_conditioned
+from test_parity_lower import pos_err
+
+pytestmark = pytest.mark.gpu
+
+N_REQ, N, T, M, K = 1024, 4096, 100, 20, 20
+
+
+@pytest.fixture(scope="module")
+def pl():
+    import paper_2212_02224_amd as pl
+    pl.load()
+    return pl
+
+
+def request(pl, i):
+    s = workload.scene(5, i, M)
+    return s, pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_scale_sampled_parity(orc, pl, precision):
+    tol_scale = 1.0 if precision == 0 else 10.0
+    pos_tol = 1e-4 if precision == 0 else 1e-3
+    cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=1, max_N=N, max_requests=N_REQ,
+                              trace=1, precision=precision)
+    h = pl.plan_create(cfg)
+    reqs = [request(pl, i)[1] for i in range(N_REQ)]
+    print(f"[scale parity] precision {precision}: {N_REQ} requests x N={N}, T={T}, M={M}, K={K}", flush=True)
+    res = pl.plan_solve_batch(h, reqs)
+    assert all(r.status == 0 for r in res), [i for i, r in enumerate(res) if r.status != 0][:5]
+    n, q = pl.elite_sizes(h.cfg, N)
+
+    orc.set_threads(8)
+    par = orc.default_params(T=T, M=M, K=K, L=1)
+    rng = np.random.default_rng(11)
+    checked = sorted({0, N_REQ - 1} | set(int(i) for i in rng.choice(N_REQ, 10, replace=False)))
+    slow_total, count = 0, 0
+    for i in checked:
+        s, _ = request(pl, i)
+        sc = orc.Scene(s.ego, s.obstacles)
+        g = pl.plan_get_trace(h, i, N, n, q)
+        p_o = orc.sample(par, s.seed, 0, N, True)
+        dp = np.abs(g["p"][0] - p_o)
+        assert np.all(dp <= 2e-5 + 1e-6 * np.abs(p_o)), (i, dp.max())
+        best = res[i].best_index
+        idx = np.array(sorted(set(int(j) for j in rng.choice(N, 24, replace=False)) | {best}))
+        xb = orc.step1(par, sc, p_o[idx])
+        xs = orc.project(par, sc, xb)
+        r_o, c_o = orc.residual_cost(par, sc, xs)
+        ok = ~ill_conditioned(orc, par, sc, xb, xs, p=p_o[idx])
+        dr = np.abs(g["r"][0][idx] - r_o)
+        dc = np.abs(g["cu"][0][idx] - c_o)
+        assert np.all(dr[ok] <= tol_scale * (1e-3 + 1e-4 * np.abs(r_o[ok]))), (i, dr[ok].max())
+        assert np.all(dc[ok] <= tol_scale * (1e-4 * np.abs(c_o[ok]) + 1e-6)), (i, dc[ok].max())
+        k = int(np.searchsorted(idx, best))
+        e = pos_err(orc, T, par.t_f, res[i].xi_best[None, :], xs[k:k + 1])[0]
+        if ok[k]:
+            assert e <= pos_tol, (i, best, e)
+        slow_total += int((~ok).sum())
+        count += len(idx)
+        print(f"   request {i}: |dp| {dp.max():.1e} |dr| {dr[ok].max():.1e} |dc|/c "
+              f"{np.max(dc[ok] / np.abs(c_o[ok])):.1e}; best {best} position error {e:.1e} m", flush=True)
+    assert slow_total <= count // 10
+    print(f"   {slow_total} ill-conditioned of {count} sampled outputs", flush=True)
+
+    # request 0 alone, in a launch of its own shape, gives the same result bit for bit
+    cfg1 = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=1, max_N=N, max_requests=1,
+                               precision=precision)
+    alone = pl.plan_solve_batch(pl.plan_create(cfg1), [reqs[0]])[0]
+    assert alone.status == 0
+    assert alone.best_index == res[0].best_index and np.array_equal(alone.xi_best, res[0].xi_best)
+    assert np.array_equal(alone.mu, res[0].mu) and np.array_equal(alone.sigma, res[0].sigma)
