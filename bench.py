@@ -107,13 +107,8 @@ def cpu_baseline(scene, c, threads: int):
 def served_stream(pl, workload, n_req: int, seed: int = 4):
     """The served workload: n_req requests with N in {256, 512, 1000, 2048},
     M in {4, 10, 20}, T in {50, 100} (seeded), on synthetic scenes."""
-    import numpy as np
-    rng = np.random.default_rng(seed)
     reqs = []
-    for i in range(n_req):
-        N = int(rng.choice([256, 512, 1000, 2048]))
-        M = int(rng.choice([4, 10, 20]))
-        T = int(rng.choice([50, 100]))
+    for i, (N, M, T) in enumerate(workload.served_mix(n_req, seed)):
         s = workload.scene(4, i, M)
         reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
     return reqs

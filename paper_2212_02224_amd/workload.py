@@ -79,6 +79,20 @@ def scene(config: int, index: int, M: int) -> Scene:
     return Scene(ego, obs, s ^ 0x9E3779B9)
 
 
+def served_mix(n_req: int, seed: int = 4) -> list[tuple[int, int, int]]:
+    """(N, M, T) of the served workload's requests: N in {256, 512, 1000,
+    2048}, M in {4, 10, 20}, T in {50, 100}, drawn per request in that
+    order from one seeded generator. Request i uses scene(4, i, M)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_req):
+        N = int(rng.choice([256, 512, 1000, 2048]))
+        M = int(rng.choice([4, 10, 20]))
+        T = int(rng.choice([50, 100]))
+        out.append((N, M, T))
+    return out
+
+
 def curved_road(config: int, index: int):
     """(road (n x 3: kappa, y_lb, y_ub), road_x0, road_dx) for scene
     (config, index); an independent stream of the scene's seed."""

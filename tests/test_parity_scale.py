@@ -1,7 +1,9 @@
-"""GPU parity at the full size of the 1024-request workload: 1024 concurrent
-requests of N = 4096, T = 100, M = 20, K = 20, all resident, in the launch
-shapes the scale measurement times (one lower launch over all 4.19M samples:
-two instants per lane in FP32, four tiles per wave in FP16 split).
+"""GPU parity at the full sizes of the two served workloads.
+
+The 1024-request workload: 1024 concurrent requests of N = 4096, T = 100,
+M = 20, K = 20, all resident, in the launch shapes the scale measurement
+times (one lower launch over all 4.19M samples: two instants per lane in
+FP32, four tiles per wave in FP16 split).
 
 The oracle cannot follow 4.19M projections, so outputs are sampled and
 computed one by one (Alg. 1, first upper iteration, structured sampler):
@@ -15,6 +17,10 @@ computed one by one (Alg. 1, first upper iteration, structured sampler):
     projection of the same sample: 1e-4 m FP32, 1e-3 m FP16 split;
   * request 0 of the full batch against the same request solved alone in a
     launch of its own (other launch shape): bit for bit.
+
+The served stream (256 mixed requests through 64 slots):
+test_served_stream_full_size.
+
 Inputs flow only from the oracle side to the comparison, never back."""
 import numpy as np
 import pytest
@@ -93,3 +99,82 @@ def test_full_scale_sampled_parity(orc, pl, precision):
     assert alone.status == 0
     assert alone.best_index == res[0].best_index and np.array_equal(alone.xi_best, res[0].xi_best)
     assert np.array_equal(alone.mu, res[0].mu) and np.array_equal(alone.sigma, res[0].sigma)
+
+
+def drain(pl, h, tickets, max_ticks=400):
+    got = {}
+    for _ in range(max_ticks):
+        pl.plan_progress(h)
+        for t in tickets:
+            if t not in got:
+                r = pl.plan_poll(h, t)
+                if r is not None:
+                    got[t] = r
+        if len(got) == len(tickets):
+            return got
+    raise AssertionError("served requests did not finish")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_served_stream_full_size(orc, pl, precision):
+    """The served workload at its measured size: 256 requests of N in {256,
+    512, 1000, 2048}, M in {4, 10, 20}, T in {50, 100} (the bench's seeded
+    mix) through 64 request slots, all submitted at once, K = 20.
+      * One upper iteration: for 12 sampled requests the returned
+        trajectory, residual and upper cost against the oracle's projection
+        of its own draw of the returned sample (the bars above).
+      * Five upper iterations (the measured setting): those requests equal
+        the same requests solved alone, bit for bit."""
+    pos_tol = 1e-4 if precision == 0 else 1e-3
+    tol_scale = 1.0 if precision == 0 else 10.0
+    mix = workload.served_mix(256)
+    reqs, scenes = [], []
+    for i, (N, M, T) in enumerate(mix):
+        s = workload.scene(4, i, M)
+        scenes.append(s)
+        reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i))
+    rng = np.random.default_rng(5)
+    picked = sorted(int(i) for i in rng.choice(len(reqs), 12, replace=False))
+
+    def config(L, slots):
+        return pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=K, upper_iters=L, max_N=2048,
+                                   max_requests=slots, precision=precision)
+
+    print(f"[served full size] precision {precision}: 256 requests, 64 slots, one iteration", flush=True)
+    h1 = pl.plan_create(config(1, 64))
+    tickets = [pl.plan_submit(h1, r) for r in reqs]
+    got = drain(pl, h1, tickets)
+    orc.set_threads(8)
+    flagged = 0
+    for i in picked:
+        N, M, T = mix[i]
+        res = got[tickets[i]]
+        assert res.status == 0, i
+        par = orc.default_params(T=T, M=M, K=K, L=1)
+        sc = orc.Scene(scenes[i].ego, scenes[i].obstacles)
+        p_o = orc.sample(par, scenes[i].seed, 0, N, True)
+        j = res.best_index
+        xb = orc.step1(par, sc, p_o[j:j + 1])
+        xs = orc.project(par, sc, xb)
+        r_o, c_o = orc.residual_cost(par, sc, xs)
+        if ill_conditioned(orc, par, sc, xb, xs, p=p_o[j:j + 1])[0]:
+            flagged += 1
+            continue
+        e = pos_err(orc, T, par.t_f, res.xi_best[None, :], xs)[0]
+        print(f"   request {i} (N={N} T={T} M={M}): best {j} position error {e:.1e} m", flush=True)
+        assert e <= pos_tol, (i, e)
+        assert abs(res.residual - r_o[0]) <= tol_scale * (1e-3 + 1e-4 * abs(r_o[0])), i
+        assert abs(res.cost_upper - c_o[0]) <= tol_scale * (1e-4 * abs(c_o[0]) + 1e-6), i
+    assert flagged <= 2
+
+    print(f"[served full size] precision {precision}: five iterations against alone", flush=True)
+    h5 = pl.plan_create(config(5, 64))
+    tickets = [pl.plan_submit(h5, r) for r in reqs]
+    got = drain(pl, h5, tickets)
+    h_alone = pl.plan_create(config(5, 1))
+    for i in picked:
+        a = pl.plan_solve_batch(h_alone, [reqs[i]])[0]
+        b = got[tickets[i]]
+        assert a.status == b.status == 0, i
+        assert a.best_index == b.best_index and np.array_equal(a.xi_best, b.xi_best), i
+        assert np.array_equal(a.mu, b.mu) and np.array_equal(a.sigma, b.sigma), i
