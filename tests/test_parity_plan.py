@@ -60,12 +60,13 @@ def set_check(name, gpu_idx, orc_idx, orc_key, tol_of_key, exempt=None):
 
 
 def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e-4, behaviour=0, sampler=0,
-               L=None, road=False, decoder_seed=None, p0_tol=None):
+               L=None, road=False, decoder_seed=None, p0_tol=None, method=None):
     c = workload.CONFIGS[cfgid]
     N, T, M, K = c["N"], c["T"], c["M"], c["K"]
     L = c["L"] if L is None else L
     orc.set_threads(8)
-    par = orc.default_params(T=T, M=M, K=K, L=L, behaviour=behaviour, sampler=sampler)
+    method = method or {}  # method parameters set alike on both sides
+    par = orc.default_params(T=T, M=M, K=K, L=L, behaviour=behaviour, sampler=sampler, **method)
     s = workload.scene(cfgid, scene_idx, M)
     rk = {}
     if road:
@@ -84,7 +85,7 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
     n, q = orc.elite_sizes(par, N)
     cfg = pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=K, upper_iters=1, max_N=N,
                               max_requests=1, trace=1, precision=precision, behaviour=behaviour,
-                              sampler=sampler)
+                              sampler=sampler, **method)
     h = pl.plan_create(cfg)
     if dec is not None:
         pl.plan_set_decoder(h, dec)
@@ -167,6 +168,16 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
 @pytest.mark.parametrize("cfgid,scene_idx", [(1, 0), (1, 1), (2, 0)])
 def test_plan_parity_per_iteration(orc, pl, cfgid, scene_idx):
     run_config(orc, pl, cfgid, scene_idx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plan_parity_mostly_infeasible(orc, pl, precision):
+    """a_max = 1 m/s^2 leaves 10-20 of the 1000 samples feasible (r = 0), so
+    the ConstraintEliteSet of 150 is not a run of equal smallest keys: the
+    selection kernel takes its radix passes over the residual keys and the
+    position-ordered scan of the boundary bin."""
+    kw = dict(tol_scale=10.0, pos_tol=1e-3) if precision else {}
+    run_config(orc, pl, 2, 0, precision=precision, L=3, method=dict(a_max=1.0), **kw)
 
 
 def test_plan_parity_large_elite_sets(orc, pl):
