@@ -260,6 +260,15 @@ def test_bad_request_fails_alone(pl):
     assert out[1].status == 0
     alone = pl.plan_solve_batch(h, [good])[0]
     assert np.array_equal(alone.xi_best, out[1].xi_best)
+    # sizes outside [1, max_N] fail alone too; an empty batch is a no-op
+    out = pl.plan_solve_batch(h, [pl.Request(N=0, T=50, ego=s.ego, obstacles=s.obstacles, seed=1), good,
+                                  pl.Request(N=65, T=50, ego=s.ego, obstacles=s.obstacles, seed=1)])
+    assert out[0].status == pl.PLAN_E_INVALID and out[2].status == pl.PLAN_E_INVALID
+    assert out[1].status == 0 and np.array_equal(out[1].xi_best, alone.xi_best)
+    assert pl.plan_solve_batch(h, []) == []
+    # one sample: it is its own elite sets and the returned trajectory
+    one = pl.plan_solve_batch(h, [pl.Request(N=1, T=50, ego=s.ego, obstacles=s.obstacles, seed=3)])[0]
+    assert one.status == 0 and one.best_index == 0 and np.all(np.isfinite(one.xi_best))
 
 
 def test_session_warm_start(pl):
