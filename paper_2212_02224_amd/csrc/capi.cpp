@@ -966,27 +966,28 @@ void admit_queued(plan_handle *h, std::vector<int> &admitted) {
 
 void free_handle(plan_handle *h) {
   if (!h) return;
-  if (h->stream) hipStreamSynchronize(h->stream);
+  // best effort: a failure while releasing cannot be reported to anyone
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (auto &e : h->ev_free) {
-    hipEventDestroy(e.first);
-    hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
   }
   for (auto &e : h->ev_pending) {
-    hipEventDestroy(e.second.first);
-    hipEventDestroy(e.second.second);
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
   }
-  if (h->own_mem && h->mem.base) hipFree(h->mem.base);
-  if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
-  if (h->h_desc) hipHostFree(h->h_desc);
+  if (h->own_mem && h->mem.base) (void)hipFree(h->mem.base);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->h_desc) (void)hipHostFree(h->h_desc);
   for (int r = 0; r < kRing; ++r) {
-    if (h->h_act_ring[r]) hipHostFree(h->h_act_ring[r]);
-    if (h->h_seg_ring[r]) hipHostFree(h->h_seg_ring[r]);
-    if (h->ring_ev[r]) hipEventDestroy(h->ring_ev[r]);
+    if (h->h_act_ring[r]) (void)hipHostFree(h->h_act_ring[r]);
+    if (h->h_seg_ring[r]) (void)hipHostFree(h->h_seg_ring[r]);
+    if (h->ring_ev[r]) (void)hipEventDestroy(h->ring_ev[r]);
   }
-  for (auto &rt : h->retiring) hipEventDestroy(rt.ev);
-  for (hipEvent_t e : h->sync_ev_free) hipEventDestroy(e);
-  if (h->h_result) hipHostFree(h->h_result);
-  if (h->h_dist) hipHostFree(h->h_dist);
+  for (auto &rt : h->retiring) (void)hipEventDestroy(rt.ev);
+  for (hipEvent_t e : h->sync_ev_free) (void)hipEventDestroy(e);
+  if (h->h_result) (void)hipHostFree(h->h_result);
+  if (h->h_dist) (void)hipHostFree(h->h_dist);
   delete h;
 }
 
@@ -1369,8 +1370,9 @@ plan_status plan_mpc_run(plan_handle *h, const plan_request *reqs, int32_t n, in
     std::vector<plan_result> tmp(out ? 0 : n);
     st = collect_impl(h, out ? out : tmp.data(), el);
   }
-  hipStreamSynchronize(h->stream);
-  hipFree(buf);
+  // release the loop's buffer on every path; the call's status is already decided
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(buf);
   h->staged = 0;
   h->staged_total = 0;
   if (e != hipSuccess) return hip_fail(h, e, "closed loop");
