@@ -1,11 +1,14 @@
 """GPU checks of the receding-horizon closed loop (plan_mpc_run): the loop
 that runs on the device without host round trips equals a host-driven
 sequence of single plans bit for bit (same state, neighbours, seed and warm
-start per cycle), and its advance step (state reached, neighbour motion,
-collision test) agrees with the FP64 oracle's, fed the GPU's trajectories.
-The per-iteration parity of each plan against the oracle is covered by the
-plan parity tests; the warm start enters them the same way (a given mu,
-Sigma at iteration 0)."""
+start per cycle), and its advance step has the properties that define it:
+each cycle starts at the previous cycle's returned trajectory evaluated at
+the execution instant, and a cycle is flagged as a collision exactly when an
+executed instant lies inside a neighbour's ellipse (evaluated here in FP64
+with the Bernstein basis of eq. param). The per-iteration parity of each
+plan against the oracle is covered by the plan parity tests; the warm start
+enters them the same way (a given mu, Sigma at iteration 0). The oracle's
+own advance is pinned on the CPU (test_oracle_mpc.py)."""
 import numpy as np
 import pytest
 
@@ -78,25 +81,46 @@ def test_mpc_loop_equals_single_plans_fp16_split(orc, pl, init):
     check_loop_against_single_plans(orc, pl, 1, init)
 
 
-def test_mpc_advance_matches_oracle(orc, pl):
-    """The GPU's advance (FP64 Bernstein evaluation, fma neighbour motion)
-    against the oracle's (basis rows of the oracle) on the GPU's own
-    trajectories: states within 1e-9, collision flags equal."""
+def check_advance(orc, reqs, log, cycles):
+    """The properties of the advance step on the loop's own logs: the state
+    of cycle c + 1 is trajectory xi_c at t_{n_exec} (position, velocity,
+    acceleration of both axes), and cycle c is flagged iff an executed
+    instant t_0..t_{n_exec} lies inside a neighbour's ellipse, the
+    neighbours moving at constant velocity from their first-cycle states
+    (scene time (c n_exec + k) t_f / (T - 1)). Returns the largest state
+    difference."""
+    worst = 0.0
+    for e, r in enumerate(reqs):
+        par = orc.default_params(T=r.T, M=r.M)
+        W, Wd, Wdd = orc.basis(r.T, par.t_f)
+        obs0 = np.asarray(r.obstacles, float).reshape(-1, 4)
+        for c in range(cycles):
+            xi = log["xi"][e, c]
+            k = N_EXEC
+            want = np.array([W[k] @ xi[:11], W[k] @ xi[11:], Wd[k] @ xi[:11], Wd[k] @ xi[11:],
+                             Wdd[k] @ xi[:11], Wdd[k] @ xi[11:]])
+            d = np.abs(want - log["ego"][e, c + 1])
+            worst = max(worst, d.max())
+            assert np.all(d <= 1e-9 * (1 + np.abs(want))), (e, c, d)
+            hit = False
+            for kk in range(N_EXEC + 1):
+                x, y = W[kk] @ xi[:11], W[kk] @ xi[11:]
+                s = (c * N_EXEC + kk) * par.t_f / (r.T - 1)
+                u = (x - (obs0[:, 0] + obs0[:, 2] * s)) / par.ell_a
+                v = (y - (obs0[:, 1] + obs0[:, 3] * s)) / par.ell_b
+                hit = hit or bool(np.any(u * u + v * v < 1.0))
+            assert bool(log["collided"][e, c]) == hit, (e, c)
+    return worst
+
+
+def test_mpc_advance_properties(orc, pl):
     mix = [(128, 100, 10), (64, 50, 4), (96, 100, 20), (32, 50, 10)]
     cycles = 6
     h = pl.plan_create(pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=10, upper_iters=3,
                                            max_N=128, max_requests=4))
     reqs = episodes(pl, mix, 40)
     _, log = pl.plan_mpc_run(h, reqs, cycles, N_EXEC)
-    worst = 0.0
-    for e, r in enumerate(reqs):
-        par = orc.default_params(T=r.T, M=r.M)
-        for c in range(cycles):
-            ego, _, hit = orc.advance(par, log["xi"][e, c], r.obstacles, c, N_EXEC)
-            d = np.abs(ego - log["ego"][e, c + 1])
-            worst = max(worst, d.max())
-            assert np.all(d <= 1e-9 * (1 + np.abs(ego))), (e, c, d)
-            assert bool(log["collided"][e, c]) == hit, (e, c)
+    worst = check_advance(orc, reqs, log, cycles)
     print(f"[mpc] advance: largest state difference {worst:.2e}", flush=True)
     # each cycle starts where the previous one ended: x moves forward
     assert np.all(np.diff(log["ego"][:, :, 0], axis=1) > 0)
@@ -104,7 +128,8 @@ def test_mpc_advance_matches_oracle(orc, pl):
 
 def test_mpc_collision_is_reported(orc, pl):
     """A neighbour placed on the ego (normalised distance below 1 at t = 0)
-    is a collision of the first cycle, on both sides."""
+    is a collision of the first cycle, and the flags have the advance
+    properties."""
     T, M = 50, 4
     h = pl.plan_create(pl.plan_config_init(T_set=[T], M_set=[M], proj_iters=10, upper_iters=2, max_N=64,
                                            max_requests=2))
@@ -114,8 +139,7 @@ def test_mpc_collision_is_reported(orc, pl):
     reqs = [pl.Request(N=64, T=T, ego=s.ego, obstacles=obs, seed=5, session_id=77)]
     _, log = pl.plan_mpc_run(h, reqs, 2, N_EXEC)
     assert log["collided"][0, 0] == 1
-    par = orc.default_params(T=T, M=M)
-    assert orc.advance(par, log["xi"][0, 0], obs, 0, N_EXEC)[2]
+    check_advance(orc, reqs, log, 2)
 
 
 @pytest.mark.parametrize("init", [0, 1])
@@ -151,3 +175,33 @@ def test_mpc_rejects_bad_arguments(pl):
     # the handle still works afterwards; without a warm start no session is needed
     res, log = pl.plan_mpc_run(h, [req(0), req(0)], 2, 5, log=("ego", "collided"))
     assert res[0].status == 0 and set(log) == {"ego", "collided"}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mpc_full_size(orc, pl, precision):
+    """The measured closed-loop configuration at full size: 256 episodes of
+    N = 1000, T = 100, M = 10, L = 5, K = 20 (the headline planner), here for
+    three cycles. Every cycle succeeds, the advance properties hold for every
+    episode and cycle, and sampled episodes equal the same episode run
+    alone, bit for bit."""
+    c = workload.CONFIGS[2]
+    N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
+    cycles, n_ep = 3, 256
+    kw = dict(T_set=[T], M_set=[M], proj_iters=K, upper_iters=L, max_N=N, precision=precision)
+    reqs = []
+    for i in range(n_ep):
+        s = workload.scene(7, i, M)
+        reqs.append(pl.Request(N=N, T=T, ego=s.ego, obstacles=s.obstacles, seed=s.seed, request_id=i,
+                               session_id=1 + i))
+    print(f"[mpc full size] precision {precision}: {n_ep} episodes x {cycles} cycles, N={N}", flush=True)
+    h = pl.plan_create(pl.plan_config_init(max_requests=n_ep, **kw))
+    _, log = pl.plan_mpc_run(h, reqs, cycles, N_EXEC)
+    assert np.all(log["status"] == 0)
+    worst = check_advance(orc, reqs, log, cycles)
+    print(f"   advance: largest state difference {worst:.2e}; collisions flagged "
+          f"{int(log['collided'].sum())}", flush=True)
+    h1 = pl.plan_create(pl.plan_config_init(max_requests=1, **kw))
+    for e in (0, 97, 255):
+        _, alone = pl.plan_mpc_run(h1, [reqs[e]], cycles, N_EXEC)
+        for k in ("ego", "xi", "mu", "collided"):
+            assert np.array_equal(alone[k][0], log[k][e]), (e, k)
