@@ -9,9 +9,11 @@ decoder MLP of the learned sampler (``decoder_forward``: numpy FP64, layer by
 layer as App. A lists them). This module is the ctypes marshalling around the
 C code and its build step (``gcc``).
 
-Parity status: pinned by the CPU tests in ``tests/test_oracle_*.py`` except
-the values of the projection iterates at finite K (parity unpinned; their
-fixed points, invariances and convergence are pinned).
+Parity status: pinned by the CPU tests in ``tests/test_oracle_*.py``. Of the
+projection (Alg. 2), every xi-update, every target pass and the fixed point
+of the multiplier step are pinned; the multiplier step's length (the printed
+rho/2 of eq. update_lagrange) is not, so the iterate values at finite K are
+"parity unpinned" in that one factor.
 """
 from __future__ import annotations
 
@@ -103,6 +105,7 @@ def _load():
     lib.orc_lower_cost.restype = C.c_double
     lib.orc_step1.argtypes = [P, S, _PD, C.c_int, _PD]
     lib.orc_project.argtypes = [P, S, _PD, _PD, C.c_int, _PD, _PD]
+    lib.orc_project_dump.argtypes = [P, S, _PD, _PD, _PD, _PD, _PD, _PD, _PD, _PD]
     lib.orc_targets.argtypes = [P, S, _PD, _PD, _PD, _PD, _PD]
     lib.orc_residual_cost.argtypes = [P, S, _PD, C.c_int, _PD, _PD]
     lib.orc_select.argtypes = [_PD, _PD, C.c_int, C.c_int, C.c_int, _PI, _PI, _PD]
@@ -233,6 +236,26 @@ def project(par: Params, scene: Scene, xi_bar, return_iterates: bool = False, p=
     if rc != 0:
         raise ValueError("oracle project: goal positions need the samples p")
     return (out, it) if return_iterates else out
+
+
+def project_dump(par: Params, scene: Scene, xi_bar, p=None) -> dict:
+    """Alg. 2 for one sample with every intermediate, k = 0..K: ``xi``
+    (K+1 x 22; xi^0 = xi_bar, then each xi-update of eq. split_xy), the
+    target pass at xi^k: ``h`` (K+1 x 2(M+2)T, rows of F), ``s`` and ``e``
+    (K+1 x 2T, lane slack and bound), ``da`` (K+1 x T), and ``lam`` (K+1 x
+    22: lambda^0 = 0, lambda^k after the step update_lagrange of iteration
+    k). The xi-update of iteration k uses row k - 1 of lam, h, s and e."""
+    xb = _f64(xi_bar).reshape(NX)
+    K, T, M = par.K, par.T, par.M
+    out = dict(xi=np.zeros((K + 1, NX)), h=np.zeros((K + 1, 2 * (M + 2) * T)), s=np.zeros((K + 1, 2 * T)),
+               e=np.zeros((K + 1, 2 * T)), da=np.zeros((K + 1, T)), lam=np.zeros((K + 1, NX)))
+    pp = _f64(p).reshape(NP) if p is not None else None
+    sc = scene.c()
+    rc = _load().orc_project_dump(C.byref(par), C.byref(sc), _pd(xb), _pd(pp) if pp is not None else None,
+                                  *[_pd(out[k]) for k in ("xi", "h", "s", "e", "da", "lam")])
+    if rc != 0:
+        raise ValueError("oracle project_dump: goal positions need the sample p")
+    return out
 
 
 def targets(par: Params, scene: Scene, xi, da_prev):

@@ -17,10 +17,13 @@
  * build's design notes; each is marked "reading" below.
  *
  * Parity status: every function is pinned by CPU tests (closed forms,
- * invariants, brute force, known-answer vectors), except the numerical
- * values of the projection iterates at finite K, which no passage of the
- * paper fixes ("parity unpinned" for orc_project iterate values; its fixed
- * points, invariances and convergence are pinned).
+ * invariants, brute force, known-answer vectors). In orc_project every
+ * xi-update is pinned (its KKT system at each iteration, the first one by an
+ * independent least-squares solve), the target pass by brute force, and the
+ * multiplier step by the fixed point it must reach. The length of the
+ * multiplier step (the printed rho/2 of eq. update_lagrange) is the one
+ * factor no property fixes: any positive length has the same fixed points,
+ * so the iterate values at finite K are "parity unpinned" in that factor.
  */
 #include "oracle.h"
 
@@ -661,8 +664,29 @@ static void acc_norm_clip(const proj_t *P, const double *xi, double *da) {
 /* Alg. 2 for one sample (reading of the unprinted initialisation: xi^0 =
  * xi_bar, lambda^0 = 0, targets from xi_bar with d_a^{-1} = clip(|a|, 0,
  * a_max); the returned iterate is the last xi-update). */
+/* Every intermediate of Alg. 2 for one sample, iterations k = 0..K (each
+ * array nullable): the iterate xi^k (xi^0 = xi_bar), the target pass taken
+ * at it (h^k, s^k, the lane bound e^k, d_a^k) and the multiplier lambda^k
+ * after the step update_lagrange of iteration k (lambda^0 = 0). */
+typedef struct proj_dump {
+  double *xi, *h, *s, *e, *da, *lam;
+} proj_dump;
+
+static void dump_step(const proj_t *P, const proj_dump *D, int k, const double *xi,
+                      const double *h, const double *s, const double *e,
+                      const double *da, const double *lam) {
+  if (!D) return;
+  int T = P->T, nF = P->nF;
+  if (D->xi) memcpy(D->xi + (size_t)k * NX, xi, sizeof(double) * NX);
+  if (D->h) memcpy(D->h + (size_t)k * nF, h, sizeof(double) * nF);
+  if (D->s) memcpy(D->s + (size_t)k * 2 * T, s, sizeof(double) * 2 * T);
+  if (D->e) memcpy(D->e + (size_t)k * 2 * T, e, sizeof(double) * 2 * T);
+  if (D->da) memcpy(D->da + (size_t)k * T, da, sizeof(double) * T);
+  if (D->lam) memcpy(D->lam + (size_t)k * NX, lam, sizeof(double) * NX);
+}
+
 static void project_one(const proj_t *P, const double *xi_bar, const double *p,
-                        double *xi_out, double *xi_iter) {
+                        double *xi_out, double *xi_iter, const proj_dump *dump) {
   const orc_params *par = P->par;
   int T = P->T, nF = P->nF, K = par->K;
   double rho = par->rho;
@@ -681,6 +705,7 @@ static void project_one(const proj_t *P, const double *xi_bar, const double *p,
   targets(P, xi, da_prev, h, s, e, da);
   memcpy(da_prev, da, sizeof(double) * T);
   if (xi_iter) memcpy(xi_iter, xi, sizeof(xi));
+  dump_step(P, dump, 0, xi, h, s, e, da, lam);
 
   for (int k = 1; k <= K; ++k) {
     /* eq. split_xy */
@@ -723,6 +748,7 @@ static void project_one(const proj_t *P, const double *xi_bar, const double *p,
       v = v - e[r] + s[r];
       for (int i = 0; i < NX; ++i) lam[i] -= 0.5 * rho * Gr[i] * v;
     }
+    dump_step(P, dump, k, xi, h, s, e, da, lam);
   }
   memcpy(xi_out, xi, sizeof(xi));
   free(e);
@@ -745,7 +771,20 @@ int orc_project(const orc_params *par, const orc_scene *sc,
   for (int j = 0; j < N; ++j)
     project_one(&P, xi_bar + (size_t)j * NX, p ? p + (size_t)j * NP : NULL,
                 xi_star + (size_t)j * NX,
-                xi_iter ? xi_iter + (size_t)j * stride_it : NULL);
+                xi_iter ? xi_iter + (size_t)j * stride_it : NULL, NULL);
+  proj_free(&P);
+  return 0;
+}
+
+int orc_project_dump(const orc_params *par, const orc_scene *sc,
+                     const double *xi_bar, const double *p, double *xi,
+                     double *h, double *s, double *e, double *da, double *lam) {
+  if (par->behaviour && p == NULL) return -1;
+  proj_t P;
+  proj_init(&P, par, sc);
+  proj_dump D = {xi, h, s, e, da, lam};
+  double xs[NX];
+  project_one(&P, xi_bar, p, xs, NULL, &D);
   proj_free(&P);
   return 0;
 }

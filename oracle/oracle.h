@@ -94,6 +94,21 @@ int orc_project(const orc_params *par, const orc_scene *sc,
                 const double *xi_bar, const double *p, int N, double *xi_star,
                 double *xi_iter);
 
+/* Alg. 2 for one sample with every intermediate, iterations k = 0..K (each
+ * output nullable, row k of each array belongs to iteration k):
+ *   xi   (K+1) x 22          xi^0 = xi_bar, xi^k the k-th xi-update (eq.
+ *                            split_xy)
+ *   h    (K+1) x 2(M+2)T     targets of the pass at xi^k (rows of F)
+ *   s, e (K+1) x 2T          lane slack and lane bound e of that pass
+ *   da   (K+1) x T           d_a of that pass
+ *   lam  (K+1) x 22          lambda^0 = 0, lambda^k after the step
+ *                            update_lagrange of iteration k
+ * The xi-update of iteration k uses lambda^(k-1), h^(k-1), s^(k-1), e^(k-1).
+ * p as for orc_project. The same code as orc_project computes it. */
+int orc_project_dump(const orc_params *par, const orc_scene *sc,
+                     const double *xi_bar, const double *p, double *xi,
+                     double *h, double *s, double *e, double *da, double *lam);
+
 /* One target pass of Alg. 2 (steps split_alpha_o .. update_slack) for one
  * xi. h is 2(M+2)T (rows of F), s is 2T, da_prev/da_out are T. */
 void orc_targets(const orc_params *par, const orc_scene *sc, const double *xi,

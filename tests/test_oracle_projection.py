@@ -1,7 +1,7 @@
 """Pins of the oracle's projection (Alg. 2) and target pass.
 
-No passage of the paper prints iterate values, so the values of the iterates
-at finite K are "parity unpinned". What is pinned:
+No passage of the paper prints iterate values. Every step of each iteration
+is pinned in test_oracle_alg2_steps.py; here, what is pinned of the whole:
   * the closed-form (alpha, d) of step split_alpha_o against a brute-force
     grid minimisation, and the clips of steps clip_d_o .. clip_d_a on
     hand-computed cases;
