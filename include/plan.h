@@ -257,6 +257,16 @@ typedef struct plan_request {
  * EliteSet with the smallest augmented cost c_u + r (ties: lower index), its
  * behavioural input and projected trajectory, and the sampling distribution
  * after the last update (the warm start of the next planning cycle).
+ * The selection ranks samples by the lower level's own residual and cost
+ * (FP32, or FP16-split products with FP32 sums); the returned trajectory's
+ * residual and upper cost are then evaluated again in FP64 (its Bernstein
+ * polynomial, every row of Table ineq_list at every instant t_k), and
+ * PLAN_F_INFEASIBLE is set from that FP64 residual.
+ *   traj_xy   caller-owned, nullable: T x 2 doubles (x, y at t_k, k = 0..T-1,
+ *             FP64 on the device) of the returned trajectory. Set it before
+ *             the call that fills the result (plan_solve_batch, plan_collect,
+ *             plan_poll, plan_mpc_run); the library keeps the pointer and
+ *             writes T x 2 values there when the request succeeded.
  */
 typedef struct plan_result {
   int32_t status;
@@ -265,11 +275,12 @@ typedef struct plan_result {
   int32_t iterations;
   double p_best[PLAN_NP];
   double xi_best[PLAN_NX];
-  double cost_upper; /* c_u of the best sample */
-  double residual;   /* r of the best sample   */
+  double cost_upper; /* c_u of the returned trajectory (FP64 evaluation) */
+  double residual;   /* r of the returned trajectory (FP64 evaluation)   */
   double mu[PLAN_NP];
   double sigma[PLAN_NP * PLAN_NP];
   double latency_s;  /* submit -> completion (served path), else solve time */
+  double *traj_xy;   /* caller-owned T x 2 or NULL (see above)            */
 } plan_result;
 
 typedef struct plan_handle plan_handle; /* opaque, owned by the library */
@@ -280,6 +291,12 @@ void plan_config_init(plan_config *cfg);
 
 /* Device bytes the library needs for cfg (tables + max_requests slots). */
 size_t plan_workspace_bytes(const plan_config *cfg);
+
+/* Sizes of the ConstraintEliteSet (*n_ces) and EliteSet (*n_es) of Alg. 1
+ * for a request of N samples under cfg: q = max(1, round(frac_es N)),
+ * n = max(q, round(frac_ces N)), both at most N (150 and 50 at N = 1000,
+ * Sec. V-A). PLAN_E_INVALID for a NULL argument or N outside [1, max_N]. */
+plan_status plan_elite_sizes(const plan_config *cfg, int32_t N, int32_t *n_ces, int32_t *n_es);
 
 /* Validate cfg, precompute the sample-independent matrices in FP64 (once,
  * Sec. III-C), and set up device memory. *out receives the handle.
@@ -294,8 +311,11 @@ void plan_destroy(plan_handle *h);
 const char *plan_last_error(const plan_handle *h);
 
 /* Solve n requests (Alg. 1 each) and wait. out[i] gets request i's result;
- * a bad request fails alone (its status), the call returns the worst status.
- * Requests beyond max_requests run in successive groups. */
+ * a bad request fails alone (its status: PLAN_E_INVALID, or PLAN_E_NOMEM for
+ * an N beyond the sample budget), the call returns the worst status.
+ * Requests beyond max_requests or the budget run in successive groups; if a
+ * group cannot run (a device error), it and every later request get that
+ * status. */
 plan_status plan_solve_batch(plan_handle *h, const plan_request *reqs,
                              int32_t n, plan_result *out);
 
@@ -310,7 +330,9 @@ plan_status plan_collect(plan_handle *h, plan_result *out);
 
 /* Lower level only (Alg. 1 Steps 1-2 and the residual/cost) for the given
  * behavioural inputs p (host, N x 8), one request's scene. Outputs (host,
- * nullable): xi_bar, xi_star (N x 22), resid, cost_upper (N). */
+ * nullable): xi_bar, xi_star (N x 22), resid, cost_upper (N; the lower
+ * level's own values, as the selection sees them). PLAN_E_INVALID for a bad
+ * request or non-finite p, PLAN_E_NOMEM if N exceeds the sample budget. */
 plan_status plan_lower_solve(plan_handle *h, const plan_request *req,
                              const double *p, int32_t N, double *xi_bar,
                              double *xi_star, double *resid,
@@ -342,9 +364,12 @@ plan_status plan_get_trace(plan_handle *h, int32_t i, double *p, double *resid,
  * PLAN_E_BUSY until the ticket's request is done, then its result
  * (latency_s: submit to the call that saw it complete) and forgets the
  * ticket. A request's arithmetic does not depend on what else is resident,
- * so its result equals the one of plan_solve_batch bit for bit. A session's
- * warm start is available to requests admitted after the previous request
- * of the session was retired. *n_active / *n_queued (nullable) receive the
+ * so its result equals the one of plan_solve_batch bit for bit. A request
+ * with a session_id is admitted only once no other request of its session is
+ * in flight (it, and the queue behind it, wait for that one to retire), so
+ * it starts from the distribution the session's previous request left,
+ * whatever the timing. plan_submit fails with PLAN_E_NOMEM for an N beyond
+ * the sample budget. *n_active / *n_queued (nullable) receive the
  * in-flight (resident or retiring) and waiting counts. plan_submit fails
  * with PLAN_E_INVALID for a bad request. The batch calls (plan_solve_batch,
  * plan_stage, plan_mpc_run, plan_set_decoder) return PLAN_E_BUSY while any
@@ -450,9 +475,10 @@ typedef struct plan_decoder {
 /* Load the decoder sampler's weights (needed before any request of a
  * handle whose config has sampler = PLAN_SAMPLER_DECODER). The library
  * folds each BatchNorm and bias into its Linear layer in FP64 and keeps the
- * layers on the device: the first in FP32, blocks 2-5 as FP16 high/low
- * pairs (three matrix-core products recover about 22 significant bits, as
- * the lower level's FP16-split form does), the output layer in FP32. The
+ * layers on the device: blocks 1-5 as FP16 high/low pairs on the matrix
+ * cores (block 1 with its 57 inputs padded to 64; three products recover
+ * about 22 significant bits, as the lower level's FP16-split form does), the
+ * output layer in FP32. The
  * arrays are copied; the call waits for the upload. PLAN_E_INVALID for a
  * handle without the decoder sampler, a missing or non-finite array, a
  * variance with var + eps <= 0, or weights beyond 1e30 in magnitude;

@@ -94,6 +94,7 @@ class plan_result(C.Structure):
         ("cost_upper", C.c_double), ("residual", C.c_double),
         ("mu", C.c_double * NP), ("sigma", C.c_double * (NP * NP)),
         ("latency_s", C.c_double),
+        ("traj_xy", _PD),
     ]
 
 
@@ -140,9 +141,10 @@ def load():
     lib.plan_profile.argtypes = [H, C.c_int32]
     lib.plan_profile_read.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.plan_set_decoder.argtypes = [H, C.POINTER(plan_decoder)]
+    lib.plan_elite_sizes.argtypes = [Cfg, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     for name in ("plan_create", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
                  "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-                 "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder"):
+                 "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder", "plan_elite_sizes"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -152,7 +154,7 @@ def exported_symbols() -> list[str]:
     return ["plan_config_init", "plan_workspace_bytes", "plan_create", "plan_destroy",
             "plan_last_error", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
             "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-            "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder"]
+            "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder", "plan_elite_sizes"]
 
 
 def _check(status: int, handle=None) -> int:
@@ -244,11 +246,26 @@ class Result:
     mu: np.ndarray
     sigma: np.ndarray
     latency_s: float
+    traj: np.ndarray | None = None  # T x 2 positions of the returned trajectory (FP64, from the device)
 
 
-def _result(r: plan_result) -> Result:
-    return Result(r.status, r.flags, r.best_index, r.iterations, np.array(r.p_best), np.array(r.xi_best),
-                  r.cost_upper, r.residual, np.array(r.mu), np.array(r.sigma).reshape(8, 8), r.latency_s)
+class _Results:
+    """plan_result array whose traj_xy members point at T x 2 numpy
+    buffers, one per request."""
+
+    def __init__(self, Ts: Sequence[int]):
+        self.arr = (plan_result * max(1, len(Ts)))()
+        self.traj = []
+        for i, T in enumerate(Ts):
+            a = np.full((max(int(T), 1), 2), np.nan)
+            self.traj.append(a)
+            self.arr[i].traj_xy = _pd(a)
+
+    def result(self, i: int) -> Result:
+        r = self.arr[i]
+        return Result(r.status, r.flags, r.best_index, r.iterations, np.array(r.p_best), np.array(r.xi_best),
+                      r.cost_upper, r.residual, np.array(r.mu), np.array(r.sigma).reshape(8, 8), r.latency_s,
+                      self.traj[i] if r.status == 0 else None)
 
 
 # ----------------------------------------------------------- entry points
@@ -315,16 +332,16 @@ def plan_last_error(h: Handle | None = None) -> str:
 
 def plan_solve_batch(h: Handle, reqs: Sequence[Request], check: bool = True) -> list[Result]:
     m = _Marshalled(reqs)
-    out = (plan_result * max(1, len(reqs)))()
-    st = load().plan_solve_batch(h.ptr, m.arr, len(reqs), out)
-    if check and st not in (PLAN_OK, PLAN_E_INVALID):
+    out = _Results([r.T for r in reqs])
+    st = load().plan_solve_batch(h.ptr, m.arr, len(reqs), out.arr)
+    if check and st not in (PLAN_OK, PLAN_E_INVALID, PLAN_E_NOMEM):
         _check(st, h.ptr)
-    return [_result(out[i]) for i in range(len(reqs))]
+    return [out.result(i) for i in range(len(reqs))]
 
 
 def plan_stage(h: Handle, reqs: Sequence[Request]) -> None:
     m = _Marshalled(reqs)
-    h._staged_n = len(reqs)
+    h._staged_T = [r.T for r in reqs]
     _check(load().plan_stage(h.ptr, m.arr, len(reqs)), h.ptr)
 
 
@@ -333,12 +350,12 @@ def plan_launch(h: Handle) -> None:
 
 
 def plan_collect(h: Handle) -> list[Result]:
-    n = getattr(h, "_staged_n", 0)
-    out = (plan_result * max(1, n))()
-    st = load().plan_collect(h.ptr, out)
-    if st not in (PLAN_OK, PLAN_E_INVALID):
+    Ts = getattr(h, "_staged_T", [])
+    out = _Results(Ts)
+    st = load().plan_collect(h.ptr, out.arr)
+    if st not in (PLAN_OK, PLAN_E_INVALID, PLAN_E_NOMEM):
         _check(st, h.ptr)
-    return [_result(out[i]) for i in range(n)]
+    return [out.result(i) for i in range(len(Ts))]
 
 
 def plan_lower_solve(h: Handle, req: Request, p: np.ndarray):
@@ -370,6 +387,9 @@ def plan_submit(h: Handle, req: Request) -> int:
     m = _Marshalled([req])
     t = C.c_uint64()
     _check(load().plan_submit(h.ptr, m.arr, C.byref(t)), h.ptr)
+    if not hasattr(h, "_ticket_T"):
+        h._ticket_T = {}
+    h._ticket_T[int(t.value)] = int(req.T)
     return int(t.value)
 
 
@@ -383,12 +403,14 @@ def plan_progress(h: Handle) -> tuple[int, int]:
 
 def plan_poll(h: Handle, ticket: int) -> Result | None:
     """The result of a finished ticket, or None while it is queued/resident."""
-    out = plan_result()
-    st = load().plan_poll(h.ptr, C.c_uint64(int(ticket)), C.byref(out))
+    T = getattr(h, "_ticket_T", {}).get(int(ticket), 1)
+    out = _Results([T])
+    st = load().plan_poll(h.ptr, C.c_uint64(int(ticket)), out.arr)
     if st == PLAN_E_BUSY:
         return None
     _check(st, h.ptr)
-    return _result(out)
+    h._ticket_T.pop(int(ticket), None)
+    return out.result(0)
 
 
 MPC_LOGS = ("ego", "xi", "mu", "sigma", "cost", "collided", "status")
@@ -402,7 +424,7 @@ def plan_mpc_run(h: Handle, reqs: Sequence[Request], cycles: int, n_exec: int = 
     (results of the last cycle, {name: array})."""
     n = len(reqs)
     m = _Marshalled(reqs)
-    out = (plan_result * max(1, n))()
+    out = _Results([r.T for r in reqs])
     shapes = dict(ego=(n, cycles + 1, 6), xi=(n, cycles, NX), mu=(n, cycles, NP), sigma=(n, cycles, NP, NP),
                   cost=(n, cycles, 2), collided=(n, cycles), status=(n, cycles))
     logs = {}
@@ -413,8 +435,8 @@ def plan_mpc_run(h: Handle, reqs: Sequence[Request], cycles: int, n_exec: int = 
         a = np.zeros(shapes[name], np.int32 if name in ("collided", "status") else np.float64)
         logs[name] = a
         setattr(lg, name, a.ctypes.data_as(_PI if a.dtype == np.int32 else _PD))
-    _check(load().plan_mpc_run(h.ptr, m.arr, n, int(cycles), int(n_exec), int(init), C.byref(lg), out), h.ptr)
-    return [_result(out[i]) for i in range(n)], logs
+    _check(load().plan_mpc_run(h.ptr, m.arr, n, int(cycles), int(n_exec), int(init), C.byref(lg), out.arr), h.ptr)
+    return [out.result(i) for i in range(n)], logs
 
 
 def plan_profile(h: Handle, enable: bool = True) -> None:
@@ -450,8 +472,10 @@ def plan_set_decoder(h: Handle, dec) -> None:
 
 
 def elite_sizes(cfg: plan_config, N: int) -> tuple[int, int]:
-    """(n, q) of the ConstraintEliteSet / EliteSet for N samples."""
-    q = max(1, int(np.floor(cfg.frac_es * N + 0.5)))
-    n = max(q, int(np.floor(cfg.frac_ces * N + 0.5)))
-    n = min(n, N)
-    return n, min(q, n)
+    """(n, q) of the ConstraintEliteSet / EliteSet for N samples, as the
+    library sizes them."""
+    n, q = C.c_int32(), C.c_int32()
+    st = load().plan_elite_sizes(C.byref(cfg), int(N), C.byref(n), C.byref(q))
+    if st != PLAN_OK:
+        raise PlanError(st, f"elite sizes: N = {N} outside [1, max_N]")
+    return int(n.value), int(q.value)

@@ -132,13 +132,13 @@ struct DevBuf {
 // Device bytes of every region, in allocation order.
 struct Layout {
   size_t basis = 0, step1 = 0, proj = 0, offs = 0, mops = 0, mainv = 0;
-  size_t desc = 0, dist = 0, result = 0, act = 0;
+  size_t desc = 0, dist = 0, result = 0, traj = 0, act = 0;
   size_t p = 0, zs = 0, rc = 0, sess = 0, xiout = 0;
   size_t tr_p = 0, tr_rc = 0, tr_idx = 0, tr_dist = 0;
   size_t dec_tab = 0, dec_act = 0, dec_seg = 0;  // decoder sampler
   size_t total() const {
     size_t s = 0;
-    for (size_t b : {basis, step1, proj, offs, mops, mainv, desc, dist, result, act, p, zs, rc, sess, xiout,
+    for (size_t b : {basis, step1, proj, offs, mops, mainv, desc, dist, result, traj, act, p, zs, rc, sess, xiout,
                      tr_p, tr_rc, tr_idx, tr_dist, dec_tab, dec_act, dec_seg})
       s += (b + 255) & ~(size_t)255;
     return s;
@@ -173,6 +173,13 @@ size_t dec_piece(int i) {
 // 16-row blocks (the matrix-core layout stores the last partial block whole).
 int dec_chunk(int64_t rows) { return (int)((std::min<int64_t>(rows, kDecChunk) + 15) / 16 * 16); }
 
+// Instants per slot of the returned-trajectory buffer: the longest horizon.
+int traj_stride(const plan_config &c) {
+  int t = 0;
+  for (int i = 0; i < c.n_T; ++i) t = std::max(t, (int)c.T_set[i]);
+  return t;
+}
+
 Layout compute_layout(const plan_config &c) {
   Layout L;
   const size_t S = (size_t)c.max_requests, N = (size_t)c.max_N, R = (size_t)budget_rows(c);
@@ -187,6 +194,7 @@ Layout compute_layout(const plan_config &c) {
   L.desc = S * sizeof(ReqDesc);
   L.dist = S * sizeof(DistState);
   L.result = S * sizeof(ResultRec);
+  L.traj = S * (size_t)traj_stride(c) * 2 * 8;
   L.act = (2 * S + 8) * 4;
   L.p = R * 8 * 4;
   L.zs = R * kZ * 4;
@@ -255,6 +263,7 @@ struct Pending {
 
 struct Resident {
   uint64_t ticket = 0;
+  uint64_t session_key = 0;  // the request's session_id (0: none)
   int slot = -1;
   int64_t row_off = 0;
   int N = 0, T = 0;
@@ -295,6 +304,8 @@ struct plan_handle {
   ReqDesc *desc = nullptr;
   DistState *dist = nullptr;
   ResultRec *result = nullptr;
+  double *traj = nullptr;  // [slot][traj_stride][2] positions of the returned trajectory
+  int traj_T = 0;          // traj_stride of the config
   int32_t *act_slots = nullptr, *blk_prefix = nullptr;
   float *p = nullptr, *zs = nullptr, *resid = nullptr, *cost = nullptr;
   double *sess = nullptr;
@@ -314,6 +325,7 @@ struct plan_handle {
   std::vector<hipEvent_t> sync_ev_free;  // events without timing, for retirement
   ResultRec *h_result = nullptr;
   DistState *h_dist = nullptr;
+  double *h_traj = nullptr;  // pinned mirror of traj
   // batch mode: staged requests in slots 0..staged-1
   int staged = 0;
   LaunchSet ls;
@@ -328,6 +340,7 @@ struct plan_handle {
   std::deque<Pending> queue;
   std::vector<Resident> resident;
   std::unordered_map<uint64_t, plan_result> done;
+  std::unordered_map<uint64_t, std::vector<double>> done_traj;  // positions of finished tickets (T x 2)
   uint64_t next_ticket = 1;
   // sessions
   std::unordered_map<uint64_t, int> sess_index;
@@ -519,6 +532,8 @@ SelArgs sel_args(plan_handle *h, int l_uniform) {
   a.cost = h->cost;
   a.dist = h->dist;
   a.result = h->result;
+  a.traj = h->traj;
+  a.traj_stride = h->traj_T;
   a.sess = h->sess;
   a.tr_p = h->tr_p;
   a.tr_r = h->tr_r;
@@ -759,6 +774,12 @@ plan_status stage_impl(plan_handle *h, const plan_request *reqs, int n, int firs
       h->err = "request " + std::to_string(first + i) + ": " + why;
       continue;
     }
+    if (d.N > h->rows) {
+      // larger than the whole sample budget: this request fails alone
+      h->staged_status[i] = PLAN_E_NOMEM;
+      h->err = "request " + std::to_string(first + i) + ": N larger than the sample budget";
+      continue;
+    }
     if (row + d.N > h->rows) return fail(h, PLAN_E_NOMEM, "batch exceeds the sample budget");
     const uint64_t sk = reqs[i].session_id;
     resolve_session(h, sk, d, sk != 0 && last_of_session[sk] == i);
@@ -833,8 +854,14 @@ plan_status launch_impl(plan_handle *h) {
   return st;
 }
 
-void fill_result(plan_result &o, const ResultRec &R, const DistState &ds, double latency) {
+// Fill o from the slot's records; the caller's trajectory buffer (o.traj_xy,
+// nullable) keeps its pointer and receives the T x 2 positions traj.
+void fill_result(plan_result &o, const ResultRec &R, const DistState &ds, double latency, const double *traj,
+                 int T) {
+  double *traj_xy = o.traj_xy;
   std::memset(&o, 0, sizeof(o));
+  o.traj_xy = traj_xy;
+  if (traj_xy && traj && R.status == 0) std::memcpy(traj_xy, traj, sizeof(double) * 2 * T);
   o.status = R.status;
   o.flags = R.flags;
   o.best_index = R.best;
@@ -855,18 +882,22 @@ plan_status collect_impl(plan_handle *h, plan_result *out, double elapsed) {
                               h->stream));
     HIP_TRY(h, hipMemcpyAsync(h->h_dist, h->dist, sizeof(DistState) * h->staged, hipMemcpyDeviceToHost,
                               h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->h_traj, h->traj, sizeof(double) * 2 * h->traj_T * h->staged,
+                              hipMemcpyDeviceToHost, h->stream));
   }
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   plan_status worst = PLAN_OK;
   for (int i = 0; i < h->staged_total; ++i) {
+    double *traj_xy = out[i].traj_xy;
     std::memset(&out[i], 0, sizeof(plan_result));
+    out[i].traj_xy = traj_xy;
     out[i].status = h->staged_status[i];
     out[i].best_index = -1;
     if (out[i].status != PLAN_OK) worst = std::min(worst, (plan_status)out[i].status);
   }
   for (int s = 0; s < h->staged; ++s) {
     plan_result &o = out[h->staged_req[s]];
-    fill_result(o, h->h_result[s], h->h_dist[s], elapsed);
+    fill_result(o, h->h_result[s], h->h_dist[s], elapsed, h->h_traj + (size_t)s * 2 * h->traj_T, h->h_desc[s].T);
     if (o.status != 0) worst = std::min(worst, (plan_status)o.status);
     else if (h->h_desc[s].session_wb >= 0) h->sess_valid[h->h_desc[s].session_wb] = 1;
   }
@@ -916,10 +947,12 @@ plan_status retire_done(plan_handle *h) {
     }
     if (q != hipSuccess) return hip_fail(h, q, "served result copy");
     const Resident rs = h->retiring[i].rs;
-    plan_result o;
+    plan_result o{};
     fill_result(o, h->h_result[rs.slot], h->h_dist[rs.slot],
-                std::chrono::duration<double>(Clock::now() - rs.submit).count());
+                std::chrono::duration<double>(Clock::now() - rs.submit).count(), nullptr, 0);
     if (o.status == 0 && rs.session_wb >= 0) h->sess_valid[rs.session_wb] = 1;
+    const double *tr = h->h_traj + (size_t)rs.slot * 2 * h->traj_T;
+    h->done_traj[rs.ticket].assign(tr, tr + 2 * rs.T);
     h->done[rs.ticket] = o;
     h->slot_busy[rs.slot] = 0;
     give_rows(h, rs.row_off, rs.N);
@@ -935,6 +968,15 @@ void admit_queued(plan_handle *h, std::vector<int> &admitted) {
   const int S = h->cfg.max_requests;
   while (!h->queue.empty()) {
     Pending &pd = h->queue.front();
+    // a request of a session waits (and the queue behind it) until the
+    // session's request in flight has retired, so it starts from that
+    // request's final distribution, whatever the timing
+    if (pd.req.session_id != 0) {
+      bool busy = false;
+      for (const auto &rs : h->resident) busy |= rs.session_key == pd.req.session_id;
+      for (const auto &rt : h->retiring) busy |= rt.rs.session_key == pd.req.session_id;
+      if (busy) break;
+    }
     int slot = -1;
     for (int s = 0; s < S; ++s)
       if (!h->slot_busy[s]) {
@@ -952,6 +994,7 @@ void admit_queued(plan_handle *h, std::vector<int> &admitted) {
     h->slot_busy[slot] = 1;
     Resident rs;
     rs.ticket = pd.ticket;
+    rs.session_key = r.session_id;
     rs.slot = slot;
     rs.row_off = off;
     rs.N = r.N;
@@ -988,6 +1031,7 @@ void free_handle(plan_handle *h) {
   for (hipEvent_t e : h->sync_ev_free) (void)hipEventDestroy(e);
   if (h->h_result) (void)hipHostFree(h->h_result);
   if (h->h_dist) (void)hipHostFree(h->h_dist);
+  if (h->h_traj) (void)hipHostFree(h->h_traj);
   delete h;
 }
 
@@ -1043,6 +1087,15 @@ size_t plan_workspace_bytes(const plan_config *cfg) {
 }
 
 const char *plan_last_error(const plan_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+plan_status plan_elite_sizes(const plan_config *cfg, int32_t N, int32_t *n_ces, int32_t *n_es) {
+  if (!cfg || !n_ces || !n_es || N < 1 || N > cfg->max_N) return PLAN_E_INVALID;
+  int n, q;
+  elite_sizes(*cfg, N, n, q);
+  *n_ces = n;
+  *n_es = q;
+  return PLAN_OK;
+}
 
 plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   if (!cfg || !out) {
@@ -1115,6 +1168,8 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->desc = (ReqDesc *)h->mem.take(L.desc);
   h->dist = (DistState *)h->mem.take(L.dist);
   h->result = (ResultRec *)h->mem.take(L.result);
+  h->traj_T = traj_stride(c);
+  h->traj = (double *)h->mem.take(L.traj);
   h->act_slots = (int32_t *)h->mem.take(L.act);
   h->blk_prefix = h->act_slots + S;
   h->p = (float *)h->mem.take(L.p);
@@ -1183,6 +1238,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->h_seg = h->h_seg_ring[0];
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_result, sizeof(ResultRec) * S);
   if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_dist, sizeof(DistState) * S);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_traj, L.traj);
   // ---- upload tables
   if (e == hipSuccess) {
     std::vector<float> basis_all;
@@ -1270,9 +1326,19 @@ plan_status plan_solve_batch(plan_handle *h, const plan_request *reqs, int32_t n
     const auto t0 = Clock::now();
     plan_status st = stage_impl(h, reqs + first, m, first);
     if (st == PLAN_OK) st = launch_impl(h);
-    if (st != PLAN_OK) return st;
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "solve");
+    hipError_t e = st == PLAN_OK ? hipStreamSynchronize(h->stream) : hipSuccess;
+    if (e != hipSuccess) st = hip_fail(h, e, "solve");
+    if (st != PLAN_OK) {
+      // this group and the ones after it did not run: each says why
+      for (int i = first; i < n; ++i) {
+        double *traj_xy = out[i].traj_xy;
+        std::memset(&out[i], 0, sizeof(plan_result));
+        out[i].traj_xy = traj_xy;
+        out[i].status = st;
+        out[i].best_index = -1;
+      }
+      return st;
+    }
     const double el = std::chrono::duration<double>(Clock::now() - t0).count();
     st = collect_impl(h, out + first, el);
     worst = std::min(worst, st);
@@ -1390,6 +1456,7 @@ plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const doub
   r.session_id = 0;
   ReqDesc &d = h->h_desc[0];
   if (const char *why = check_request(h, r, d)) return fail(h, PLAN_E_INVALID, why);
+  if (N > h->rows) return fail(h, PLAN_E_NOMEM, "N larger than the sample budget");
   if (!finite_all(p, 8 * N)) return fail(h, PLAN_E_INVALID, "non-finite p");
   d.init_mode = kInitForced;
   d.row_off = 0;
@@ -1544,6 +1611,8 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
                                 hipMemcpyDeviceToHost, h->stream));
       HIP_TRY(h, hipMemcpyAsync(h->h_dist + rs.slot, h->dist + rs.slot, sizeof(DistState), hipMemcpyDeviceToHost,
                                 h->stream));
+      HIP_TRY(h, hipMemcpyAsync(h->h_traj + (size_t)rs.slot * 2 * h->traj_T, h->traj + (size_t)rs.slot * 2 * h->traj_T,
+                                sizeof(double) * 2 * rs.T, hipMemcpyDeviceToHost, h->stream));
       Retiring rt;
       rt.rs = rs;
       if (!h->sync_ev_free.empty()) {
@@ -1568,7 +1637,13 @@ plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out) {
   if (st != PLAN_OK) return st;
   auto it = h->done.find(ticket);
   if (it != h->done.end()) {
+    double *traj_xy = out->traj_xy;
     *out = it->second;
+    out->traj_xy = traj_xy;
+    auto tt = h->done_traj.find(ticket);
+    if (traj_xy && tt != h->done_traj.end() && out->status == 0)
+      std::memcpy(traj_xy, tt->second.data(), sizeof(double) * tt->second.size());
+    if (tt != h->done_traj.end()) h->done_traj.erase(tt);
     h->done.erase(it);
     return PLAN_OK;
   }

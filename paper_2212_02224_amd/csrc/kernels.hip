@@ -39,6 +39,7 @@
 
 #include "plan_internal.h"
 #include "rng.h"
+#include "traj64.h"
 
 namespace plan {
 
@@ -558,19 +559,28 @@ __device__ void stage_road(const ReqDesc &D, float4 *s_road) {
 
 // Sampling distribution of upper iteration l into LDS (Gaussian draws only):
 // the request's or the session's at iteration 0 (factored here), else the
-// one the previous update left with its factor.
+// one the previous update left with its factor. At iteration 0 the first
+// workgroup of the request (first) also copies the prior it read into the
+// slot's own state, where the update of that iteration reads it: the session
+// store is shared, and another request of the same session may write it
+// while this request's update runs.
 __device__ void load_distribution(const LowerArgs &A, const ReqDesc &D, const MethodParams &P, int slot, int l,
-                                  double *s_mu, double *s_chol) {
+                                  bool first, double *s_mu, double *s_chol) {
   if (l == 0) {
+    const double *m0 = D.mu0, *s0 = D.sigma0;
+    if (D.init_mode == kInitSession) {
+      m0 = A.sess + (size_t)D.session * 72;
+      s0 = m0 + 8;
+    }
     if (threadIdx.x == 0) {
-      const double *m0 = D.mu0, *s0 = D.sigma0;
-      if (D.init_mode == kInitSession) {
-        m0 = A.sess + (size_t)D.session * 72;
-        s0 = m0 + 8;
-      }
       for (int a = 0; a < 8; ++a) s_mu[a] = m0[a];
       if (!chol8(s0, P.cov_jitter, s_chol))
         for (int i = 0; i < 64; ++i) s_chol[i] = 0.0;  // reported by the update
+    }
+    if (first && threadIdx.x < 72) {
+      DistState &Sd = A.dist[slot];
+      if (threadIdx.x < 8) Sd.mu[threadIdx.x] = m0[threadIdx.x];
+      else Sd.sigma[threadIdx.x - 8] = s0[threadIdx.x - 8];
     }
   } else if (threadIdx.x < 72) {
     const DistState &Sd = A.dist[slot];
@@ -746,7 +756,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   // samples in the rows already: the caller's, or the decoder sampler's
   const bool forced = D.init_mode == kInitForced || decoded_start(D, P, l);
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
-  if (!forced && !structured) load_distribution(A, D, P, bi.x, l, s_mu, s_chol);
+  if (!forced && !structured) load_distribution(A, D, P, bi.x, l, bi.y == 0, s_mu, s_chol);
   const Scal S = make_scal(D, P);
 
   // Basis rows of this lane's instants and the fixed part of the trajectory.
@@ -1039,7 +1049,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   if constexpr (ROAD) stage_road(D, s_road);
   const bool forced = D.init_mode == kInitForced || decoded_start(D, P, l);
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
-  if (!forced && !structured) load_distribution(A, D, P, slot, l, s_mu, s_chol);
+  if (!forced && !structured) load_distribution(A, D, P, slot, l, bi.y == 0, s_mu, s_chol);
   const Scal S = make_scal(D, P);
   {
     // fixed part per instant: (x, xd + vx0, xdd, 0), (y, yd, ydd, 0); zero
@@ -1661,13 +1671,10 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       if (D.init_mode == kInitStructured) {
         structured_moments(P, s_mu, s_sig);
       } else {
-        const double *m0 = D.mu0, *s0 = D.sigma0;
-        if (D.init_mode == kInitSession) {
-          m0 = A.sess + (size_t)D.session * 72;
-          s0 = m0 + 8;
-        }
-        for (int a = 0; a < 8; ++a) s_mu[a] = m0[a];
-        for (int i = 0; i < 64; ++i) s_sig[i] = s0[i];
+        // the prior the lower level drew from, copied into the slot's state
+        // by its first workgroup (a session's store may change meanwhile)
+        for (int a = 0; a < 8; ++a) s_mu[a] = Sd.mu[a];
+        for (int i = 0; i < 64; ++i) s_sig[i] = Sd.sigma[i];
         double Lt[64];
         ok = chol8(s_sig, P.cov_jitter, Lt) ? 1 : 0;
       }
@@ -1816,32 +1823,61 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       if (A.l_uniform < 0) D.cur_iter = l + 1;
     }
   }
-  if (last && tid >= 64 && tid < 128) {
+  if (last) {
     // Return: lowest c_u + r in the final EliteSet (ties: lower index),
-    // written by wave 1 while wave 0 factors the covariance.
-    const int t = tid - 64;
-    const uint32_t b = jbest;
-    const double n10 = 10.0, tf = P.t_f;
-    const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
-    const double ax0 = D.ego[4], ay0 = D.ego[5];
-    const float *zb = A.zs + (base + b) * kZ;
-    if (t < 8) R.p[t] = (double)p[(size_t)b * 8 + t];
-    if (t < 8) R.xi[3 + t] = (double)zb[t] + x0 + vx0 * tf * (double)(3 + t) / n10;
-    if (t >= 8 && t < 14) R.xi[14 + (t - 8)] = (double)zb[t];
-    if (t == 14) R.xi[20] = R.xi[21] = (double)zb[14];
-    if (t == 15) {
-      R.xi[0] = x0;
-      R.xi[1] = x0 + vx0 * tf / n10;
-      R.xi[2] = x0 + 2.0 * vx0 * tf / n10 + ax0 * tf * tf / (n10 * (n10 - 1.0));
-      R.xi[11] = y0;
-      R.xi[12] = y0 + vy0 * tf / n10;
-      R.xi[13] = y0 + 2.0 * vy0 * tf / n10 + ay0 * tf * tf / (n10 * (n10 - 1.0));
+    // written by waves 1-3 while wave 0 factors the covariance. The returned
+    // trajectory's residual over Table ineq_list and its upper cost are
+    // evaluated again in FP64 (instant k on thread 64 + k, k + 192, ...),
+    // summed per wave in lane order and then over the waves in wave order;
+    // they set the result's residual, cost and infeasible flag, and the
+    // trajectory's positions at every instant are stored.
+    __shared__ double s_rc64[3][2];
+    if (tid >= 64) {
+      const int t = tid - 64;
+      const uint32_t b = jbest;
+      const double n10 = 10.0, tf = P.t_f;
+      const double x0 = D.ego[0], y0 = D.ego[1], vx0 = D.ego[2], vy0 = D.ego[3];
+      const double ax0 = D.ego[4], ay0 = D.ego[5];
+      const float *zb = A.zs + (base + b) * kZ;
+      double xi[22];
+      xi[0] = x0;
+      xi[1] = x0 + vx0 * tf / n10;
+      xi[2] = x0 + 2.0 * vx0 * tf / n10 + ax0 * tf * tf / (n10 * (n10 - 1.0));
+      xi[11] = y0;
+      xi[12] = y0 + vy0 * tf / n10;
+      xi[13] = y0 + 2.0 * vy0 * tf / n10 + ay0 * tf * tf / (n10 * (n10 - 1.0));
+#pragma unroll
+      for (int c = 0; c < 8; ++c) xi[3 + c] = (double)zb[c] + x0 + vx0 * tf * (double)(3 + c) / n10;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) xi[14 + c] = (double)zb[8 + c];
+      xi[20] = xi[21] = (double)zb[14];
+      if (t < 22) R.xi[t] = xi[t];
+      if (t < 8) R.p[t] = (double)p[(size_t)b * 8 + t];
+      double rr = 0.0, cc = 0.0;
+      for (int k = t; k < D.T; k += kSelBlock - kWave) {
+        double rk, ck, xk, yk;
+        residual_cost64(D, P, xi, k, rk, ck, xk, yk);
+        rr += rk;
+        cc += ck;
+        if (A.traj) {
+          A.traj[((size_t)slot * A.traj_stride + k) * 2] = xk;
+          A.traj[((size_t)slot * A.traj_stride + k) * 2 + 1] = yk;
+        }
+      }
+      rr = wave_sum_d(rr);
+      cc = wave_sum_d(cc);
+      if ((tid & 63) == 0) {
+        s_rc64[(tid >> 6) - 1][0] = rr;
+        s_rc64[(tid >> 6) - 1][1] = cc;
+      }
     }
-    if (t == 16) {
-      R.best = (int32_t)b;
-      R.cost_upper = (double)cu[b];
-      R.residual = (double)r[b];
-      uint32_t fl = (r[b] > 0.f) ? PLAN_F_INFEASIBLE : 0u;
+    __syncthreads();
+    if (tid == 64) {
+      const double r64 = (s_rc64[0][0] + s_rc64[1][0]) + s_rc64[2][0];
+      R.best = (int32_t)jbest;
+      R.cost_upper = (s_rc64[0][1] + s_rc64[1][1]) + s_rc64[2][1];
+      R.residual = r64;
+      uint32_t fl = (r64 > 0.0) ? PLAN_F_INFEASIBLE : 0u;
       if (D.init_mode == kInitSession || D.init_mode == kInitGiven) fl |= PLAN_F_WARM;
       R.flags = fl;
     }

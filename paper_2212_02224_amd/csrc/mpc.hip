@@ -11,30 +11,9 @@
 #include <stdint.h>
 
 #include "plan_internal.h"
+#include "traj64.h"
 
 namespace plan {
-
-// Position, velocity and acceleration of one axis at tau = t / t_f from its
-// 11 Bernstein coefficients (FP64): the derivatives are Bernstein sums of
-// degree 9 and 8 over the forward differences of the coefficients.
-__device__ void bernstein_state(const double *c, double tau, double t_f, double &pos, double &vel, double &acc) {
-  const double b10[11] = {1, 10, 45, 120, 210, 252, 210, 120, 45, 10, 1};
-  const double b9[10] = {1, 9, 36, 84, 126, 126, 84, 36, 9, 1};
-  const double b8[9] = {1, 8, 28, 56, 70, 56, 28, 8, 1};
-  double tp[11], up[11];
-  tp[0] = up[0] = 1.0;
-  for (int i = 1; i <= 10; ++i) {
-    tp[i] = tp[i - 1] * tau;
-    up[i] = up[i - 1] * (1.0 - tau);
-  }
-  double p = 0.0, v = 0.0, a = 0.0;
-  for (int i = 0; i <= 10; ++i) p += b10[i] * tp[i] * up[10 - i] * c[i];
-  for (int i = 0; i <= 9; ++i) v += b9[i] * tp[i] * up[9 - i] * (c[i + 1] - c[i]);
-  for (int i = 0; i <= 8; ++i) a += b8[i] * tp[i] * up[8 - i] * (c[i + 2] - 2.0 * c[i + 1] + c[i]);
-  pos = p;
-  vel = 10.0 * v / t_f;
-  acc = 90.0 * a / (t_f * t_f);
-}
 
 // Scene time of absolute instant m of an episode (cycle c starts at
 // m = c n_exec): m t_f / (T - 1), one rounding per operation.

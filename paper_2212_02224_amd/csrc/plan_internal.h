@@ -83,7 +83,8 @@ struct DistState {
   double chol[64];
 };
 
-// Result record of one slot (FP64).
+// Result record of one slot (FP64). cost_upper and residual are those of
+// the returned trajectory xi, evaluated in FP64.
 struct ResultRec {
   int32_t status;
   uint32_t flags;
@@ -119,7 +120,7 @@ struct LowerArgs {
   const float *step1;        // per-T: S (16x8) then R (16x4)
   const float *proj;         // per-(T,M): A^-1 (16x16) then D (16)
   float *p;                  // row pool [rows][8] (written unless forced)
-  const DistState *dist;     // slot distribution (iterations >= 1)
+  DistState *dist;           // slot distribution (iterations >= 1; written at iteration 0, see below)
   const double *sess;        // session store (iteration 0 of a warm start)
   float *zs;                 // row pool [rows][16] free coefficients
   float *resid;              // row pool [rows]
@@ -143,6 +144,8 @@ struct SelArgs {
   const float *cost;
   DistState *dist;
   ResultRec *result;
+  double *traj;              // [slot][traj_stride][2]: positions of the returned trajectory (FP64)
+  int32_t traj_stride;       // instants per slot of traj (the longest horizon of the config)
   double *sess;              // session store [n_sess][72]: mu then Sigma
   // optional trace (per slot and iteration; max_N rows per slot)
   float *tr_p;               // [slot][L][max_N][8]

@@ -1,32 +1,115 @@
-"""Conditioning of the projection, shared by the GPU parity tests.
+"""Sensitivity-scaled parity bars, shared by the GPU parity tests.
 
 Alg. 2 is not a continuous function of its input everywhere: the (alpha, d)
 step takes the direction atan2(dy/b, dx/a) from a neighbour's centre to the
 trajectory, which turns through pi as the trajectory passes the centre, and
 the velocity step the direction atan2(ydot, xdot), which is undefined at
-rest. Near those points an FP32 run cannot follow the FP64 oracle, however it
-is implemented. The oracle itself shows it: its own answer moves far more
-than its input when the input is perturbed by a rounding-sized amount.
+rest. Near those points no FP32 run can follow the FP64 oracle closely,
+however it is implemented; the oracle shows it on its own, its answer moving
+far more than its input when the input moves by a rounding-sized amount.
 
-ill_conditioned() flags the samples whose FP64 projection moves by more than
-`limit` (2e-5 m, i.e. 20 times) when xi_bar is perturbed by `noise` (1e-6 m,
-about the FP32 rounding of the coefficients, seeded), or whose projection
-iterates pass below the speed floor v_eps. The parity tests count those
-samples, print their largest error, and hold every other sample to the full
-bar; a flagged sample that changes an elite set is treated like a near tie.
+So every sample j is held to a bar scaled by the oracle's own spread there
+(reading Z39). Spread: the free coefficients of xi_bar are perturbed by their
+FP32 rounding magnitude (one unit in the last place of FP32 times a standard
+normal, each coefficient in the frame the kernels carry it: x relative to
+the line x0 + vx0 t, y as it is), the oracle projects again, and m_j is the
+largest change over SEEDS perturbations of the position (max over t_k), and
+likewise of r_j and c_u,j. The bar is
+
+    error_j <= base + C m_j,   C = 2 sqrt(K),
+
+with base the bar of a well-conditioned sample (FP32: 1e-4 m, r within
+1e-3 + 1e-4 r, c_u within 1e-4 relative; FP16 split ten times that). C: the
+GPU rounds at each of the K projection iterations, not only its input, and
+K independent roundings of the input's size add up to about sqrt(K) of them;
+the factor 2 covers draws beyond the largest of the SEEDS perturbations.
+Every sample of every case is held to its bar. A sample whose bar is
+loosened by more than the base itself (C m_j > base) is "flagged": the tests
+count and print the flagged samples with their largest error, and bound
+their number per case to a tenth of its samples (MAX_FLAGGED; at least one
+in cases of fewer than ten), with a stated exception for the fixed grid,
+whose lane-centred samples follow neighbours' centre lines.
 """
 import numpy as np
 
+SEEDS = (1, 2, 3, 4)
+MAX_FLAGGED = 0.1
 
-def ill_conditioned(orc, par, sc, xi_bar, xi_star, p=None, noise=1e-6, limit=2e-5, seed=1):
+
+def bar_factor(par) -> float:
+    return 2.0 * float(np.sqrt(par.K))
+
+
+def _free_mask():
+    m = np.zeros(22, bool)
+    m[3:11] = True   # c3..c10 of x
+    m[14:22] = True  # c3..c10 of y (c9 = c10 move together)
+    return m
+
+
+def perturbed(par, ego, xi_bar, seed):
+    """xi_bar with each free coefficient moved by one FP32 ulp of its value
+    (in the kernels' frame) times a standard normal."""
     rng = np.random.default_rng(seed)
-    xb2 = xi_bar + noise * rng.standard_normal(xi_bar.shape)
-    xs2, it = orc.project(par, sc, xb2, return_iterates=True, p=p)
-    W, Wd, _ = orc.basis(par.T, par.t_f)
-    dx = (xs2[:, :11] - xi_star[:, :11]) @ W.T
-    dy = (xs2[:, 11:] - xi_star[:, 11:]) @ W.T
-    move = np.sqrt(dx ** 2 + dy ** 2).max(axis=1)
-    vx = np.einsum('jkc,tc->jkt', it[:, :, :11], Wd)
-    vy = np.einsum('jkc,tc->jkt', it[:, :, 11:], Wd)
-    slow = np.hypot(vx, vy).min(axis=(1, 2)) < par.v_eps
-    return (move > limit) | slow
+    ref = np.zeros(22)
+    ref[:11] = ego[0] + ego[2] * par.t_f * np.arange(11) / 10.0
+    rel = np.abs(xi_bar - ref).astype(np.float32)
+    ulp = np.spacing(rel).astype(np.float64)
+    d = ulp * rng.standard_normal(xi_bar.shape) * _free_mask()
+    d[:, 21] = d[:, 20]
+    return xi_bar + d
+
+
+def positions(orc, par, xi):
+    W, _, _ = orc.basis(par.T, par.t_f)
+    return xi[:, :11] @ W.T, xi[:, 11:] @ W.T
+
+
+class Spread:
+    """The oracle's own spread per sample (pos in m, r, cu) under FP32-sized
+    perturbations of xi_bar, and the bars it implies."""
+
+    def __init__(self, orc, par, sc, xi_bar, xi_star, p=None):
+        xi_bar = np.asarray(xi_bar, float).reshape(-1, 22)
+        xi_star = np.asarray(xi_star, float).reshape(-1, 22)
+        ego = np.asarray(sc.ego, float)
+        x0, y0 = positions(orc, par, xi_star)
+        r0, c0 = orc.residual_cost(par, sc, xi_star)
+        n = xi_bar.shape[0]
+        self.pos, self.r, self.cu = np.zeros(n), np.zeros(n), np.zeros(n)
+        for s in SEEDS:
+            x2 = orc.project(par, sc, perturbed(par, ego, xi_bar, s), p=p)
+            x1, y1 = positions(orc, par, x2)
+            self.pos = np.maximum(self.pos, np.sqrt((x1 - x0) ** 2 + (y1 - y0) ** 2).max(axis=1))
+            r2, c2 = orc.residual_cost(par, sc, x2)
+            self.r = np.maximum(self.r, np.abs(r2 - r0))
+            self.cu = np.maximum(self.cu, np.abs(c2 - c0))
+        self.C = bar_factor(par)
+
+    def pos_bar(self, base):
+        return base + self.C * self.pos
+
+    def r_bar(self, base):
+        return base + self.C * self.r
+
+    def cu_bar(self, base):
+        return base + self.C * self.cu
+
+    def flagged(self, base):
+        return self.C * self.pos > base
+
+
+def check_positions(tag, err, spread, base, max_flagged=MAX_FLAGGED):
+    """err_j <= base + C m_j for every sample; print the flagged count and
+    the largest errors; bound the flagged fraction."""
+    bar = spread.pos_bar(base)
+    fl = spread.flagged(base)
+    ok = ~fl
+    worst = int(np.argmax(err / bar))
+    print(f"   {tag}: position error max {err.max():.2e} m (unflagged {err[ok].max() if ok.any() else 0:.2e}, "
+          f"p99 {np.percentile(err, 99):.2e}); flagged {int(fl.sum())} of {err.size} (largest error there "
+          f"{err[fl].max() if fl.any() else 0:.2e} m, largest bar {bar.max():.2e} m); "
+          f"worst error/bar {err[worst] / bar[worst]:.2f} at sample {worst}", flush=True)
+    assert np.all(err <= bar), (worst, err[worst], bar[worst])
+    assert fl.sum() <= max(1, int(max_flagged * err.size)), fl.mean()
+    return fl

@@ -48,11 +48,11 @@ def test_struct_layout_matches_header(pl):
 #include <stddef.h>
 #include "plan.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(plan_config), sizeof(plan_request),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(plan_config), sizeof(plan_request),
          sizeof(plan_result), offsetof(plan_config, stream), offsetof(plan_request, first_iter),
          offsetof(plan_result, latency_s), sizeof(plan_mpc_log), offsetof(plan_mpc_log, status),
          offsetof(plan_request, road), offsetof(plan_request, observation), sizeof(plan_decoder),
-         offsetof(plan_decoder, bn_eps));
+         offsetof(plan_decoder, bn_eps), offsetof(plan_result, traj_xy));
   return 0;
 }
 '''
@@ -67,7 +67,8 @@ int main(void) {
     want = [C.sizeof(b.plan_config), C.sizeof(b.plan_request), C.sizeof(b.plan_result),
             b.plan_config.stream.offset, b.plan_request.first_iter.offset, b.plan_result.latency_s.offset,
             C.sizeof(b.plan_mpc_log), b.plan_mpc_log.status.offset, b.plan_request.road.offset,
-            b.plan_request.observation.offset, C.sizeof(b.plan_decoder), b.plan_decoder.bn_eps.offset]
+            b.plan_request.observation.offset, C.sizeof(b.plan_decoder), b.plan_decoder.bn_eps.offset,
+            b.plan_result.traj_xy.offset]
     assert got == want
 
 
@@ -105,10 +106,15 @@ def test_fp16_split_config_accepted(pl):
 
 
 def test_elite_sizes_match_oracle(pl, orc):
-    cfg = pl.plan_config_init()
+    """The library's sizes (plan_elite_sizes, no device needed) against the
+    oracle's, and its argument checks."""
+    cfg = pl.plan_config_init(max_N=4096)
     par = orc.default_params()
     for N in (1, 5, 64, 256, 512, 1000, 2048, 4096, 333):
         assert pl.elite_sizes(cfg, N) == orc.elite_sizes(par, N)
+    for N in (0, 4097):
+        with pytest.raises(pl.PlanError):
+            pl.elite_sizes(cfg, N)
 
 
 def test_workload_scenes_are_seeded(pl):

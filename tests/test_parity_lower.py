@@ -1,19 +1,20 @@
 """GPU parity of the lower level (Alg. 1 Steps 1-2 + residual/cost) against
 the FP64 oracle, teacher-forced: both sides get the oracle's samples p.
 
-Bar (FP32 path): every trajectory within 1e-4 m of the oracle at every
-instant of the horizon (max over t_k of the Euclidean position error);
-residual r within 1e-3 + 1e-4 r and upper cost c_u within 1e-4 relative.
-The positions compared are both evaluated in FP64 from the returned
-coefficients. Samples on which the FP64 projection is itself ill-conditioned
-(parity_common.ill_conditioned) are counted and reported, not held to the
-bar; they are at most a tenth of a case.
+Bar (FP32 path), per sample j (parity_common): every trajectory within
+1e-4 m + C m_j of the oracle at every instant of the horizon (max over t_k
+of the Euclidean position error), residual r within 1e-3 + 1e-4 r + C m_r,j
+and upper cost c_u within 1e-4 c_u + C m_c,j, where m is the oracle's own
+spread under FP32-sized perturbations of xi_bar and C = 2 sqrt(K). Step 1
+(xi_bar) is held to 1e-4 m flat. The positions compared are both evaluated
+in FP64 from the returned coefficients. At most a tenth of a case may be
+flagged (C m_j > 1e-4 m).
 """
 import numpy as np
 import pytest
 
 from paper_2212_02224_amd import workload
-from parity_common import ill_conditioned
+from parity_common import Spread, check_positions
 
 pytestmark = pytest.mark.gpu
 
@@ -37,16 +38,14 @@ def run_case(orc, pl, handle, par, req, p, tag):
     xb_g, xs_g, r_g, c_g = pl.plan_lower_solve(handle, req, p)
     e_bar = pos_err(orc, par.T, par.t_f, xb_g, xb_o)
     e_star = pos_err(orc, par.T, par.t_f, xs_g, xs_o)
-    ok = ~ill_conditioned(orc, par, sc, xb_o, xs_o)
+    sp = Spread(orc, par, sc, xb_o, xs_o)
     dr = np.abs(r_g - r_o)
-    print(f"   xi_bar err max {e_bar.max():.2e}  xi* err max {e_star[ok].max():.2e} "
-          f"p99 {np.percentile(e_star[ok], 99):.2e}  |dr| max {dr[ok].max():.2e}; ill-conditioned "
-          f"{int((~ok).sum())} (xi* err there {e_star[~ok].max() if (~ok).any() else 0:.2e})", flush=True)
-    assert ok.mean() >= 0.9
+    dc = np.abs(c_g - c_o)
+    print(f"   xi_bar err max {e_bar.max():.2e}  |dr| max {dr.max():.2e}", flush=True)
+    check_positions("xi*", e_star, sp, POS_TOL)
     assert e_bar.max() <= POS_TOL, e_bar.max()
-    assert e_star[ok].max() <= POS_TOL, (e_star[ok].max(), int(np.argmax(np.where(ok, e_star, 0))))
-    assert np.all(dr[ok] <= 1e-3 + 1e-4 * np.abs(r_o[ok])), dr[ok].max()
-    assert np.all(np.abs(c_g - c_o)[ok] <= 1e-4 * np.abs(c_o[ok]) + 1e-6), np.abs(c_g - c_o)[ok].max()
+    assert np.all(dr <= sp.r_bar(1e-3 + 1e-4 * np.abs(r_o))), dr.max()
+    assert np.all(dc <= sp.cu_bar(1e-4 * np.abs(c_o) + 1e-6)), dc.max()
     # boundary conditions hold exactly in the returned coefficients
     W, Wd, Wdd = orc.basis(par.T, par.t_f)
     ego = np.asarray(req.ego, float)

@@ -2,9 +2,11 @@
 FP16 matrix-core products with FP32 accumulation, every operand split into
 high and low FP16 halves) against the FP64 oracle.
 
-Bar for reduced precision: every trajectory within 1e-3 m of the oracle at
-every instant (max over t_k of the Euclidean position error); residual r
-within 1e-2 + 1e-3 r and upper cost c_u within 1e-3 relative. The measured
+Bar for reduced precision, per sample j (parity_common): every trajectory
+within 1e-3 m + C m_j of the oracle at every instant (max over t_k of the
+Euclidean position error); residual r within 1e-2 + 1e-3 r + C m_r,j and
+upper cost c_u within 1e-3 c_u + C m_c,j, with m the oracle's own spread
+under FP32-sized perturbations of xi_bar and C = 2 sqrt(K). The measured
 errors are printed per case (they are near the FP32 path's, since the split
 keeps about 22 significant bits per operand).
 """
@@ -12,7 +14,7 @@ import numpy as np
 import pytest
 
 from paper_2212_02224_amd import workload
-from parity_common import ill_conditioned
+from parity_common import Spread, check_positions
 
 pytestmark = pytest.mark.gpu
 
@@ -49,18 +51,15 @@ def run_case(orc, pl, handle, par, req, p, tag):
     xb_g, xs_g, r_g, c_g = pl.plan_lower_solve(handle, req, p)
     e_bar = pos_err(orc, par.T, par.t_f, xb_g, xb_o)
     e_star = pos_err(orc, par.T, par.t_f, xs_g, xs_o)
-    ok = ~ill_conditioned(orc, par, sc, xb_o, xs_o)
+    sp = Spread(orc, par, sc, xb_o, xs_o)
     dr = np.abs(r_g - r_o)
-    dc = np.abs(c_g - c_o) / np.maximum(np.abs(c_o), 1e-12)
-    print(f"   xi_bar err max {e_bar.max():.2e}  xi* err max {e_star[ok].max():.2e} "
-          f"p50 {np.median(e_star[ok]):.2e} p99 {np.percentile(e_star[ok], 99):.2e}  |dr| max {dr[ok].max():.2e} "
-          f"|dc|/c max {dc[ok].max():.2e}; ill-conditioned {int((~ok).sum())} "
-          f"(xi* err there {e_star[~ok].max() if (~ok).any() else 0:.2e})", flush=True)
-    assert ok.mean() >= 0.9
+    dc = np.abs(c_g - c_o)
+    print(f"   xi_bar err max {e_bar.max():.2e}  xi* err p50 {np.median(e_star):.2e}  |dr| max {dr.max():.2e} "
+          f"|dc|/c max {np.max(dc / np.maximum(np.abs(c_o), 1e-12)):.2e}", flush=True)
+    check_positions("xi*", e_star, sp, POS_TOL)
     assert e_bar.max() <= 1e-4, e_bar.max()  # Step 1 is FP32 in both modes
-    assert e_star[ok].max() <= POS_TOL, (e_star[ok].max(), int(np.argmax(np.where(ok, e_star, 0))))
-    assert np.all(dr[ok] <= 1e-2 + 1e-3 * np.abs(r_o[ok])), dr[ok].max()
-    assert np.all(np.abs(c_g - c_o)[ok] <= 1e-3 * np.abs(c_o[ok]) + 1e-4), np.abs(c_g - c_o)[ok].max()
+    assert np.all(dr <= sp.r_bar(1e-2 + 1e-3 * np.abs(r_o))), dr.max()
+    assert np.all(dc <= sp.cu_bar(1e-3 * np.abs(c_o) + 1e-4)), dc.max()
     W, Wd, _ = orc.basis(par.T, par.t_f)
     ego = np.asarray(req.ego, float)
     assert np.allclose(xs_g[:, :11] @ W[0], ego[0], atol=1e-9)

@@ -8,22 +8,23 @@ iteration is therefore checked teacher-forced from the oracle: the GPU gets
 the oracle's distribution before iteration l (and the same sample-stream
 index), and must reproduce
   * the samples p (FP32 Box-Muller vs FP64: |dp| <= 2e-5 + 1e-6 |p|),
-  * r and c_u of every sample (lower-level bars; samples on which the FP64
-    projection is itself ill-conditioned, parity_common.ill_conditioned, are
-    counted and reported instead),
-  * the ConstraintEliteSet and EliteSet, up to swaps between samples whose
-    oracle keys are within the key tolerance of the set's boundary, or
-    swaps of ill-conditioned samples (near ties; counted and reported),
+  * r and c_u of every sample, each within the lower-level bar plus C times
+    the oracle's own spread at that sample (parity_common; at most a tenth
+    of the samples flagged, a quarter on the fixed grid),
+  * the ConstraintEliteSet and EliteSet, up to swaps of members whose oracle
+    keys are within the two members' key tolerances of each other (near
+    ties; counted and reported),
   * mu and Sigma after the update, within the bound that the cost tolerance
-    implies through the weights (derived below),
-  * the returned best sample.
+    implies through the weights (derived below), and the returned best
+    sample (position bar plus C times its spread), at every iteration whose
+    sets match, and at least one iteration per case.
 Inputs flow only from the oracle to the GPU, never back.
 """
 import numpy as np
 import pytest
 
 from paper_2212_02224_amd import workload
-from parity_common import ill_conditioned
+from parity_common import Spread
 
 pytestmark = pytest.mark.gpu
 
@@ -43,24 +44,28 @@ def c_tol(c, scale=1.0):
     return scale * (1e-4 * np.abs(c) + 1e-6)
 
 
-def set_check(name, gpu_idx, orc_idx, orc_key, tol_of_key, exempt=None):
-    """Sets equal up to swaps of near-tied members (or of exempt samples,
-    see slow_samples); returns the swap count."""
+def set_check(name, gpu_idx, orc_idx, orc_key, tol):
+    """Sets equal up to swaps of near-tied members: every member of the
+    symmetric difference has an oracle key within its own tolerance plus the
+    largest tolerance among the swapped members and the boundary member, of
+    the set's boundary key (tol: per-sample key tolerance). Returns the swap
+    count."""
     g, o = set(map(int, gpu_idx)), set(map(int, orc_idx))
     if g == o:
         return 0
-    boundary = np.max(orc_key[list(o)])
+    ol = list(o)
+    jb = ol[int(np.argmax(orc_key[ol]))]
+    boundary = orc_key[jb]
     diff = g.symmetric_difference(o)
+    t_pair = max(tol[jb], max(tol[j] for j in diff))
     for j in diff:
-        if exempt is not None and exempt[j]:
-            continue
-        assert abs(orc_key[j] - boundary) <= 2 * tol_of_key(boundary) + 2 * tol_of_key(orc_key[j]), \
-            f"{name}: sample {j} key {orc_key[j]} not near the boundary {boundary}"
+        assert abs(orc_key[j] - boundary) <= 2 * (tol[j] + t_pair), \
+            f"{name}: sample {j} key {orc_key[j]} (tol {tol[j]:.2e}) not near the boundary {boundary}"
     return len(diff) // 2
 
 
 def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e-4, behaviour=0, sampler=0,
-               L=None, road=False, decoder_seed=None, p0_tol=None, method=None):
+               L=None, road=False, decoder_seed=None, p0_tol=None, method=None, max_flagged=None):
     c = workload.CONFIGS[cfgid]
     N, T, M, K = c["N"], c["T"], c["M"], c["K"]
     L = c["L"] if L is None else L
@@ -89,7 +94,12 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
     h = pl.plan_create(cfg)
     if dec is not None:
         pl.plan_set_decoder(h, dec)
-    swaps_total = 0
+    swaps_total, compared = 0, 0
+    if max_flagged is None:
+        # the fixed grid's lane-centred samples ride along neighbours' centre
+        # lines, where the obstacle step's direction flips (about 15-18% of
+        # its 1000 samples flagged, measured on the oracle alone)
+        max_flagged = 0.25 if sampler == 1 else 0.1
     rt = lambda r: r_tol(r, tol_scale)  # noqa: E731
     ct = lambda c: c_tol(c, tol_scale)  # noqa: E731
     for l in range(L):
@@ -109,33 +119,37 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
             assert np.all(dp <= p0_tol(tr["p"][l])), dp.max()
         else:
             assert np.all(dp <= 2e-5 + 1e-6 * np.abs(tr["p"][l])), dp.max()
-        # residuals and costs
-        slow = ill_conditioned(orc, par, sc, tr["xi_bar"][l], tr["xi_star"][l], p=tr["p"][l])
-        ok = ~slow
+        # residuals and costs, each within its bar plus C times the oracle's spread
+        sp = Spread(orc, par, sc, tr["xi_bar"][l], tr["xi_star"][l], p=tr["p"][l])
+        fl = sp.flagged(pos_tol)
         dr = np.abs(g["r"][0] - tr["r"][l])
         dc = np.abs(g["cu"][0] - tr["cu"][l])
-        print(f"   |dp| {dp.max():.2e} |dr| {dr[ok].max():.2e} |dc|/c {np.max(dc[ok] / tr['cu'][l][ok]):.2e}; "
-              f"{int(slow.sum())} ill-conditioned samples (|dr| there {dr[slow].max() if slow.any() else 0:.2e})",
-              flush=True)
-        assert np.all(dr[ok] <= rt(tr["r"][l][ok])), dr[ok].max()
-        assert np.all(dc[ok] <= ct(tr["cu"][l][ok])), dc[ok].max()
+        tol_r = sp.r_bar(rt(tr["r"][l]))
+        tol_c = sp.cu_bar(ct(tr["cu"][l]))
+        print(f"   |dp| {dp.max():.2e} |dr| {dr.max():.2e} |dc|/c {np.max(dc / tr['cu'][l]):.2e}; flagged "
+              f"{int(fl.sum())} of {N} (|dr| there {dr[fl].max() if fl.any() else 0:.2e}, |dc| "
+              f"{dc[fl].max() if fl.any() else 0:.2e})", flush=True)
+        assert np.all(dr <= tol_r), dr.max()
+        assert np.all(dc <= tol_c), dc.max()
+        assert fl.sum() <= max(1, int(max_flagged * N)), fl.mean()
         # elite sets
-        sw = set_check("ConstraintEliteSet", g["ces"][0], tr["ces"][l], tr["r"][l], rt, slow)
+        sw = set_check("ConstraintEliteSet", g["ces"][0], tr["ces"][l], tr["r"][l], tol_r)
         c_full = tr["cu"][l] + tr["r"][l]
+        tol_full = tol_r + tol_c
         if sw == 0:
-            sw += set_check("EliteSet", g["es"][0], tr["es"][l], c_full, lambda c: ct(c) + rt(0.0), slow)
+            sw += set_check("EliteSet", g["es"][0], tr["es"][l], c_full, tol_full)
         else:
             # the EliteSets are drawn from different ConstraintEliteSets: a
-            # member common to both whose cost is clearly below both sets'
-            # boundaries must be in both
+            # member common to both that fewer than q members of either
+            # ConstraintEliteSet could undercut (within the two tolerances)
+            # must be in both EliteSets
             common = np.intersect1d(g["ces"][0], tr["ces"][l])
-            bg = c_full[g["es"][0]].max() if len(g["es"][0]) else 0.0
-            bo = c_full[tr["es"][l]].max()
-            lim = min(bg, bo)
-            sure = [j for j in common if c_full[j] < lim - 2 * (ct(lim) + rt(0.0)) and not slow[j]]
+            gc = np.union1d(g["ces"][0], tr["ces"][l])
+            sure = [int(j) for j in common
+                    if np.sum((c_full[gc] - tol_full[gc] <= c_full[j] + tol_full[j]) & (gc != j)) < q]
             assert set(sure) <= set(map(int, g["es"][0])) and set(sure) <= set(map(int, tr["es"][l]))
-            print(f"   ConstraintEliteSet differs by {sw} ill-conditioned / near-tied swap(s): EliteSets "
-                  f"compared on {len(sure)} common members below both boundaries", flush=True)
+            print(f"   ConstraintEliteSet differs by {sw} near-tied swap(s): EliteSets compared on "
+                  f"{len(sure)} common members that cannot be undercut", flush=True)
         swaps_total += sw
         if sw == 0:
             # mu, Sigma: a cost error dc changes each weight by a factor
@@ -153,14 +167,15 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
             assert np.all(np.abs(g["sigma"][0] - tr["Sigma"][l]) <= tol_S)
             # returned sample of this iteration's EliteSet
             assert res.best_index == tr["es"][l][0]
-            if slow[res.best_index]:
-                continue
             W, _, _ = orc.basis(T, par.t_f)
-            e = np.sqrt((((res.xi_best[:11] - tr["xi_star"][l][res.best_index][:11]) @ W.T) ** 2 +
-                         ((res.xi_best[11:] - tr["xi_star"][l][res.best_index][11:]) @ W.T) ** 2)).max()
-            assert e <= pos_tol, e
+            jb = res.best_index
+            e = np.sqrt((((res.xi_best[:11] - tr["xi_star"][l][jb][:11]) @ W.T) ** 2 +
+                         ((res.xi_best[11:] - tr["xi_star"][l][jb][11:]) @ W.T) ** 2)).max()
+            assert e <= sp.pos_bar(pos_tol)[jb], (e, sp.pos_bar(pos_tol)[jb])
+            compared += 1
         else:
             print(f"   {sw} near-tie swap(s): update not compared at this iteration", flush=True)
+    assert compared >= 1, "no iteration compared mu, Sigma and the returned sample"
     print(f"   near-tie swaps over {L} iterations: {swaps_total}", flush=True)
     return swaps_total
 
