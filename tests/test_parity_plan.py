@@ -16,8 +16,10 @@ index), and must reproduce
     ties; counted and reported),
   * mu and Sigma after the update, within the bound that the cost tolerance
     implies through the weights (derived below), and the returned best
-    sample (position bar plus C times its spread), at every iteration whose
-    sets match, and at least one iteration per case.
+    sample (position bar plus C times its spread), at every iteration: the
+    expected update is the oracle's over the EliteSet the GPU took, which is
+    the oracle's own set or, after near-tie swaps, another resolution of the
+    ties checked member by member against the oracle's keys.
 Inputs flow only from the oracle to the GPU, never back.
 """
 import numpy as np
@@ -148,33 +150,59 @@ def run_config(orc, pl, cfgid, scene_idx, precision=0, tol_scale=1.0, pos_tol=1e
             sure = [int(j) for j in common
                     if np.sum((c_full[gc] - tol_full[gc] <= c_full[j] + tol_full[j]) & (gc != j)) < q]
             assert set(sure) <= set(map(int, g["es"][0])) and set(sure) <= set(map(int, tr["es"][l]))
+            # and the GPU's EliteSet is, by the oracle's costs, the q lowest of
+            # the GPU's ConstraintEliteSet up to near ties
+            gces = np.asarray(g["ces"][0], np.int64)
+            alt = gces[np.lexsort((gces, c_full[gces]))][:q]
+            set_check("EliteSet of the GPU's ConstraintEliteSet", g["es"][0], alt, c_full, tol_full)
             print(f"   ConstraintEliteSet differs by {sw} near-tied swap(s): EliteSets compared on "
                   f"{len(sure)} common members that cannot be undercut", flush=True)
         swaps_total += sw
-        if sw == 0:
-            # mu, Sigma: a cost error dc changes each weight by a factor
-            # exp(+-2 dc / gamma); the weighted mean moves by at most
-            # eta (e^{2 dc/gamma} - 1) max_j |p_j - m|, the covariance by the
-            # same factor times max_j |p_j - m|^2 (plus FP32 sample rounding).
-            es = tr["es"][l]
-            dcm = np.max(dc[es] + dr[es])
-            w = np.expm1(2 * dcm / par.gamma)
-            spread = np.abs(tr["p"][l][es] - tr["mu"][l]).max()
-            tol_mu = par.eta * w * spread + 5e-5 * tol_scale * (1 + np.abs(tr["mu"][l]))
-            tol_S = (par.eta * (w * spread ** 2 + 2 * spread * tol_mu.max())
-                     + 1e-4 * tol_scale * (1 + np.abs(tr["Sigma"][l])))
-            assert np.all(np.abs(g["mu"][0] - tr["mu"][l]) <= tol_mu), np.abs(g["mu"][0] - tr["mu"][l]).max()
-            assert np.all(np.abs(g["sigma"][0] - tr["Sigma"][l]) <= tol_S)
-            # returned sample of this iteration's EliteSet
-            assert res.best_index == tr["es"][l][0]
-            W, _, _ = orc.basis(T, par.t_f)
-            jb = res.best_index
-            e = np.sqrt((((res.xi_best[:11] - tr["xi_star"][l][jb][:11]) @ W.T) ** 2 +
-                         ((res.xi_best[11:] - tr["xi_star"][l][jb][11:]) @ W.T) ** 2)).max()
-            assert e <= sp.pos_bar(pos_tol)[jb], (e, sp.pos_bar(pos_tol)[jb])
-            compared += 1
+        # mu, Sigma after the update, over the EliteSet the GPU took. With no
+        # swap that is the oracle's own set. With near-tie swaps it is another
+        # resolution of the ties, each member of which was checked above
+        # against the oracle's keys; the oracle's update over that set (its
+        # own samples, costs and prior) is then the expected value, since the
+        # update is a function of the set alone (eqs. s_formula, mean_update,
+        # cov_update).
+        es = np.asarray(g["es"][0], np.int64)
+        es = es[np.lexsort((es, c_full[es]))]
+        if l > 0:
+            prior = (tr["mu"][l - 1], tr["Sigma"][l - 1])
+        elif p0 is not None:
+            prior = orc.sample_moments(p0)
         else:
-            print(f"   {sw} near-tie swap(s): update not compared at this iteration", flush=True)
+            prior = orc.initial_moments(par)
+        mu_ref, S_ref = orc.update(par, prior[0], prior[1], tr["p"][l], es, c_full[es])
+        if sw == 0:
+            # the prior is the one the oracle's plan used: its update over its
+            # own set is the trace's, to rounding
+            assert np.allclose(mu_ref, tr["mu"][l], rtol=1e-12, atol=1e-12)
+            assert np.allclose(S_ref, tr["Sigma"][l], rtol=1e-10, atol=1e-12)
+        # a cost error dc changes each weight by a factor exp(+-2 dc / gamma);
+        # the weighted mean moves by at most eta (e^{2 dc/gamma} - 1)
+        # max_j |p_j - m|, the covariance by the same factor times
+        # max_j |p_j - m|^2 (plus FP32 sample rounding)
+        dcm = np.max(dc[es] + dr[es])
+        w = np.expm1(2 * dcm / par.gamma)
+        spread = np.abs(tr["p"][l][es] - mu_ref).max()
+        tol_mu = par.eta * w * spread + 5e-5 * tol_scale * (1 + np.abs(mu_ref))
+        tol_S = par.eta * (w * spread ** 2 + 2 * spread * tol_mu.max()) + 1e-4 * tol_scale * (1 + np.abs(S_ref))
+        assert np.all(np.abs(g["mu"][0] - mu_ref) <= tol_mu), np.abs(g["mu"][0] - mu_ref).max()
+        assert np.all(np.abs(g["sigma"][0] - S_ref) <= tol_S), np.abs(g["sigma"][0] - S_ref).max()
+        # returned sample: the lowest (c, j) of that EliteSet, up to a near tie
+        # at the top; its trajectory against the oracle's projection of it
+        jb = res.best_index
+        assert jb in set(map(int, es)), jb
+        assert jb == es[0] or abs(c_full[jb] - c_full[es[0]]) <= 2 * (tol_full[jb] + tol_full[es[0]]), \
+            (jb, int(es[0]))
+        W, _, _ = orc.basis(T, par.t_f)
+        e = np.sqrt((((res.xi_best[:11] - tr["xi_star"][l][jb][:11]) @ W.T) ** 2 +
+                     ((res.xi_best[11:] - tr["xi_star"][l][jb][11:]) @ W.T) ** 2)).max()
+        assert e <= sp.pos_bar(pos_tol)[jb], (e, sp.pos_bar(pos_tol)[jb])
+        if sw:
+            print(f"   {sw} near-tie swap(s): update compared over the EliteSet the GPU took", flush=True)
+        compared += 1
     assert compared >= 1, "no iteration compared mu, Sigma and the returned sample"
     print(f"   near-tie swaps over {L} iterations: {swaps_total}", flush=True)
     return swaps_total
