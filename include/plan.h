@@ -338,6 +338,33 @@ plan_status plan_lower_solve(plan_handle *h, const plan_request *req,
                              double *xi_star, double *resid,
                              double *cost_upper);
 
+/* plan_lower_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels on the same inputs, with every array on the
+ * device and the library's working memory for the call (the request
+ * descriptor, the launch arrays and the free-coefficient rows of the
+ * samples) in a static device array of about 260 KB, one per GPU, held until
+ * the process ends; its address on the handle's device is looked up once, at
+ * plan_create. The call allocates nothing, enqueues on the handle's stream
+ * and waits for its own work before returning.
+ *   p           device, N x 8 floats: the behavioural inputs (read only;
+ *               not checked for finiteness: non-finite values give NaN
+ *               outputs).
+ *   xi_bar, xi_star   device, N x 22 doubles each, or both NULL.
+ *   resid, cost_upper device, N floats each (the lower level's own values).
+ * The caller's device arrays must be ready when the handle's stream reaches
+ * the call (e.g. synchronise the stream that wrote them first).
+ * N <= PLAN_MAX_N (the scratch array's row count; larger N: PLAN_E_NOMEM)
+ * and N <= max_N. Every call rewrites the parts it uses, so nothing is
+ * cleared between calls; two calls that overlap on one GPU (other host
+ * threads or handles) share the array and race. Errors as plan_lower_solve
+ * (PLAN_E_INVALID for a bad request or a NULL array, PLAN_E_BUSY while
+ * served requests are in flight). Slot 0 of a staged batch is replaced. */
+plan_status plan_lower_solve_static(plan_handle *h, const plan_request *req,
+                                    const float *p, int32_t N, double *xi_bar,
+                                    double *xi_star, float *resid,
+                                    float *cost_upper);
+
 /* Per-iteration record of the last plan_solve_batch / plan_collect for
  * staged request i (needs cfg.trace): samples p (L x N x 8), residuals and
  * costs (L x N), ConstraintEliteSet (L x n) and EliteSet (L x q) sample

@@ -132,6 +132,8 @@ def load():
     lib.plan_launch.argtypes = [H]
     lib.plan_collect.argtypes = [H, Res]
     lib.plan_lower_solve.argtypes = [H, Req, _PD, C.c_int32, _PD, _PD, _PD, _PD]
+    lib.plan_lower_solve_static.argtypes = [H, Req, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p]
     lib.plan_get_trace.argtypes = [H, C.c_int32, _PD, _PD, _PD, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), _PD, _PD]
     lib.plan_submit.argtypes = [H, Req, C.POINTER(C.c_uint64)]
@@ -143,8 +145,9 @@ def load():
     lib.plan_set_decoder.argtypes = [H, C.POINTER(plan_decoder)]
     lib.plan_elite_sizes.argtypes = [Cfg, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     for name in ("plan_create", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
-                 "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-                 "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder", "plan_elite_sizes"):
+                 "plan_lower_solve", "plan_lower_solve_static", "plan_get_trace", "plan_submit",
+                 "plan_progress", "plan_poll", "plan_mpc_run", "plan_profile", "plan_profile_read",
+                 "plan_set_decoder", "plan_elite_sizes"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -153,8 +156,9 @@ def load():
 def exported_symbols() -> list[str]:
     return ["plan_config_init", "plan_workspace_bytes", "plan_create", "plan_destroy",
             "plan_last_error", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
-            "plan_lower_solve", "plan_get_trace", "plan_submit", "plan_progress", "plan_poll",
-            "plan_mpc_run", "plan_profile", "plan_profile_read", "plan_set_decoder", "plan_elite_sizes"]
+            "plan_lower_solve", "plan_lower_solve_static", "plan_get_trace", "plan_submit",
+            "plan_progress", "plan_poll", "plan_mpc_run", "plan_profile", "plan_profile_read",
+            "plan_set_decoder", "plan_elite_sizes"]
 
 
 def _check(status: int, handle=None) -> int:
@@ -368,6 +372,17 @@ def plan_lower_solve(h: Handle, req: Request, p: np.ndarray):
     m = _Marshalled([req])
     _check(load().plan_lower_solve(h.ptr, m.arr, _pd(p), N, _pd(xb), _pd(xs), _pd(r), _pd(c)), h.ptr)
     return xb, xs, r, c
+
+
+def plan_lower_solve_static(h: Handle, req: Request, p_ptr: int, N: int, xi_bar_ptr: int, xi_star_ptr: int,
+                            resid_ptr: int, cost_ptr: int) -> None:
+    """plan_lower_solve on device arrays (addresses as integers, e.g. a torch
+    tensor's data_ptr(); xi pointers may both be 0), with the library's
+    working memory in its static device array: allocates nothing."""
+    m = _Marshalled([req])
+    vp = lambda a: C.c_void_p(a) if a else None
+    _check(load().plan_lower_solve_static(h.ptr, m.arr, vp(p_ptr), N, vp(xi_bar_ptr), vp(xi_star_ptr),
+                                          vp(resid_ptr), vp(cost_ptr)), h.ptr)
 
 
 def plan_get_trace(h: Handle, i: int, N: int, n: int, q: int) -> dict:

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplan.so")
-SOURCES = ["kernels.hip", "mpc.hip", "decoder.hip", "capi.cpp", "precompute.cpp"]
+SOURCES = ["kernels.hip", "mpc.hip", "decoder.hip", "static_scratch.hip", "capi.cpp", "precompute.cpp"]
 ARCH = os.environ.get("PLAN_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

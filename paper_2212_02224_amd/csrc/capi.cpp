@@ -291,6 +291,8 @@ struct plan_handle {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int n_cu = 256;  // compute units of the device
+  int device = 0;  // device current at plan_create
+  StaticScratch scr;  // plan_lower_solve_static's working memory on that device
   bool own_mem = false;
   DevBuf mem;
   Layout lay;
@@ -1217,13 +1219,17 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   hipError_t e = hipSuccess;
   {
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
       h->n_cu = cus;
+    h->device = dev;
+    // the static scratch array's address on this device (once per device)
+    if (e == hipSuccess) e = static_scratch_init(dev, &h->scr);
   }
-  if (c.stream) {
+  if (e == hipSuccess && c.stream) {
     h->stream = (hipStream_t)c.stream;
-  } else {
+  } else if (e == hipSuccess) {
     e = hipStreamCreate(&h->stream);
     h->own_stream = e == hipSuccess;
   }
@@ -1487,6 +1493,60 @@ plan_status plan_lower_solve(plan_handle *h, const plan_request *req, const doub
     if (cost_upper) cost_upper[j] = rc[N + j];
   }
   h->staged = 0;  // slot 0 was overwritten
+  return PLAN_OK;
+}
+
+plan_status plan_lower_solve_static(plan_handle *h, const plan_request *req, const float *p, int32_t N,
+                                    double *xi_bar, double *xi_star, float *resid, float *cost_upper) {
+  if (!h || !req || !p || !resid || !cost_upper) return fail(h, PLAN_E_INVALID, "bad arguments");
+  if ((xi_bar == nullptr) != (xi_star == nullptr))
+    return fail(h, PLAN_E_INVALID, "xi_bar and xi_star must both be given or both be NULL");
+  if (served_in_flight(h))
+    return fail(h, PLAN_E_BUSY, "served requests are in flight; drain them before batch calls");
+  if (N > h->scr.rows)
+    return fail(h, PLAN_E_NOMEM, "N larger than the static scratch (" + std::to_string(h->scr.rows) + " rows)");
+  plan_request r = *req;
+  r.N = N;
+  r.mu0 = r.sigma0 = nullptr;
+  r.session_id = 0;
+  ReqDesc &d = h->h_desc[0];
+  if (const char *why = check_request(h, r, d)) return fail(h, PLAN_E_INVALID, why);
+  d.init_mode = kInitForced;
+  d.row_off = 0;
+  const int slot0 = 0;
+  LaunchSet ls;
+  make_launch_set(h, &slot0, 1, ls);
+  if (ls.n_act != 1 || ls.n_act + ls.ngroups > 8) return fail(h, PLAN_E_INVALID, "internal: launch set");
+  h->staged = 0;  // slot 0's host descriptor now holds this request
+  // descriptor and launch arrays into the scratch array (pinned host sources,
+  // and the call waits below, so the next call cannot overwrite them early)
+  const int32_t *act = h->h_act, *prefix = h->h_act + h->cfg.max_requests;
+  HIP_TRY(h, hipMemcpyAsync(h->scr.desc, h->h_desc, sizeof(ReqDesc), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->scr.act, act, sizeof(int32_t) * ls.n_act, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->scr.act + 8, prefix, sizeof(int32_t) * (ls.n_act + ls.ngroups),
+                            hipMemcpyHostToDevice, h->stream));
+  const bool mf = mfma_mode(h->cfg);
+  for (int k = 0; k < ls.ngroups; ++k) {
+    const LaunchSet::Group &gr = ls.grp[k];
+    LowerArgs la = lower_args(h, gr.n, 0);
+    la.desc = h->scr.desc;
+    la.act_slots = h->scr.act + gr.act_off;
+    la.blk_prefix = h->scr.act + 8 + gr.act_off + k;
+    la.p = const_cast<float *>(p);  // read only: the samples are the caller's (kInitForced)
+    la.dist = nullptr;              // not read for caller's samples
+    la.sess = nullptr;
+    la.zs = h->scr.zs;
+    la.resid = resid;
+    la.cost = cost_upper;
+    la.xi_bar_out = xi_bar;
+    la.xi_star_out = xi_star;
+    const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
+    const hipError_t e =
+        mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, gr.T, gr.lds, h->stream, nullptr, nullptr)
+           : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(h, e, mf ? "lower_mfma_kernel" : "lower_kernel");
+  }
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
   return PLAN_OK;
 }
 

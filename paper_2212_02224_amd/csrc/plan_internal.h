@@ -158,6 +158,23 @@ struct SelArgs {
   int32_t max_N, max_ces, max_es;
 };
 
+// Working memory of plan_lower_solve_static: a file-scope device array (one
+// copy per GPU, static_scratch.hip), addressed through the device pointers
+// that static_scratch_init takes once per device. Holds one request
+// descriptor, the launch arrays and the free-coefficient rows of up to
+// kStaticRows samples.
+constexpr int kStaticRows = PLAN_MAX_N;
+struct StaticScratch {
+  ReqDesc *desc = nullptr;
+  int32_t *act = nullptr;  // act_slots at [0, 8), blk_prefix at [8, 16)
+  float *zs = nullptr;     // [kStaticRows][kZ]
+  int32_t rows = 0;
+};
+// With `device` current: look up the array's address on that device (once
+// per device; later calls reuse it) and fill *out.
+hipError_t static_scratch_init(int device, StaticScratch *out);
+size_t static_scratch_bytes();
+
 // Decoder sampler (App. A decoder MLP at inference). Its samples are the
 // rows of the requests being decoded, concatenated: segment s covers
 // concatenated rows [row_begin, row_begin + n) = samples 0..n-1 of slot.
