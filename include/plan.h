@@ -85,11 +85,19 @@ typedef enum plan_status {
  *                         residual) stays FP32. Requires every T <= 128;
  *                         values beyond the FP16 range (|v| > 65504 after the
  *                         scalings) give NaN residuals, which rank last.
- * Both modes draw the same samples and use the same selection and update.
+ *   PLAN_PREC_FP32_MFMA   the same dense products on the matrix cores in
+ *                         FP32 (FP32 operands, FP32 accumulation; no
+ *                         splitting), everything else as PLAN_PREC_FP32.
+ *                         Groups of 16 samples per workgroup, so it pays on
+ *                         large batches (thousands of samples in flight);
+ *                         requires every T <= 128.
+ * All modes draw the same samples and use the same selection and update;
+ * a request's results depend on the mode, never on what else runs with it.
  */
 typedef enum plan_precision {
   PLAN_PREC_FP32 = 0,
-  PLAN_PREC_FP16_SPLIT = 1
+  PLAN_PREC_FP16_SPLIT = 1,
+  PLAN_PREC_FP32_MFMA = 2
 } plan_precision;
 
 /*

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libplan.so")
 
 PLAN_OK, PLAN_E_INVALID, PLAN_E_NOMEM, PLAN_E_DEVICE, PLAN_E_BUSY, PLAN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-PLAN_PREC_FP32, PLAN_PREC_FP16_SPLIT = 0, 1
+PLAN_PREC_FP32, PLAN_PREC_FP16_SPLIT, PLAN_PREC_FP32_MFMA = 0, 1, 2
 PLAN_F_INFEASIBLE, PLAN_F_WARM = 1, 2
 PLAN_MPC_SAMPLER, PLAN_MPC_WARM = 0, 1
 PLAN_BEHAV_SETPOINTS, PLAN_BEHAV_GOALS = 0, 1

@@ -31,8 +31,8 @@
 namespace plan {
 hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, bool road, size_t lds,
                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, int T,
-                             size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, bool f32,
+                             int T, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1);
 hipError_t launch_advance(const AdvArgs &a, const MethodParams &p, int n, hipStream_t st);
@@ -66,17 +66,22 @@ int64_t budget_rows(const plan_config &c) {
   return c.sample_budget > 0 ? c.sample_budget : (int64_t)c.max_requests * c.max_N;
 }
 
-bool mfma_mode(const plan_config &c) { return c.precision == PLAN_PREC_FP16_SPLIT; }
+bool mfma_mode(const plan_config &c) {
+  return c.precision == PLAN_PREC_FP16_SPLIT || c.precision == PLAN_PREC_FP32_MFMA;
+}
+bool mfma_f32(const plan_config &c) { return c.precision == PLAN_PREC_FP32_MFMA; }
 
 // Dynamic LDS of the lower kernels: two neighbours per float4 and instant;
-// the matrix-core kernel adds its basis table (kEvInstHalfs halves per
-// instant of the padded horizon), the fixed trajectory part (two float4 per
-// instant), the N^T g sums of its tile pairs and their total.
-size_t lds_bytes(int M, int T, bool mfma) {
+// the matrix-core kernel adds its basis table (kEvInstHalfs halves, or in
+// the FP32 form kEv32InstFloats floats, per instant of the padded horizon),
+// the fixed trajectory part (two float4 per instant), the N^T g sums of its
+// tile pairs and their total.
+size_t lds_bytes(int M, int T, bool mfma, bool f32 = false) {
   size_t b = (size_t)((M + 1) / 2) * T * sizeof(float4);
   if (mfma) {
     const size_t NT = (size_t)((T + 3) / 4), NI = 4 * NT;
-    b += NI * kEvInstHalfs * 2 + (2 * NI + ((NT + 1) / 2 + 1) * kWave) * sizeof(float4);
+    b += (f32 ? NI * kEv32InstFloats * 4 : NI * kEvInstHalfs * 2) +
+         (2 * NI + ((NT + 1) / 2 + 1) * kWave) * sizeof(float4);
   }
   return b;
 }
@@ -188,8 +193,9 @@ Layout compute_layout(const plan_config &c) {
   L.proj = (size_t)c.n_T * c.n_M * kProjFloats * 4;
   L.offs = (size_t)c.n_T * 3 * 4;
   if (mfma_mode(c)) {
-    for (int i = 0; i < c.n_T; ++i) L.mops += (size_t)4 * ((c.T_set[i] + 3) / 4) * kEvInstHalfs * 2;
-    L.mainv = (size_t)c.n_T * c.n_M * 2 * kWave * 8;
+    const size_t per_inst = mfma_f32(c) ? kEv32InstFloats * 4 : kEvInstHalfs * 2;
+    for (int i = 0; i < c.n_T; ++i) L.mops += (size_t)4 * ((c.T_set[i] + 3) / 4) * per_inst;
+    if (!mfma_f32(c)) L.mainv = (size_t)c.n_T * c.n_M * 2 * kWave * 8;
   }
   L.desc = S * sizeof(ReqDesc);
   L.dist = S * sizeof(DistState);
@@ -246,10 +252,11 @@ const char *validate_config(const plan_config &c) {
     return "unknown sampler";
   if (c.served_run_ahead < 0 || c.served_run_ahead > kRing - 1) return "served_run_ahead must be in [0, 3]";
   if (c.behaviour == PLAN_BEHAV_GOALS && !(c.w_s > 0)) return "goal positions need w_s > 0 (the cost is c_s alone)";
-  if (c.precision != PLAN_PREC_FP32 && c.precision != PLAN_PREC_FP16_SPLIT) return "unsupported precision";
+  if (c.precision != PLAN_PREC_FP32 && c.precision != PLAN_PREC_FP16_SPLIT && c.precision != PLAN_PREC_FP32_MFMA)
+    return "unsupported precision";
   if (mfma_mode(c))
     for (int i = 0; i < c.n_T; ++i)
-      if (c.T_set[i] > kMfmaMaxT) return "PLAN_PREC_FP16_SPLIT supports T <= 128";
+      if (c.T_set[i] > kMfmaMaxT) return "the matrix-core precisions support T <= 128";
   return nullptr;
 }
 
@@ -437,7 +444,8 @@ const char *check_request(const plan_handle *h, const plan_request &r, ReqDesc &
   if (ti < 0) return "T not in T_set";
   if (mi < 0) return "M not in M_set";
   if (lds_bytes(r.M, r.T, false) > 60 * 1024) return "M * T too large for the LDS table";
-  if (mfma_mode(c) && lds_bytes(r.M, r.T, true) > 64 * 1024) return "M * T too large for the LDS table";
+  if (mfma_mode(c) && lds_bytes(r.M, r.T, true, mfma_f32(c)) > 64 * 1024)
+    return "M * T too large for the LDS table";
   if (!finite_all(r.ego, 6) || !std::isfinite(r.kappa_road)) return "non-finite ego state";
   if (r.M > 0 && r.obstacles == nullptr) return "obstacles missing";
   if (r.M > 0 && !finite_all(r.obstacles, 4 * r.M)) return "non-finite obstacle";
@@ -632,7 +640,7 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
       act[pos] = slots[i];
       prefix[pos + k] = blocks;
       blocks += blocks_for(d.N, d.T, mf);
-      gr.lds = std::max(gr.lds, lds_bytes(d.M, d.T, mf));
+      gr.lds = std::max(gr.lds, lds_bytes(d.M, d.T, mf, mfma_f32(h->cfg)));
       ++pos;
     }
     gr.n = pos - gr.act_off;
@@ -680,7 +688,7 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
     const ReqDesc &d = h->h_desc[act[i]];
     prefix[i + k0] = blocks;
     blocks += blocks_for(d.N, d.T, mf, 1);
-    all.lds = std::max(all.lds, lds_bytes(d.M, d.T, mf));
+    all.lds = std::max(all.lds, lds_bytes(d.M, d.T, mf, mfma_f32(h->cfg)));
   }
   prefix[pos0 + n + k0] = blocks;
   all.nblocks = blocks;
@@ -729,7 +737,8 @@ plan_status launch_lower_set(plan_handle *h, const LaunchSet &ls, int l_uniform,
           // two tiles per wave while a launch cannot fill every CU with two
           // workgroups, else four (same arithmetic either way)
           const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
-          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, gr.T, gr.lds, h->stream, a, b)
+          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds,
+                                        h->stream, a, b)
                     : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, a, b);
         },
         mf ? "lower_mfma_kernel" : "lower_kernel");
@@ -1165,7 +1174,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->mops_off = h->basis_off + 2 * c.n_T;
   if (L.mops) {
     h->mops = (uint16_t *)h->mem.take(L.mops);
-    h->mainv = (uint16_t *)h->mem.take(L.mainv);
+    if (L.mainv) h->mainv = (uint16_t *)h->mem.take(L.mainv);
   }
   h->desc = (ReqDesc *)h->mem.take(L.desc);
   h->dist = (DistState *)h->mem.take(L.dist);
@@ -1256,11 +1265,12 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
       basis_all.insert(basis_all.end(), bts[i].table.begin(), bts[i].table.end());
       if (h->mops) {
         offs[2 * c.n_T + i] = (int32_t)mops_all.size();
-        build_mfma_basis(bts[i], tmp);
+        if (mfma_f32(c)) build_mfma32_basis(bts[i], tmp);
+        else build_mfma_basis(bts[i], tmp);
         mops_all.insert(mops_all.end(), tmp.begin(), tmp.end());
       }
     }
-    if (h->mops)
+    if (h->mainv)
       for (auto &t : pj) {
         build_mfma_inverse(t, tmp);
         mainv_all.insert(mainv_all.end(), tmp.begin(), tmp.end());
@@ -1542,7 +1552,8 @@ plan_status plan_lower_solve_static(plan_handle *h, const plan_request *req, con
     la.xi_star_out = xi_star;
     const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
     const hipError_t e =
-        mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, gr.T, gr.lds, h->stream, nullptr, nullptr)
+        mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds, h->stream,
+                               nullptr, nullptr)
            : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(h, e, mf ? "lower_mfma_kernel" : "lower_kernel");
   }

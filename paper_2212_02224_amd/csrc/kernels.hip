@@ -899,7 +899,9 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
 
   if (!active) return;
   const size_t row = slot_off + j;
-  if ((lane & 3) == 0 && v < 15) A.zs[row * kZ + v] = z;
+  // all 16 entries (the pad one is 0), so each row is one whole 64-byte line;
+  // every wave of the sample holds the same z, the first one stores it
+  if (wi == 0 && (lane & 3) == 0) A.zs[row * kZ + v] = z;
   if (wi == 0 && lane == 0) {
     A.resid[row] = rr;
     A.cost[row] = cc;
@@ -964,6 +966,27 @@ __device__ __forceinline__ void split_corr(const Corr &c, h8 &hi, h8 &lo) {
   lo = h8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
 }
 
+// FP32 matrix-core product 16 x 4 by 4 x 16: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; D row 4 (l / 16) + u, column l % 16 is element u of
+// lane l.
+__device__ __forceinline__ f4 mma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// 4 x 4 transpose across the lane groups of a sample: lane group g holds
+// a[g][0..3] (lanes n, n + 16, n + 32, n + 48 of sample n); returns
+// b[g][u] = a[u][g]. Exchanging the off-diagonal 2 x 2 blocks between the
+// half-waves, then the off-diagonal elements of each block between the
+// 16-lane rows of each half.
+__device__ __forceinline__ f4 transpose_groups(f4 a) {
+  float a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+  swap32(a0, a2);
+  swap32(a1, a3);
+  swap16(a0, a1);
+  swap16(a2, a3);
+  return f4{a0, a1, a2, a3};
+}
+
 __device__ __forceinline__ void swap32u(uint32_t &a, uint32_t &b) {
   auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
   a = r[0];
@@ -1010,10 +1033,22 @@ __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int N, i
   finish_draw(P, structured, j, N, sel, z, wb1, mu, chol, p);
 }
 
-// Dynamic LDS of the matrix-core kernel: basis table [4 NT][kEvInstHalfs],
-// neighbours [pair of neighbours][T] (float4), fixed trajectory part [4 NT][2]
-// (float4), N^T g per tile pair [ceil(NT / 2)][64] (float4), total [64].
-template <int TPW, bool ROAD>
+// Dynamic LDS of the matrix-core kernel: basis table [4 NT][kEvInstHalfs]
+// (F32: [4 NT][kEv32InstFloats]), neighbours [pair of neighbours][T]
+// (float4), fixed trajectory part [4 NT][2] (float4), N^T g per tile pair
+// [ceil(NT / 2)][64] (float4), total [64].
+//
+// F32 selects the FP32 form of the same dataflow: every product on the
+// matrix cores in FP32 (v_mfma_f32_16x16x4f32, one instant of a tile or one
+// group of 4 coefficients per instruction), no operand splitting:
+//   evaluation  4 products per tile (2 per axis), the coefficient operand
+//               regrouped once per pass by a 4 x 4 transpose across the
+//               lane groups of each sample;
+//   N^T g       6 products per tile (one per axis and derivative order, the
+//               instants of the tile along K, each lane's own differences as
+//               its B element);
+//   xi-update   4 products per iteration (A^-1 in FP32, rhs transposed).
+template <int TPW, bool ROAD, bool F32>
 __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_dyn[];
   __shared__ double s_mu[8], s_chol[64];
@@ -1034,7 +1069,8 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   const bool active = j < N;
   const size_t slot_off = (size_t)D.row_off;
 
-  const int tab_f4 = NT * kEvInstHalfs / 2;  // 4 NT instants x 224 bytes, in float4
+  // 4 NT instants x 224 bytes (F32: 192 bytes), in float4
+  const int tab_f4 = F32 ? NT * kEv32InstFloats : NT * kEvInstHalfs / 2;
   _Float16 *s_tab = reinterpret_cast<_Float16 *>(s_dyn);
   float4 *s_obs = s_dyn + tab_f4;
   float4 *s_fix = s_obs + npair * T;
@@ -1092,11 +1128,29 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
               by[0], by[q_step_y], by[2 * q_step_y], (_Float16)0.f};
   };
 
-  const h4 *Ai = reinterpret_cast<const h4 *>(A.mainv) + (size_t)D.tm_idx * 2 * kWave;
-  const h4 ai_hi = Ai[lane], ai_lo = Ai[kWave + lane];
-  f4 Dv;
+  //   F32 form: the table holds (x c_g, x c_{4+g}, y c_g, y c_{4+g}) per
+  //   (instant, order, g); evaluation row n = 4 a + q reads its group's
+  //   float4, the accumulation row n (a coefficient) reads its basis value
+  //   at instant g for each order from the x or the y entry, and the zero
+  //   entry (y c_7, slot 15 of every order) for the other axis.
+  const float *s_t32 = reinterpret_cast<const float *>(s_dyn);
+  const int ev32 = (n >> 2) * kEv32InstFloats + min(n & 3, 2) * 16 + 4 * g;
+  const int acx32 = g * kEv32InstFloats + (n < 8 ? (n & 3) * 4 + (n >> 2) : 15);
+  const int acy32 = g * kEv32InstFloats + (n >= 8 ? ((n - 8) & 3) * 4 + 2 + ((n - 8) >> 2) : 15);
+
+  h4 ai_hi, ai_lo;
+  f4 ai32, Dv;
   {
     const float *Pj = A.proj + (size_t)D.tm_idx * kProjFloats;
+    if constexpr (F32) {
+      // A^-1 row n, columns 4 kb + g (kb = 0..3)
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) ai32[kb] = Pj[n * 16 + 4 * kb + g];
+    } else {
+      const h4 *Ai = reinterpret_cast<const h4 *>(A.mainv) + (size_t)D.tm_idx * 2 * kWave;
+      ai_hi = Ai[lane];
+      ai_lo = Ai[kWave + lane];
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) Dv[u] = Pj[256 + 4 * g + u];
   }
@@ -1126,14 +1180,35 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   }
   f4 z = zb, mu = {0.f, 0.f, 0.f, 0.f};
 
+  // Coefficient operands of a pass: FP16 halves (bx, by), or for F32 the
+  // transposed state bz (bz[u] = coefficient 4 u + g of the lane's sample).
+  struct CoefOps {
+    h4 bx, by;
+    f4 bz;
+  };
+  auto coef_ops = [&](f4 zz) -> CoefOps {
+    CoefOps o;
+    if constexpr (F32) o.bz = transpose_groups(zz);
+    else coef_operands(zz, o.bx, o.by);
+    return o;
+  };
+
   // Trajectory state at this lane's instant of a tile.
-  auto evaluate = [&](int tile, h4 bx, h4 by) -> State6 {
+  auto evaluate = [&](int tile, const CoefOps &co) -> State6 {
     const float4 cx = s_fix[2 * (4 * tile + g)], cy = s_fix[2 * (4 * tile + g) + 1];
     f4 ex = {cx.x, cx.y, cx.z, cx.w}, ey = {cy.x, cy.y, cy.z, cy.w};
-    ex = mma(ev_op(tile, 0, 0), bx, ex);
-    ex = mma(ev_op(tile, 0, 1), bx, ex);
-    ey = mma(ev_op(tile, 1, 0), by, ey);
-    ey = mma(ev_op(tile, 1, 1), by, ey);
+    if constexpr (F32) {
+      const float4 a = *reinterpret_cast<const float4 *>(s_t32 + tile * 4 * kEv32InstFloats + ev32);
+      ex = mma_f32(a.x, co.bz[0], ex);
+      ex = mma_f32(a.y, co.bz[1], ex);
+      ey = mma_f32(a.z, co.bz[2], ey);
+      ey = mma_f32(a.w, co.bz[3], ey);
+    } else {
+      ex = mma(ev_op(tile, 0, 0), co.bx, ex);
+      ex = mma(ev_op(tile, 0, 1), co.bx, ex);
+      ey = mma(ev_op(tile, 1, 0), co.by, ey);
+      ey = mma(ev_op(tile, 1, 1), co.by, ey);
+    }
     State6 st;
     st.x = ex[0];
     st.xd = ex[1];
@@ -1148,16 +1223,26 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   // One target pass over this wave's tiles at the current z (first: the
   // initial d_a from the same evaluation); returns N^T g of the workgroup.
   auto accumulate = [&](int tile, const Corr &c, f4 acc) -> f4 {
-    h8 dh, dl;
-    split_corr(c, dh, dl);
-    const h8 ch = ac_op(tile, 0), cl = ac_op(tile, 1);
-    acc = mma32(ch, dh, acc);
-    acc = mma32(ch, dl, acc);
-    return mma32(cl, dh, acc);
+    if constexpr (F32) {
+      const float *bx = s_t32 + tile * 4 * kEv32InstFloats + acx32;
+      const float *by = s_t32 + tile * 4 * kEv32InstFloats + acy32;
+      acc = mma_f32(bx[0], c.dox, acc);
+      acc = mma_f32(bx[16], c.dvx, acc);
+      acc = mma_f32(bx[32], c.dax, acc);
+      acc = mma_f32(by[0], c.wy, acc);
+      acc = mma_f32(by[16], c.dvy, acc);
+      return mma_f32(by[32], c.day, acc);
+    } else {
+      h8 dh, dl;
+      split_corr(c, dh, dl);
+      const h8 ch = ac_op(tile, 0), cl = ac_op(tile, 1);
+      acc = mma32(ch, dh, acc);
+      acc = mma32(ch, dl, acc);
+      return mma32(cl, dh, acc);
+    }
   };
   auto pass = [&](bool first) -> f4 {
-    h4 bx, by;
-    coef_operands(z, bx, by);
+    const CoefOps co = coef_ops(z);
 #pragma unroll
     for (int pr = 0; pr < TPW / 2; ++pr) {
       const int pair = wave * (TPW / 2) + pr;
@@ -1168,7 +1253,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
           const int i = 2 * pr + h, tile = 2 * pair + h;
           if (tile < NT) {
             const int t = 4 * tile + g;
-            const State6 st = evaluate(tile, bx, by);
+            const State6 st = evaluate(tile, co);
             if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
             acc = accumulate(tile, targets_at<ROAD>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
                                                     active && t < T, da[i]),
@@ -1205,14 +1290,22 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
     // xi-update (eq. split_xy): dz = A^-1 rhs on the matrix cores
     f4 rhs;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) rhs[u] = fmaf(Dv[u], zb[u] - z[u], fmaf(S.rho, G[u], mu[u])) * kRhsScale;
-    h4 rh, rl;
-    split4(rhs, rh, rl);
+    for (int u = 0; u < 4; ++u) rhs[u] = fmaf(Dv[u], zb[u] - z[u], fmaf(S.rho, G[u], mu[u]));
     f4 dz = {0.f, 0.f, 0.f, 0.f};
-    dz = mma(ai_hi, rh, dz);
-    dz = mma(ai_hi, rl, dz);
-    dz = mma(ai_lo, rh, dz);
-    z += dz * (float)(1.0 / (kAinvScale * kRhsScale));
+    if constexpr (F32) {
+      const f4 rt = transpose_groups(rhs);
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) dz = mma_f32(ai32[kb], rt[kb], dz);
+      z += dz;
+    } else {
+      rhs *= kRhsScale;
+      h4 rh, rl;
+      split4(rhs, rh, rl);
+      dz = mma(ai_hi, rh, dz);
+      dz = mma(ai_hi, rl, dz);
+      dz = mma(ai_lo, rh, dz);
+      z += dz * (float)(1.0 / (kAinvScale * kRhsScale));
+    }
     if (k < K) {
       G = pass(false);
       mu += (0.5f * S.rho) * G;  // eq. update_lagrange
@@ -1222,8 +1315,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   // Residual and upper cost of xi* = xi^K: per tile pair, summed over the
   // 4 lane groups of a sample, then over the pairs in pair order.
   {
-    h4 bx, by;
-    coef_operands(z, bx, by);
+    const CoefOps co = coef_ops(z);
 #pragma unroll
     for (int pr = 0; pr < TPW / 2; ++pr) {
       const int pair = wave * (TPW / 2) + pr;
@@ -1235,7 +1327,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
           if (tile < NT) {
             const int t = 4 * tile + g;
             float r1, c1;
-            residual_at<ROAD>(evaluate(tile, bx, by), S, s_obs, s_road, npair, T, t < T ? t : T - 1,
+            residual_at<ROAD>(evaluate(tile, co), S, s_obs, s_road, npair, T, t < T ? t : T - 1,
                               active && t < T, r1, c1);
             rr += r1;
             cc += c1;
@@ -1904,12 +1996,14 @@ hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, 
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kBlock), lds, st, a, p);
   return hipGetLastError();
 }
-hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, int T,
-                             size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, bool f32,
+                             int T, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if ((tpw != 2 && tpw != 4) || T < 1 || T > kMfmaMaxT) return hipErrorInvalidValue;
   const int waves = (T + 4 * tpw - 1) / (4 * tpw);
-  auto kern = tpw == 2 ? (road ? lower_mfma_kernel<2, true> : lower_mfma_kernel<2, false>)
-                       : (road ? lower_mfma_kernel<4, true> : lower_mfma_kernel<4, false>);
+  auto kern = f32 ? (tpw == 2 ? (road ? lower_mfma_kernel<2, true, true> : lower_mfma_kernel<2, false, true>)
+                              : (road ? lower_mfma_kernel<4, true, true> : lower_mfma_kernel<4, false, true>))
+                  : (tpw == 2 ? (road ? lower_mfma_kernel<2, true, false> : lower_mfma_kernel<2, false, false>)
+                              : (road ? lower_mfma_kernel<4, true, false> : lower_mfma_kernel<4, false, false>));
   if (ev0 != nullptr)
     hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(kWave * waves), (uint32_t)lds, st, ev0, ev1, 0, a, p);
   else

@@ -42,6 +42,13 @@ enum BasisCol {
 constexpr int kEvAxisHalfs = 48;          // 3 orders x 16
 constexpr int kEvPad = 96;                // offset of the zero pad
 constexpr int kEvInstHalfs = 112;         // halves per instant (224 bytes)
+// Basis table of the FP32 matrix-core lower level, per instant t (padded to
+// a multiple of 4 instants, zero beyond T), in FP32:
+//   [q = position, velocity, acceleration][g = 0..3]
+//     (x c_g, x c_{4+g}, y c_g, y c_{4+g})
+// over the same 8 free coefficients per axis (x: c3..c10; y: c3..c8,
+// c9 + c10, 0): one float4 per (instant, order, lane group).
+constexpr int kEv32InstFloats = 48;       // floats per instant (192 bytes)
 // How iteration 0 draws its samples.
 enum InitMode : int32_t {
   kInitStructured = 0,  // structured initial sampler (lanes + uniform speeds)

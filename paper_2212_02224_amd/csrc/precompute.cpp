@@ -422,6 +422,22 @@ void build_mfma_basis(const BasisTable &bt, std::vector<uint16_t> &ops) {
         }
 }
 
+void build_mfma32_basis(const BasisTable &bt, std::vector<uint16_t> &ops) {
+  const int NI = 4 * ((bt.T + 3) / 4);
+  std::vector<float> tab((size_t)NI * kEv32InstFloats, 0.f);
+  for (int t = 0; t < NI && t < bt.T; ++t)
+    for (int q = 0; q < 3; ++q)
+      for (int g = 0; g < 4; ++g) {
+        float *e = &tab[(size_t)t * kEv32InstFloats + q * 16 + g * 4];
+        e[0] = (float)free_basis(bt, false, q, t, g);
+        e[1] = (float)free_basis(bt, false, q, t, 4 + g);
+        e[2] = (float)free_basis(bt, true, q, t, g);
+        e[3] = (float)free_basis(bt, true, q, t, 4 + g);
+      }
+  ops.assign(tab.size() * 2, 0);
+  std::memcpy(ops.data(), tab.data(), tab.size() * sizeof(float));
+}
+
 void build_mfma_inverse(const ProjTable &pt, std::vector<uint16_t> &ops) {
   ops.assign(2 * 64 * 4, 0);
   for (int lane = 0; lane < 64; ++lane)

@@ -40,6 +40,10 @@ void build_proj(const BasisTable &bt, int M, double rho, bool goals, ProjTable &
 //   inverse [2][64 lanes][4]: high then low half of kAinvScale * A^-1 in the
 //           A-operand lane order of v_mfma_f32_16x16x16_f16
 void build_mfma_basis(const BasisTable &bt, std::vector<uint16_t> &ops);
+// The FP32 matrix-core form of the same table (kEv32InstFloats floats per
+// instant, layout in plan_internal.h), returned as the FP16-sized words of
+// its bytes so both forms share one device region.
+void build_mfma32_basis(const BasisTable &bt, std::vector<uint16_t> &ops);
 void build_mfma_inverse(const ProjTable &pt, std::vector<uint16_t> &ops);
 
 // Device tables of the decoder sampler: each block's BatchNorm (inference

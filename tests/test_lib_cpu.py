@@ -83,8 +83,9 @@ def test_config_defaults_and_workspace(pl):
 
 @pytest.mark.parametrize("over", [dict(max_N=0), dict(max_N=5000), dict(T_set=[8]), dict(M_set=[40]),
                                   dict(upper_iters=0), dict(gamma=0.0), dict(y_lb=3.0, y_ub=-3.0),
-                                  dict(frac_ces=0.01, frac_es=0.05), dict(precision=7), dict(precision=2),
-                                  dict(precision=1, T_set=[50, 200]), dict(behaviour=2), dict(sampler=3),
+                                  dict(frac_ces=0.01, frac_es=0.05), dict(precision=7), dict(precision=3),
+                                  dict(precision=1, T_set=[50, 200]), dict(precision=2, T_set=[50, 200]),
+                                  dict(behaviour=2), dict(sampler=3),
                                   dict(behaviour=1, w_s=0.0), dict(served_run_ahead=4),
                                   dict(served_run_ahead=-1)])
 def test_invalid_config_rejected_before_device(pl, over):

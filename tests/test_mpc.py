@@ -177,7 +177,7 @@ def test_mpc_rejects_bad_arguments(pl):
     assert res[0].status == 0 and set(log) == {"ego", "collided"}
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_mpc_full_size(orc, pl, precision):
     """The measured closed-loop configuration at full size: 256 episodes of
     N = 1000, T = 100, M = 10, L = 5, K = 20 (the headline planner), here for

@@ -125,7 +125,7 @@ def test_decoder_goal_plan_parity(orc, pl):
     run_config(orc, pl, 1, 2, behaviour=1, decoder_seed=2, p0_tol=p_tol)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_decoder_batch_and_served_equal_alone(pl, precision):
     """Decoder rows of several requests share the decoder launches (in a
     batch, and in the served mode next to requests mid-flight); each

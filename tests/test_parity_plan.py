@@ -213,13 +213,13 @@ def test_plan_parity_per_iteration(orc, pl, cfgid, scene_idx):
     run_config(orc, pl, cfgid, scene_idx)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_plan_parity_mostly_infeasible(orc, pl, precision):
     """a_max = 1 m/s^2 leaves 10-20 of the 1000 samples feasible (r = 0), so
     the ConstraintEliteSet of 150 is not a run of equal smallest keys: the
     selection kernel takes its radix passes over the residual keys and the
     position-ordered scan of the boundary bin."""
-    kw = dict(tol_scale=10.0, pos_tol=1e-3) if precision else {}
+    kw = dict(tol_scale=10.0, pos_tol=1e-3) if precision == 1 else {}
     run_config(orc, pl, 2, 0, precision=precision, L=3, method=dict(a_max=1.0), **kw)
 
 

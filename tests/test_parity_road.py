@@ -34,7 +34,7 @@ def road_kw(cfgid, idx):
     return dict(road=rp, road_x0=rx0, road_dx=rdx)
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-4), (1, 1e-3)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-4), (1, 1e-3), (2, 1e-4)])
 @pytest.mark.parametrize("N,T,M,idx,v0", [(256, 100, 10, 0, 18.0), (37, 50, 4, 1, 20.0), (9, 128, 3, 4, 22.0),
                                            (200, 64, 20, 3, 24.0)])
 def test_road_lower_parity(orc, pl, precision, tol, N, T, M, idx, v0):
@@ -63,7 +63,7 @@ def test_road_lower_parity(orc, pl, precision, tol, N, T, M, idx, v0):
     print(f"   xi_bar err {e_bar.max():.2e}", flush=True)
     check_positions("xi*", e_star, sp, tol)
     assert e_bar.max() <= 1e-4
-    r_scale = 1.0 if precision == 0 else 10.0
+    r_scale = 10.0 if precision == 1 else 1.0
     assert np.all(np.abs(r_g - r_o) <= sp.r_bar(r_scale * (1e-3 + 1e-4 * np.abs(r_o))))
     assert np.all(np.abs(c_g - c_o) <= sp.cu_bar(r_scale * 1e-4 * np.abs(c_o) + 1e-4))
 
@@ -77,7 +77,7 @@ def test_road_plan_parity_fp16_split(orc, pl):
     run_config(orc, pl, 1, 1, precision=1, tol_scale=10.0, pos_tol=1e-3, road=True)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_one_knot_profile_equals_constant_road(pl, precision):
     """A profile of one knot (kappa, y_lb, y_ub) describes the constant road
     with that curvature and the configured lane limits: same plan, bit for
@@ -96,7 +96,7 @@ def test_one_knot_profile_equals_constant_road(pl, precision):
         assert np.array_equal(a.xi_best, b.xi_best) and np.array_equal(a.mu, b.mu), i
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_mixed_road_batch_equals_alone(pl, precision):
     """Requests with and without a profile in one batch and in the served
     mode (separate launches per kernel variant) return what they return

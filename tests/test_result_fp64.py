@@ -38,7 +38,7 @@ def check_result(orc, pl, par, sc, res, T):
     return r_o[0]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("case", ["feasible", "infeasible", "curved_road"])
 def test_returned_residual_cost_and_positions_are_fp64(orc, pl, precision, case):
     c = workload.CONFIGS[2]
@@ -60,7 +60,7 @@ def test_returned_residual_cost_and_positions_are_fp64(orc, pl, precision, case)
         assert r > 0.0 and res.flags & pl.PLAN_F_INFEASIBLE
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_served_results_carry_fp64_residual_and_positions(orc, pl, precision):
     cfg = pl.plan_config_init(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=10, upper_iters=3, max_N=512,
                               max_requests=3, precision=precision)

@@ -68,7 +68,7 @@ def samples(N, seed):
     return p.astype(np.float32)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_static_equals_allocating(pl, hip, precision):
     cfg = pl.plan_config_init(T_set=[50, 100], M_set=[4, 10], proj_iters=20, upper_iters=5, max_N=1000,
                               max_requests=1, precision=precision)
