@@ -55,7 +55,7 @@ HEADLINE_REQUESTS = 1024
 # FP32 form of the headline: 0 = PLAN_PREC_FP32 (every product on the vector
 # ALUs), 2 = PLAN_PREC_FP32_MFMA (the dense products on the matrix cores in
 # FP32); both FP32 throughout and held to the same parity bar
-HEADLINE_PRECISION = 2
+HEADLINE_PRECISION = 0
 PRECISION_NAMES = {0: "fp32_valu", 1: "fp16_split", 2: "fp32_mfma"}
 # the lower kernel of each form (as rocprofv3 names it at the headline's
 # shape) and the key of its committed profile
@@ -474,6 +474,45 @@ def time_plan(pl, torch, c, scene, precision, steps, warmup, road=None, decoder=
     return t1 - t0, ms, cnt, res
 
 
+def copy_probe(torch):
+    """Three device-to-device copies of 512 MiB: a kernel of known traffic
+    that calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def plan_legs(pl, torch, workload, c, args, out):
+    """The single plan (the latency case) in FP32 and, unless --no-mixed, in
+    the FP16 split, into out["c2_plan"] and out["mixed"]["c3_plan"]; returns
+    the (steps, warm-up) it used."""
+    N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
+    scene = workload.scene(PLAN_CFG_ID, 0, M)
+    psteps, pwarm = max(args.steps, 50), max(args.warmup, 10)
+    print(f"[bench] plan {c['name']} fp32: {pwarm} warm-up + {psteps} timed steps", file=sys.stderr, flush=True)
+    el2, ms2, cnt2, res = time_plan(pl, torch, c, scene, 0, psteps, pwarm)
+    out["c2_plan"] = {
+        "workload": c["name"] + f"-L{L}-K{K}", "value": N * L * psteps / el2, "unit": "QP-solves/s",
+        "ms_per_plan": 1e3 * el2 / psteps,
+        "roofline": roofline(0, ms2["lower"] / max(1, cnt2["lower"]), N, T, M, K, cnt2["lower"], c["name"],
+                             kernel="lower_kernel<1, false>"),
+        "kernel_ms_per_step": {k: ms2[k] / psteps for k in ms2},
+        "plan": {"best_index": res.best_index, "cost_upper": res.cost_upper, "residual": res.residual}}
+    if not args.no_mixed:
+        print("[bench] plan fp16_split", file=sys.stderr, flush=True)
+        el3, ms3, cnt3, res3 = time_plan(pl, torch, c, scene, 1, psteps, pwarm)
+        out["mixed"]["c3_plan"] = {
+            "precision": "fp16_split", "value": N * L * psteps / el3, "unit": "QP-solves/s",
+            "ms_per_plan": 1e3 * el3 / psteps,
+            "roofline": roofline(1, ms3["lower"] / max(1, cnt3["lower"]), N, T, M, K, cnt3["lower"], c["name"],
+                                 kernel="lower_mfma_kernel<2, false, false>"),
+            "kernel_ms_per_step": {k: ms3[k] / psteps for k in ms3},
+            "plan": {"best_index": res3.best_index, "cost_upper": res3.cost_upper, "residual": res3.residual}}
+    return psteps, pwarm
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,12 +532,18 @@ def main() -> int:
     ap.add_argument("--precision", type=int, default=HEADLINE_PRECISION, choices=sorted(PRECISION_NAMES),
                     help="form of the headline batch (0 FP32 on the vector ALUs, 1 FP16 split, 2 FP32 on the "
                          "matrix cores); the default is the headline's")
+    ap.add_argument("--plan-only", action="store_true",
+                    help="only the single plan of N = 1000, T = 100, M = 10 in FP32 and, unless --no-mixed, in the "
+                         "FP16 split (e.g. under a profiler); prints those entries alone")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline batch (e.g. under a profiler: every lower_kernel launch is then "
                          "the headline's)")
     args = ap.parse_args()
     if args.headline_only:
         args.no_cpu_baseline = args.no_served = args.no_mixed = args.no_scale = True
+        args.no_mpc = args.no_decoder = args.no_behaviours = True
+    if args.plan_only:
+        args.no_cpu_baseline = args.no_served = args.no_scale = True
         args.no_mpc = args.no_decoder = args.no_behaviours = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): requests are independent, "
@@ -513,6 +558,14 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if args.plan_only:
+        out = {"mixed": {}}
+        c = workload.CONFIGS[PLAN_CFG_ID]
+        plan_legs(pl, torch, workload, c, args, out)
+        if args.copy_probe:
+            copy_probe(torch)
+        print(json.dumps(out), flush=True)
+        return 0
     c5 = workload.CONFIGS[CFG_ID]
     N5, T5, M5, L5, K5 = c5["N"], c5["T"], c5["M"], c5["L"], c5["K"]
     wl5 = f"batch-{HEADLINE_REQUESTS}xN{N5}-T{T5}-M{M5}"
@@ -563,12 +616,7 @@ def main() -> int:
         out["mixed"] = {}
     del reqs5, res5
     if args.copy_probe:
-        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe(torch)
     if args.headline_only:
         print(json.dumps(out), flush=True)
         return 0
@@ -577,26 +625,7 @@ def main() -> int:
     c = workload.CONFIGS[PLAN_CFG_ID]
     N, T, M, L, K = c["N"], c["T"], c["M"], c["L"], c["K"]
     scene = workload.scene(PLAN_CFG_ID, 0, M)
-    psteps, pwarm = max(args.steps, 50), max(args.warmup, 10)
-    print(f"[bench] plan {c['name']} fp32: {pwarm} warm-up + {psteps} timed steps", file=sys.stderr, flush=True)
-    el2, ms2, cnt2, res = time_plan(pl, torch, c, scene, 0, psteps, pwarm)
-    out["c2_plan"] = {
-        "workload": c["name"] + f"-L{L}-K{K}", "value": N * L * psteps / el2, "unit": "QP-solves/s",
-        "ms_per_plan": 1e3 * el2 / psteps,
-        "roofline": roofline(0, ms2["lower"] / max(1, cnt2["lower"]), N, T, M, K, cnt2["lower"], c["name"],
-                             kernel="lower_kernel<1, false>"),
-        "kernel_ms_per_step": {k: ms2[k] / psteps for k in ms2},
-        "plan": {"best_index": res.best_index, "cost_upper": res.cost_upper, "residual": res.residual}}
-    if not args.no_mixed:
-        print("[bench] plan fp16_split", file=sys.stderr, flush=True)
-        el3, ms3, cnt3, res3 = time_plan(pl, torch, c, scene, 1, psteps, pwarm)
-        out["mixed"]["c3_plan"] = {
-            "precision": "fp16_split", "value": N * L * psteps / el3, "unit": "QP-solves/s",
-            "ms_per_plan": 1e3 * el3 / psteps,
-            "roofline": roofline(1, ms3["lower"] / max(1, cnt3["lower"]), N, T, M, K, cnt3["lower"], c["name"],
-                                 kernel="lower_mfma_kernel<2, false, false>"),
-            "kernel_ms_per_step": {k: ms3[k] / psteps for k in ms3},
-            "plan": {"best_index": res3.best_index, "cost_upper": res3.cost_upper, "residual": res3.residual}}
+    psteps, pwarm = plan_legs(pl, torch, workload, c, args, out)
     args.steps, args.warmup = psteps, pwarm  # the C2-based legs below
     if not args.no_behaviours:
         # the other behavioural inputs of eq. behaviour_param on the same scene
