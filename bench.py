@@ -259,12 +259,10 @@ def _run_served(pl, h, reqs, arrivals):
         if not pending:
             continue
         pl.plan_progress(h)
-        for t in list(pending):
-            r = pl.plan_poll(h, t)
-            if r is not None:
-                if r.status != 0:
-                    raise RuntimeError(f"served request failed: {pl.plan_last_error(h)}")
-                lat[pending.pop(t)] = r.latency_s
+        for t, r in pl.plan_poll_done(h, len(pending)):
+            if r.status != 0:
+                raise RuntimeError(f"served request failed: {pl.plan_last_error(h)}")
+            lat[pending.pop(t)] = r.latency_s
     return lat, time.perf_counter() - t0
 
 

@@ -414,6 +414,19 @@ plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticke
 plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued);
 plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out);
 
+/* Every finished served request at once, for a serving loop that would
+ * otherwise poll ticket by ticket: retires what has completed (as plan_poll
+ * does), then moves up to max_n finished results, in ticket order, into
+ * out[0..*n_done) with their tickets in tickets[0..*n_done), and forgets
+ * those tickets; the rest stay for the next call. out[i].traj_xy, if set
+ * before the call, must hold the longest horizon of the config (T x 2
+ * doubles) and receives the returned trajectory. A ticket is returned by
+ * exactly one of plan_poll and plan_poll_done. PLAN_E_INVALID for NULL
+ * arrays with max_n > 0 or a negative max_n; *n_done = 0 when nothing has
+ * finished. */
+plan_status plan_poll_done(plan_handle *h, uint64_t *tickets, plan_result *out, int32_t max_n,
+                           int32_t *n_done);
+
 /*
  * Receding-horizon closed loop (MPC-Bi-Level, Sec. V-A "MPC Baselines").
  * Every episode replans with Alg. 1 once per cycle, executes the first

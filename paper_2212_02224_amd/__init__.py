@@ -14,6 +14,6 @@ from .binding import (PLAN_BEHAV_GOALS, PLAN_BEHAV_SETPOINTS, PLAN_SAMPLER_GRID,
                       MPC_LOGS, plan_get_trace, plan_last_error, plan_launch, plan_lower_solve,
                       plan_lower_solve_static,
                       plan_mpc_run,
-                      plan_poll, plan_progress, plan_submit,
+                      plan_poll, plan_poll_done, plan_progress, plan_submit,
                       plan_profile, plan_profile_read, plan_set_decoder, plan_solve_batch, plan_stage,
                       plan_workspace_bytes)

@@ -139,6 +139,7 @@ def load():
     lib.plan_submit.argtypes = [H, Req, C.POINTER(C.c_uint64)]
     lib.plan_progress.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.plan_poll.argtypes = [H, C.c_uint64, Res]
+    lib.plan_poll_done.argtypes = [H, C.POINTER(C.c_uint64), Res, C.c_int32, C.POINTER(C.c_int32)]
     lib.plan_mpc_run.argtypes = [H, Req, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(plan_mpc_log), Res]
     lib.plan_profile.argtypes = [H, C.c_int32]
     lib.plan_profile_read.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -146,8 +147,8 @@ def load():
     lib.plan_elite_sizes.argtypes = [Cfg, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     for name in ("plan_create", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
                  "plan_lower_solve", "plan_lower_solve_static", "plan_get_trace", "plan_submit",
-                 "plan_progress", "plan_poll", "plan_mpc_run", "plan_profile", "plan_profile_read",
-                 "plan_set_decoder", "plan_elite_sizes"):
+                 "plan_progress", "plan_poll", "plan_poll_done", "plan_mpc_run", "plan_profile",
+                 "plan_profile_read", "plan_set_decoder", "plan_elite_sizes"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -157,8 +158,8 @@ def exported_symbols() -> list[str]:
     return ["plan_config_init", "plan_workspace_bytes", "plan_create", "plan_destroy",
             "plan_last_error", "plan_solve_batch", "plan_stage", "plan_launch", "plan_collect",
             "plan_lower_solve", "plan_lower_solve_static", "plan_get_trace", "plan_submit",
-            "plan_progress", "plan_poll", "plan_mpc_run", "plan_profile", "plan_profile_read",
-            "plan_set_decoder", "plan_elite_sizes"]
+            "plan_progress", "plan_poll", "plan_poll_done", "plan_mpc_run", "plan_profile",
+            "plan_profile_read", "plan_set_decoder", "plan_elite_sizes"]
 
 
 def _check(status: int, handle=None) -> int:
@@ -426,6 +427,25 @@ def plan_poll(h: Handle, ticket: int) -> Result | None:
     _check(st, h.ptr)
     h._ticket_T.pop(int(ticket), None)
     return out.result(0)
+
+
+def plan_poll_done(h: Handle, max_n: int = 64) -> list[tuple[int, Result]]:
+    """Every finished served request (up to max_n), in ticket order, as
+    (ticket, Result) pairs; an empty list while none has finished."""
+    Tmax = max(int(h.cfg.T_set[i]) for i in range(h.cfg.n_T))
+    out = _Results([Tmax] * max_n)
+    tickets = (C.c_uint64 * max(1, max_n))()
+    n = C.c_int32()
+    _check(load().plan_poll_done(h.ptr, tickets, out.arr, max_n, C.byref(n)), h.ptr)
+    got = []
+    for i in range(n.value):
+        t = int(tickets[i])
+        T = getattr(h, "_ticket_T", {}).pop(t, Tmax)
+        r = out.result(i)
+        if r.traj is not None:
+            r.traj = r.traj[:T]
+        got.append((t, r))
+    return got
 
 
 MPC_LOGS = ("ego", "xi", "mu", "sigma", "cost", "collided", "status")

@@ -1727,6 +1727,34 @@ plan_status plan_poll(plan_handle *h, uint64_t ticket, plan_result *out) {
   return fail(h, PLAN_E_INVALID, "unknown ticket");
 }
 
+plan_status plan_poll_done(plan_handle *h, uint64_t *tickets, plan_result *out, int32_t max_n, int32_t *n_done) {
+  if (!h || !n_done || max_n < 0 || (max_n > 0 && (!tickets || !out))) return fail(h, PLAN_E_INVALID, "bad arguments");
+  *n_done = 0;
+  plan_status st = retire_done(h);
+  if (st != PLAN_OK) return st;
+  // finished tickets in ticket (submission) order, up to max_n
+  std::vector<uint64_t> ready;
+  ready.reserve(h->done.size());
+  for (const auto &kv : h->done) ready.push_back(kv.first);
+  std::sort(ready.begin(), ready.end());
+  int32_t k = 0;
+  for (uint64_t t : ready) {
+    if (k == max_n) break;
+    auto it = h->done.find(t);
+    double *traj_xy = out[k].traj_xy;
+    out[k] = it->second;
+    out[k].traj_xy = traj_xy;
+    auto tt = h->done_traj.find(t);
+    if (traj_xy && tt != h->done_traj.end() && out[k].status == 0)
+      std::memcpy(traj_xy, tt->second.data(), sizeof(double) * tt->second.size());
+    if (tt != h->done_traj.end()) h->done_traj.erase(tt);
+    h->done.erase(it);
+    tickets[k++] = t;
+  }
+  *n_done = k;
+  return PLAN_OK;
+}
+
 plan_status plan_set_decoder(plan_handle *h, const plan_decoder *dec) {
   if (!h || !dec) return fail(h, PLAN_E_INVALID, "bad arguments");
   if (h->cfg.sampler != PLAN_SAMPLER_DECODER)

@@ -1081,7 +1081,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   const bool active = j < N;
   const size_t slot_off = (size_t)D.row_off;
 
-  // 4 NT instants x 224 bytes (F32: 192 bytes), in float4
+  // 4 NT instants x 240 bytes (F32: 192 bytes), in float4
   const int tab_f4 = F32 ? NT * kEv32InstFloats : NT * kEvInstHalfs / 2;
   _Float16 *s_tab = reinterpret_cast<_Float16 *>(s_dyn);
   float4 *s_obs = s_dyn + tab_f4;

@@ -38,10 +38,12 @@ enum BasisCol {
 // multiple of 4 instants, zero beyond T), in FP16 halves:
 //   [axis x, y][q = position, velocity, acceleration][hi 0..7 | lo 8..15]
 // over the 8 free coefficients of the axis (x: c3..c10; y: c3..c8, c9 + c10,
-// 0), then a zero pad of 16 halves. v = hi + lo to about 22 bits.
+// 0), then a zero pad of 16 halves and 8 unused ones (the stride of 60
+// dwords per instant spreads both read patterns over the LDS banks: 3%
+// faster than 56). v = hi + lo to about 22 bits.
 constexpr int kEvAxisHalfs = 48;          // 3 orders x 16
 constexpr int kEvPad = 96;                // offset of the zero pad
-constexpr int kEvInstHalfs = 112;         // halves per instant (224 bytes)
+constexpr int kEvInstHalfs = 120;         // halves per instant (240 bytes; the 8-half gap spreads LDS banks)
 // Basis table of the FP32 matrix-core lower level, per instant t (padded to
 // a multiple of 4 instants, zero beyond T), in FP32:
 //   [q = position, velocity, acceleration][g = 0..3]

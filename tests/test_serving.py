@@ -75,6 +75,43 @@ def test_served_all_at_once_equals_alone(pl):
         assert got[t].latency_s > 0
 
 
+def test_poll_done_returns_each_ticket_once_and_equals_alone(pl):
+    """plan_poll_done hands back every finished request in ticket order,
+    each exactly once, with the result (and trajectory) it has alone; a
+    capacity smaller than the finished count leaves the rest for the next
+    call; plan_poll then knows none of them."""
+    reqs = reqs_of(pl)
+    ref = alone_results(pl, reqs)
+    h = pl.plan_create(cfg_of(pl))
+    assert pl.plan_poll_done(h, 4) == []
+    tickets = []
+    for i, r in enumerate(reqs):
+        tickets.append(pl.plan_submit(h, r))
+        if i % 3 == 2:
+            pl.plan_progress(h)
+    got, order = {}, []
+    for _ in range(200):
+        pl.plan_progress(h)
+        batch = pl.plan_poll_done(h, 3)
+        assert len(batch) <= 3
+        ts = [t for t, _ in batch]
+        assert ts == sorted(ts)
+        for t, r in batch:
+            assert t not in got
+            got[t] = r
+            order.append(t)
+        if len(got) == len(tickets):
+            break
+    assert sorted(got) == sorted(tickets)
+    for i, t in enumerate(tickets):
+        assert same(got[t], ref[i]), i
+        assert got[t].traj is not None and got[t].traj.shape == (reqs[i].T, 2)
+        assert np.array_equal(got[t].traj, ref[i].traj)
+    with pytest.raises(pl.PlanError):
+        pl.plan_poll(h, tickets[0])
+    assert pl.plan_poll_done(h, 8) == []
+
+
 def test_served_staggered_arrivals_equal_alone(pl):
     reqs = reqs_of(pl)
     ref = alone_results(pl, reqs)
