@@ -482,6 +482,25 @@ def copy_probe(torch):
     torch.cuda.synchronize()
 
 
+def decoder_legs(pl, torch, workload, c, scene, steps, warmup):
+    """The single plan with iteration 0 drawn by the decoder sampler (App. A
+    decoder MLP, random weights of the paper's sizes), FP32 and FP16 split."""
+    N, L = c["N"], c["L"]
+    res = {}
+    dec = workload.decoder_weights(0)
+    for name, prec in (("f32", 0), ("fp16_split", 1)):
+        print(f"[bench] plan from the decoder sampler, {name}", file=sys.stderr, flush=True)
+        eld, msd, cntd, resd = time_plan(pl, torch, c, scene, prec, steps, warmup, decoder=dec)
+        dms = msd["decoder"] / max(1, cntd["decoder"])
+        res[name] = {
+            "value": N * L * steps / eld, "unit": "QP-solves/s", "ms_per_plan": 1e3 * eld / steps,
+            "decoder_ms_per_plan": dms, "lower_avg_ms": msd["lower"] / max(1, cntd["lower"]),
+            "decoder_alg_tflops": N * DECODER_FLOPS / (dms * 1e-3) / 1e12,
+            "decoder_mfma_frac": N * DECODER_MFMA_FLOPS / (dms * 1e-3) / 2.5e15,
+            "plan": {"best_index": resd.best_index, "cost_upper": resd.cost_upper, "residual": resd.residual}}
+    return res
+
+
 def plan_legs(pl, torch, workload, c, args, out):
     """The single plan (the latency case) in FP32 and, unless --no-mixed, in
     the FP16 split, into out["c2_plan"] and out["mixed"]["c3_plan"]; returns
@@ -533,6 +552,9 @@ def main() -> int:
     ap.add_argument("--plan-only", action="store_true",
                     help="only the single plan of N = 1000, T = 100, M = 10 in FP32 and, unless --no-mixed, in the "
                          "FP16 split (e.g. under a profiler); prints those entries alone")
+    ap.add_argument("--decoder-only", action="store_true",
+                    help="only the single plan drawn by the decoder sampler, FP32 then FP16 split (e.g. under a "
+                         "profiler); prints that entry alone")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline batch (e.g. under a profiler: every lower_kernel launch is then "
                          "the headline's)")
@@ -556,6 +578,14 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if args.decoder_only:
+        c = workload.CONFIGS[PLAN_CFG_ID]
+        out = {"decoder": decoder_legs(pl, torch, workload, c, workload.scene(PLAN_CFG_ID, 0, c["M"]),
+                                       max(args.steps, 50), max(args.warmup, 10))}
+        if args.copy_probe:
+            copy_probe(torch)
+        print(json.dumps(out), flush=True)
+        return 0
     if args.plan_only:
         out = {"mixed": {}}
         c = workload.CONFIGS[PLAN_CFG_ID]
@@ -660,20 +690,7 @@ def main() -> int:
             print(f"[bench] closed loop {name}: {eps} episodes x {cyc} cycles", file=sys.stderr, flush=True)
             out["mpc"][name] = mpc_bench(pl, workload, torch, prec, eps, cyc, c=c, init=init)
     if not args.no_decoder:
-        # the decoder sampler (App. A decoder MLP, random weights) drawing
-        # iteration 0 of the headline plan
-        out["decoder"] = {}
-        dec = workload.decoder_weights(0)
-        for name, prec in (("f32", 0), ("fp16_split", 1)):
-            print(f"[bench] plan from the decoder sampler, {name}", file=sys.stderr, flush=True)
-            eld, msd, cntd, resd = time_plan(pl, torch, c, scene, prec, args.steps, args.warmup, decoder=dec)
-            dms = msd["decoder"] / max(1, cntd["decoder"])
-            out["decoder"][name] = {
-                "value": N * L * args.steps / eld, "unit": "QP-solves/s", "ms_per_plan": 1e3 * eld / args.steps,
-                "decoder_ms_per_plan": dms, "lower_avg_ms": msd["lower"] / max(1, cntd["lower"]),
-                "decoder_alg_tflops": N * DECODER_FLOPS / (dms * 1e-3) / 1e12,
-                "decoder_mfma_frac": N * DECODER_MFMA_FLOPS / (dms * 1e-3) / 2.5e15,
-                "plan": {"best_index": resd.best_index, "cost_upper": resd.cost_upper, "residual": resd.residual}}
+        out["decoder"] = decoder_legs(pl, torch, workload, c, scene, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         print("[bench] FP64 oracle on the host cores, and its accuracy check", file=sys.stderr, flush=True)
         out.update(cpu_baseline_leg(pl, workload))

@@ -52,15 +52,28 @@ __device__ __forceinline__ void split_act(float v, _Float16 &hi, _Float16 &lo) {
 
 // Tile of this workgroup, XCD-aware: workgroups are dispatched round-robin
 // over the 8 XCDs (each with its own L2), so workgroup b runs on XCD b % 8.
-// Logical tiles are dealt to XCDs in contiguous ranges (n fastest, then
-// rows), so the workgroups sharing an activation row block sit on one L2;
-// the remainder of the grid keeps the identity map.
-__device__ __forceinline__ void xcd_tile(int &tx, int &ty) {
-  const int T = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+// split2d (the 1024 -> 1024 layers, whose weights and activations are about
+// the same size) and a tile grid that splits evenly: XCD x takes one block
+// of a 4 x 2 split of the grid (a quarter of the output features, half of
+// the rows), so each L2 reads a quarter of the weights and half of the
+// activations instead of all the weights (measured: 37.8 -> 24 MB fetched
+// per layer at 1000 rows). Otherwise logical tiles go to XCDs in contiguous
+// ranges (n fastest, then rows), which keeps each XCD on its own rows: best
+// where the weights are the smaller operand. The remainder of the grid keeps
+// the identity map. Tiles are independent: the map changes where a tile
+// runs, not its result.
+__device__ __forceinline__ void xcd_tile(bool split2d, int &tx, int &ty) {
+  const int gx = gridDim.x, gy = gridDim.y, T = gx * gy, b = blockIdx.y * gx + blockIdx.x;
+  if (split2d && gx % 4 == 0 && gy % 2 == 0) {
+    const int x = b % 8, i = b / 8, qx = gx / 4, hy = gy / 2;
+    tx = (x % 4) * qx + i % qx;
+    ty = (x / 4) * hy + i / qx;
+    return;
+  }
   const int per = T / 8;
   const int t = b < 8 * per ? (b % 8) * per + b / 8 : b;
-  tx = t % gridDim.x;
-  ty = t / gridDim.x;
+  tx = t % gx;
+  ty = t / gx;
 }
 
 // Operand layout of the matrix-core layers ("fragment-major"): a matrix of
@@ -132,7 +145,7 @@ __global__ void __launch_bounds__(kWave *(KSPLIT > 4 ? KSPLIT : 4)) dec_gemm_ker
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   int tx, ty;
-  xcd_tile(tx, ty);
+  xcd_tile(Ly.n_in == Ly.n_out, tx, ty);
   const int wn = KSPLIT == 1 ? (wave & 1) : 0, wm = KSPLIT == 1 ? (wave >> 1) : 0;
   const int n_base = (tx * (KSPLIT == 1 ? 2 : 1) + wn) * 16 * TN;
   const int m_base = (ty * (KSPLIT == 1 ? 2 : 1) + wm) * 16 * TM;
