@@ -63,7 +63,8 @@ typedef enum plan_status {
   PLAN_E_NOMEM = -2,       /* workspace / HBM budget too small               */
   PLAN_E_DEVICE = -3,      /* HIP runtime error                              */
   PLAN_E_BUSY = -4,        /* plan_poll: not finished yet                    */
-  PLAN_E_UNSUPPORTED = -5  /* configuration the library does not implement   */
+  PLAN_E_UNSUPPORTED = -5, /* configuration the library does not implement   */
+  PLAN_E_TIMEOUT = -6      /* a bounded device-side wait gave up (fused_iters) */
 } plan_status;
 
 /* plan_result.flags */
@@ -155,6 +156,26 @@ typedef enum plan_sampler_t {
  *                   joins it. Larger values keep the GPU busier (more
  *                   throughput) but a new request waits behind the
  *                   iterations already enqueued (more latency).
+ *   fused_iters     PLAN_PREC_FP32 only, 0 (the default) or 1. 1: all L
+ *                   upper iterations of a launch group in one launch; the
+ *                   selection and update of each request run on the device
+ *                   by the workgroup that finishes its last samples, and the
+ *                   request's next iteration starts as soon as its update
+ *                   has run (no per-iteration launches or host round trips).
+ *                   Results are bitwise those of the per-iteration launches.
+ *                   Measured on MI355X it is slower than back-to-back
+ *                   per-iteration launches (whose gaps are about a
+ *                   microsecond): the workgroups' device-scope release and
+ *                   acquire across the eight L2 caches and the selection's
+ *                   registers cost more than the launches save. In served
+ *                   mode with fused_iters = 1 each plan_progress call
+ *                   enqueues the whole solve of the requests it admits
+ *                   (served_run_ahead is then unused).
+ *   fused_wait_us   bound on how long a workgroup of a fused launch waits
+ *                   for an update before it gives up (default 1 s, far
+ *                   above any real wait); the requests whose updates did
+ *                   not all run then fail with PLAN_E_TIMEOUT, and the
+ *                   launch still ends.
  *   proj_iters      K, iterations of Alg. 2 (its maxiter).
  *   upper_iters     L, iterations of Alg. 1 (its N).
  *   frac_ces/es     n = max(q, round(frac_ces N)), q = max(1, round(frac_es N))
@@ -198,6 +219,8 @@ typedef struct plan_config {
   int32_t behaviour; /* plan_behaviour */
   int32_t sampler;   /* plan_sampler_t: initial sampler */
   int32_t served_run_ahead; /* served mode: iterations enqueued ahead (0..3) */
+  int32_t fused_iters;   /* 1: every upper iteration of a launch group in one launch */
+  int32_t fused_wait_us; /* bound of a device-side wait of the fused launch [us] */
   int64_t sample_budget; /* sample rows resident at once (0: max_requests * max_N) */
   void *device_workspace;
   size_t workspace_bytes;

@@ -6,7 +6,7 @@ The planner runs as HIP kernels in ``libplan.so`` behind the C ABI of
 """
 from .binding import (PLAN_BEHAV_GOALS, PLAN_BEHAV_SETPOINTS, PLAN_SAMPLER_GRID,  # noqa: F401
                       PLAN_SAMPLER_DECODER, PLAN_OBS_DIM, PLAN_SAMPLER_RANDOM, PLAN_E_BUSY, PLAN_E_DEVICE, PLAN_E_INVALID, PLAN_E_NOMEM,
-                      PLAN_E_UNSUPPORTED, PLAN_F_INFEASIBLE, PLAN_F_WARM, PLAN_MPC_SAMPLER,
+                      PLAN_E_TIMEOUT, PLAN_E_UNSUPPORTED, PLAN_F_INFEASIBLE, PLAN_F_WARM, PLAN_MPC_SAMPLER,
                       PLAN_MAX_ROAD, PLAN_MPC_WARM, PLAN_OK,
                       PLAN_PREC_FP16_SPLIT, PLAN_PREC_FP32, PLAN_PREC_FP32_MFMA, Handle,
                       PlanError, Request, Result, elite_sizes, exported_symbols, load,

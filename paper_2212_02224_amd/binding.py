@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libplan.so")
 
 PLAN_OK, PLAN_E_INVALID, PLAN_E_NOMEM, PLAN_E_DEVICE, PLAN_E_BUSY, PLAN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+PLAN_E_TIMEOUT = -6
 PLAN_PREC_FP32, PLAN_PREC_FP16_SPLIT, PLAN_PREC_FP32_MFMA = 0, 1, 2
 PLAN_F_INFEASIBLE, PLAN_F_WARM = 1, 2
 PLAN_MPC_SAMPLER, PLAN_MPC_WARM = 0, 1
@@ -53,6 +54,7 @@ class plan_config(C.Structure):
         ("lane_sigma", C.c_double), ("vd_lo", C.c_double), ("vd_hi", C.c_double),
         ("precision", C.c_int32), ("trace", C.c_int32),
         ("behaviour", C.c_int32), ("sampler", C.c_int32), ("served_run_ahead", C.c_int32),
+        ("fused_iters", C.c_int32), ("fused_wait_us", C.c_int32),
         ("sample_budget", C.c_int64),
         ("device_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("stream", C.c_void_p),

@@ -35,6 +35,9 @@ hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblo
                              int T, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_select(const SelArgs &a, const MethodParams &p, int nreq, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1);
+hipError_t launch_lower_fused(const LowerArgs &a, const SelArgs &sa, const MethodParams &p, uint32_t *ctl,
+                              int nblocks, int ipl, bool road, size_t obs_lds, uint64_t wait_ticks, hipStream_t st,
+                              hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_advance(const AdvArgs &a, const MethodParams &p, int n, hipStream_t st);
 hipError_t launch_decoder(const DecArgs &a, int total_rows, int n_cu, hipStream_t st, hipEvent_t ev0,
                           hipEvent_t ev1);
@@ -137,13 +140,13 @@ struct DevBuf {
 // Device bytes of every region, in allocation order.
 struct Layout {
   size_t basis = 0, step1 = 0, proj = 0, offs = 0, mops = 0, mainv = 0;
-  size_t desc = 0, dist = 0, result = 0, traj = 0, act = 0;
+  size_t desc = 0, dist = 0, result = 0, traj = 0, act = 0, fctl = 0;
   size_t p = 0, zs = 0, rc = 0, sess = 0, xiout = 0;
   size_t tr_p = 0, tr_rc = 0, tr_idx = 0, tr_dist = 0;
   size_t dec_tab = 0, dec_act = 0, dec_seg = 0;  // decoder sampler
   size_t total() const {
     size_t s = 0;
-    for (size_t b : {basis, step1, proj, offs, mops, mainv, desc, dist, result, traj, act, p, zs, rc, sess, xiout,
+    for (size_t b : {basis, step1, proj, offs, mops, mainv, desc, dist, result, traj, act, fctl, p, zs, rc, sess, xiout,
                      tr_p, tr_rc, tr_idx, tr_dist, dec_tab, dec_act, dec_seg})
       s += (b + 255) & ~(size_t)255;
     return s;
@@ -202,6 +205,7 @@ Layout compute_layout(const plan_config &c) {
   L.result = S * sizeof(ResultRec);
   L.traj = S * (size_t)traj_stride(c) * 2 * 8;
   L.act = (2 * S + 8) * 4;
+  L.fctl = (4 + 2 * S) * 4;
   L.p = R * 8 * 4;
   L.zs = R * kZ * 4;
   L.rc = R * 2 * 4;
@@ -251,6 +255,8 @@ const char *validate_config(const plan_config &c) {
   if (c.sampler != PLAN_SAMPLER_RANDOM && c.sampler != PLAN_SAMPLER_GRID && c.sampler != PLAN_SAMPLER_DECODER)
     return "unknown sampler";
   if (c.served_run_ahead < 0 || c.served_run_ahead > kRing - 1) return "served_run_ahead must be in [0, 3]";
+  if (c.fused_iters < 0 || c.fused_iters > 1) return "fused_iters must be 0 or 1";
+  if (c.fused_iters != 0 && c.fused_wait_us < 1) return "fused_wait_us must be >= 1";
   if (c.behaviour == PLAN_BEHAV_GOALS && !(c.w_s > 0)) return "goal positions need w_s > 0 (the cost is c_s alone)";
   if (c.precision != PLAN_PREC_FP32 && c.precision != PLAN_PREC_FP16_SPLIT && c.precision != PLAN_PREC_FP32_MFMA)
     return "unsupported precision";
@@ -316,6 +322,8 @@ struct plan_handle {
   double *traj = nullptr;  // [slot][traj_stride][2] positions of the returned trajectory
   int traj_T = 0;          // traj_stride of the config
   int32_t *act_slots = nullptr, *blk_prefix = nullptr;
+  uint32_t *fctl = nullptr;  // control words of the fused launches (zero between launches)
+  int wall_khz = 100000;     // device wall clock [kHz] (the fused launches' wait bound)
   float *p = nullptr, *zs = nullptr, *resid = nullptr, *cost = nullptr;
   double *sess = nullptr;
   double *xi_out = nullptr;
@@ -722,26 +730,33 @@ plan_status upload_launch_set(plan_handle *h, const LaunchSet &ls) {
   return PLAN_OK;
 }
 
+// Lower-level launch of group k of a launch set at upper iteration l_uniform
+// (-1: each slot's cur_iter).
+plan_status launch_lower_group(plan_handle *h, const LaunchSet &ls, int k, int l_uniform, double *xi_bar,
+                               double *xi_star) {
+  const LaunchSet::Group &gr = ls.grp[k];
+  LowerArgs la = lower_args(h, gr.n, l_uniform);
+  la.act_slots += gr.act_off;
+  la.blk_prefix += gr.act_off + k;
+  la.xi_bar_out = xi_bar;
+  la.xi_star_out = xi_star;
+  const bool mf = mfma_mode(h->cfg);
+  return timed(
+      h, 0,
+      [&](hipEvent_t a, hipEvent_t b) {
+        // two tiles per wave while a launch cannot fill every CU with two
+        // workgroups, else four (same arithmetic either way)
+        const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
+        return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds,
+                                      h->stream, a, b)
+                  : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, a, b);
+      },
+      mf ? "lower_mfma_kernel" : "lower_kernel");
+}
+
 plan_status launch_lower_set(plan_handle *h, const LaunchSet &ls, int l_uniform, double *xi_bar, double *xi_star) {
   for (int k = 0; k < ls.ngroups; ++k) {
-    const LaunchSet::Group &gr = ls.grp[k];
-    LowerArgs la = lower_args(h, gr.n, l_uniform);
-    la.act_slots += gr.act_off;
-    la.blk_prefix += gr.act_off + k;
-    la.xi_bar_out = xi_bar;
-    la.xi_star_out = xi_star;
-    const bool mf = mfma_mode(h->cfg);
-    plan_status st = timed(
-        h, 0,
-        [&](hipEvent_t a, hipEvent_t b) {
-          // two tiles per wave while a launch cannot fill every CU with two
-          // workgroups, else four (same arithmetic either way)
-          const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
-          return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds,
-                                        h->stream, a, b)
-                    : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, a, b);
-        },
-        mf ? "lower_mfma_kernel" : "lower_kernel");
+    plan_status st = launch_lower_group(h, ls, k, l_uniform, xi_bar, xi_star);
     if (st != PLAN_OK) return st;
   }
   return PLAN_OK;
@@ -756,6 +771,38 @@ plan_status launch_iteration(plan_handle *h, const LaunchSet &ls, int l_uniform)
     st = timed(
         h, 1, [&](hipEvent_t a, hipEvent_t b) { return launch_select(sa, h->mp, ls.n_act, h->stream, a, b); },
         "select_update_kernel");
+  }
+  return st;
+}
+
+// Do the launch groups run as fused launches (fused_iters)? Only the FP32
+// vector-ALU lower level has the fused form.
+bool fused_mode(const plan_config &c) { return c.fused_iters != 0 && !mfma_mode(c); }
+
+// Every upper iteration of a launch set (arrays on the device, decoder
+// samples launched), all slots from iteration 0: one lower-level and one
+// selection launch per iteration, or (fused_iters) one fused launch per
+// launch group.
+plan_status launch_solve(plan_handle *h, const LaunchSet &ls) {
+  plan_status st = PLAN_OK;
+  if (!fused_mode(h->cfg)) {
+    for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) st = launch_iteration(h, ls, l);
+    return st;
+  }
+  const uint64_t wait_ticks = (uint64_t)h->cfg.fused_wait_us * (uint64_t)h->wall_khz / 1000u;
+  for (int k = 0; st == PLAN_OK && k < ls.ngroups; ++k) {
+    const LaunchSet::Group &gr = ls.grp[k];
+    LowerArgs la = lower_args(h, gr.n, -1);
+    la.act_slots += gr.act_off;
+    la.blk_prefix += gr.act_off + k;
+    const SelArgs sa = sel_args(h, -1);
+    st = timed(
+        h, 0,
+        [&](hipEvent_t a, hipEvent_t b) {
+          return launch_lower_fused(la, sa, h->mp, h->fctl, gr.nblocks, gr.ipl, gr.road, gr.lds, wait_ticks,
+                                    h->stream, a, b);
+        },
+        "lower_fused_kernel");
   }
   return st;
 }
@@ -854,14 +901,8 @@ plan_status launch_dec_segments(plan_handle *h) {
 
 plan_status launch_impl(plan_handle *h) {
   if (h->staged == 0) return PLAN_OK;
-  plan_status st = PLAN_OK;
-  for (int l = 0; st == PLAN_OK && l < h->cfg.upper_iters; ++l) {
-    if (l == 0) {
-      st = launch_dec_segments(h);  // table uploaded at staging
-      if (st != PLAN_OK) break;
-    }
-    st = launch_iteration(h, h->ls, l);
-  }
+  plan_status st = launch_dec_segments(h);  // table uploaded at staging
+  if (st == PLAN_OK) st = launch_solve(h, h->ls);
   return st;
 }
 
@@ -909,6 +950,9 @@ plan_status collect_impl(plan_handle *h, plan_result *out, double elapsed) {
   for (int s = 0; s < h->staged; ++s) {
     plan_result &o = out[h->staged_req[s]];
     fill_result(o, h->h_result[s], h->h_dist[s], elapsed, h->h_traj + (size_t)s * 2 * h->traj_T, h->h_desc[s].T);
+    if (o.status == PLAN_E_TIMEOUT)
+      h->err = "fused launch: a device-side wait exceeded fused_wait_us; requests whose iterations did not all run "
+               "failed with PLAN_E_TIMEOUT";
     if (o.status != 0) worst = std::min(worst, (plan_status)o.status);
     else if (h->h_desc[s].session_wb >= 0) h->sess_valid[h->h_desc[s].session_wb] = 1;
   }
@@ -1090,6 +1134,8 @@ void plan_config_init(plan_config *c) {
   c->vd_lo = 5.0;
   c->vd_hi = 25.0;
   c->precision = PLAN_PREC_FP32;
+  c->fused_iters = 0;
+  c->fused_wait_us = 1000000;
 }
 
 size_t plan_workspace_bytes(const plan_config *cfg) {
@@ -1183,6 +1229,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
   h->traj = (double *)h->mem.take(L.traj);
   h->act_slots = (int32_t *)h->mem.take(L.act);
   h->blk_prefix = h->act_slots + S;
+  h->fctl = (uint32_t *)h->mem.take(L.fctl);
   h->p = (float *)h->mem.take(L.p);
   h->zs = (float *)h->mem.take(L.zs);
   h->resid = (float *)h->mem.take(L.rc);
@@ -1213,7 +1260,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     for (int i = 0; i < 4; ++i) h->dec_act[i] = (uint16_t *)h->mem.take((size_t)chunk * kDecHidden * 2);
     h->dec_seg = (DecSeg *)h->mem.take(L.dec_seg);
   }
-  if (!h->xi_out || (c.trace && !h->tr_mu) || (c.sampler == PLAN_SAMPLER_DECODER && !h->dec_seg)) {
+  if (!h->xi_out || !h->fctl || (c.trace && !h->tr_mu) || (c.sampler == PLAN_SAMPLER_DECODER && !h->dec_seg)) {
     g_create_error = "internal: workspace carve failed";
     free_handle(h);
     return PLAN_E_NOMEM;
@@ -1232,6 +1279,9 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     if (e == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         cus > 0)
       h->n_cu = cus;
+    int khz = 0;
+    if (e == hipSuccess && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      h->wall_khz = khz;
     h->device = dev;
     // the static scratch array's address on this device (once per device)
     if (e == hipSuccess) e = static_scratch_init(dev, &h->scr);
@@ -1291,6 +1341,7 @@ plan_status plan_create(const plan_config *cfg, plan_handle **out) {
     if (e == hipSuccess && h->mainv)
       e = hipMemcpyAsync(h->mainv, mainv_all.data(), mainv_all.size() * 2, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->sess, 0, L.sess, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->fctl, 0, L.fctl, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   }
   if (e != hipSuccess) {
@@ -1618,9 +1669,86 @@ plan_status plan_submit(plan_handle *h, const plan_request *req, uint64_t *ticke
   return PLAN_OK;
 }
 
+// Result copies of a served request whose last iteration is enqueued, and
+// its move to the retiring list (retired by retire_done once the copies
+// have arrived).
+plan_status enqueue_retire(plan_handle *h, const Resident &rs) {
+  HIP_TRY(h, hipMemcpyAsync(h->h_result + rs.slot, h->result + rs.slot, sizeof(ResultRec), hipMemcpyDeviceToHost,
+                            h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->h_dist + rs.slot, h->dist + rs.slot, sizeof(DistState), hipMemcpyDeviceToHost,
+                            h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->h_traj + (size_t)rs.slot * 2 * h->traj_T, h->traj + (size_t)rs.slot * 2 * h->traj_T,
+                            sizeof(double) * 2 * rs.T, hipMemcpyDeviceToHost, h->stream));
+  Retiring rt;
+  rt.rs = rs;
+  if (!h->sync_ev_free.empty()) {
+    rt.ev = h->sync_ev_free.back();
+    h->sync_ev_free.pop_back();
+  } else {
+    HIP_TRY(h, hipEventCreateWithFlags(&rt.ev, hipEventDisableTiming));
+  }
+  HIP_TRY(h, hipEventRecord(rt.ev, h->stream));
+  h->retiring.push_back(rt);
+  return PLAN_OK;
+}
+
+// Served mode with fused iterations: each call enqueues the whole solve of
+// the requests it admits (one launch set, every iteration), so a request's
+// iterations follow each other on the device without host ticks. At most
+// kRing such solves are in flight (the pinned launch arrays of the one
+// enqueued kRing calls ago are reused once it has finished).
+plan_status progress_fused(plan_handle *h, int32_t *n_active, int32_t *n_queued) {
+  if (h->tick >= kRing) HIP_TRY(h, hipEventSynchronize(h->ring_ev[(h->tick - kRing) % kRing]));
+  plan_status st = retire_done(h);
+  if (st != PLAN_OK) return st;
+  std::vector<int> admitted;
+  admit_queued(h, admitted);
+  if (admitted.empty() && !h->retiring.empty()) {
+    // nothing to launch: wait for the oldest result instead (the stream
+    // completes them in order), so that every call makes progress
+    HIP_TRY(h, hipEventSynchronize(h->retiring.front().ev));
+    st = retire_done(h);
+    if (st != PLAN_OK) return st;
+    admit_queued(h, admitted);
+  }
+  if (!admitted.empty()) {
+    std::sort(admitted.begin(), admitted.end());
+    for (size_t a = 0; a < admitted.size();) {
+      size_t b = a + 1;
+      while (b < admitted.size() && admitted[b] == admitted[b - 1] + 1) ++b;
+      HIP_TRY(h, hipMemcpyAsync(h->desc + admitted[a], h->h_desc + admitted[a], sizeof(ReqDesc) * (b - a),
+                                hipMemcpyHostToDevice, h->stream));
+      a = b;
+    }
+    const int rg = (int)(h->tick % kRing);
+    h->h_act = h->h_act_ring[rg];
+    h->h_seg = h->h_seg_ring[rg];
+    LaunchSet ls;
+    make_launch_set(h, admitted.data(), (int)admitted.size(), ls);
+    st = upload_launch_set(h, ls);
+    if (st == PLAN_OK) st = upload_dec_segments(h, admitted.data(), (int)admitted.size());
+    if (st == PLAN_OK) st = launch_dec_segments(h);
+    if (st == PLAN_OK) st = launch_solve(h, ls);
+    if (st != PLAN_OK) return st;
+    HIP_TRY(h, hipEventRecord(h->ring_ev[rg], h->stream));
+    ++h->tick;
+    for (int i = (int)h->resident.size() - 1; i >= 0; --i) {
+      Resident &rs = h->resident[i];
+      rs.iters = h->cfg.upper_iters;
+      st = enqueue_retire(h, rs);
+      if (st != PLAN_OK) return st;
+      h->resident.erase(h->resident.begin() + i);
+    }
+  }
+  if (n_active) *n_active = (int32_t)(h->resident.size() + h->retiring.size());
+  if (n_queued) *n_queued = (int32_t)h->queue.size();
+  return PLAN_OK;
+}
+
 plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) {
   if (!h) return PLAN_E_INVALID;
   h->staged = 0;  // batch slots are reused
+  if (fused_mode(h->cfg)) return progress_fused(h, n_active, n_queued);
   // Run-ahead limit: tick t is enqueued once tick t - 1 - run_ahead has
   // finished (which also frees ring entry t % kRing, last used by tick
   // t - kRing).
@@ -1678,22 +1806,8 @@ plan_status plan_progress(plan_handle *h, int32_t *n_active, int32_t *n_queued) 
     for (int i = n_act - 1; i >= 0; --i) {
       Resident &rs = h->resident[i];
       if (++rs.iters < h->cfg.upper_iters) continue;
-      HIP_TRY(h, hipMemcpyAsync(h->h_result + rs.slot, h->result + rs.slot, sizeof(ResultRec),
-                                hipMemcpyDeviceToHost, h->stream));
-      HIP_TRY(h, hipMemcpyAsync(h->h_dist + rs.slot, h->dist + rs.slot, sizeof(DistState), hipMemcpyDeviceToHost,
-                                h->stream));
-      HIP_TRY(h, hipMemcpyAsync(h->h_traj + (size_t)rs.slot * 2 * h->traj_T, h->traj + (size_t)rs.slot * 2 * h->traj_T,
-                                sizeof(double) * 2 * rs.T, hipMemcpyDeviceToHost, h->stream));
-      Retiring rt;
-      rt.rs = rs;
-      if (!h->sync_ev_free.empty()) {
-        rt.ev = h->sync_ev_free.back();
-        h->sync_ev_free.pop_back();
-      } else {
-        HIP_TRY(h, hipEventCreateWithFlags(&rt.ev, hipEventDisableTiming));
-      }
-      HIP_TRY(h, hipEventRecord(rt.ev, h->stream));
-      h->retiring.push_back(rt);
+      st = enqueue_retire(h, rs);
+      if (st != PLAN_OK) return st;
       h->resident.erase(h->resident.begin() + i);
     }
   }

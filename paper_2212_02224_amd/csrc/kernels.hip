@@ -733,25 +733,91 @@ __device__ __forceinline__ void write_xi(const ReqDesc &D, const MethodParams &P
 }
 
 // IPL instants per lane: instant (wi IPL + u) 64 + lane in slot u of wave wi
-// of a sample; ceil(T / (64 IPL)) waves per sample.
-template <int IPL, bool ROAD>
-__global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
-  extern __shared__ float4 s_obs[];
-  __shared__ float s_red[2][4 * IPL][16];
-  __shared__ double s_mu[8], s_chol[64];
-  __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
+// of a sample; ceil(T / (64 IPL)) waves per sample, 4 / that samples per
+// workgroup (wave sl NW + wi is wave wi of sample sl).
+struct LowerShape {
+  int NW, spb, wave, lane, sl, wi;
+};
+template <int IPL>
+__device__ __forceinline__ LowerShape lower_shape(int T) {
+  LowerShape h;
+  h.NW = (T + kWave * IPL - 1) / (kWave * IPL);
+  h.spb = 4 / h.NW;
+  h.wave = threadIdx.x / kWave;
+  h.lane = threadIdx.x % kWave;
+  h.sl = h.wave / h.NW;
+  h.wi = h.wave - h.sl * h.NW;
+  return h;
+}
 
-  const int2 bi = block_slot(A);
-  const ReqDesc &D = A.desc[bi.x];
-  const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
+// The part of a lower-level workgroup's state that depends on its request
+// alone (not on the upper iteration or on which samples it serves): the
+// method's scalars, the basis rows of the lane's instants with the fixed part
+// of the trajectory, and the lane's row of A^-1 and D.
+template <int IPL>
+struct LowerSetup {
+  Lane L[IPL];
+  Scal S;
+  float arow[16];
+  float Dv;
+};
+
+// Set-up of a request: its neighbour table (and road profile) into LDS and
+// the register part. The LDS tables are ready after the next barrier.
+template <int IPL, bool ROAD>
+__device__ __forceinline__ void lower_setup(const LowerArgs &A, const MethodParams &P, const ReqDesc &D,
+                                            float4 *s_obs, float4 *s_road, LowerSetup<IPL> &U) {
+  const LowerShape h = lower_shape<IPL>(D.T);
+  const int T = D.T;
+  stage_neighbours(D, P, s_obs);
+  if constexpr (ROAD) stage_road(D, s_road);
+  U.S = make_scal(D, P);
+  // Basis rows of this lane's instants and the fixed part of the trajectory.
+  const float *Bt = A.basis + D.basis_off;
+  const int Tp = D.basis_tpad;
+#pragma unroll
+  for (int u = 0; u < IPL; ++u) {
+    const int t = (h.wi * IPL + u) * kWave + h.lane;
+    const int tt = t < T ? t : T - 1;
+    Lane &L = U.L[u];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      L.bx[c] = Bt[(kColW + c) * Tp + tt];
+      L.bdx[c] = Bt[(kColWd + c) * Tp + tt];
+      L.bddx[c] = Bt[(kColWdd + c) * Tp + tt];
+    }
+    L.by7 = Bt[(kColY7 + 0) * Tp + tt];
+    L.bdy7 = Bt[(kColY7 + 1) * Tp + tt];
+    L.bddy7 = Bt[(kColY7 + 2) * Tp + tt];
+    const State6 f = fixed_part(Bt, Tp, tt, D, P);
+    L.xf = f.x;
+    L.xdf = f.xd;
+    L.xddf = f.xdd;
+    L.yf = f.y;
+    L.ydf = f.yd;
+    L.yddf = f.ydd;
+  }
+  const int v = h.lane >> 2;
+  const float *Pj = A.proj + (size_t)D.tm_idx * kProjFloats;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) U.arow[c] = Pj[v * 16 + c];
+  U.Dv = Pj[256 + v];
+}
+
+// The samples of workgroup `rank` of the request in `slot` at upper
+// iteration l, with the request's set-up in U and LDS: the sample p_j,
+// step 1, K projection iterations, residual and upper cost, rows written.
+// Every thread of the workgroup calls it (it holds barriers).
+template <int IPL, bool ROAD>
+__device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParams &P, const ReqDesc &D, int slot,
+                                           int rank, int l, const LowerSetup<IPL> &U, const float4 *s_obs,
+                                           const float4 *s_road, float (*s_red)[4 * IPL][16], double *s_mu,
+                                           double *s_chol) {
+  const LowerShape h = lower_shape<IPL>(D.T);
   const int T = D.T, M = D.M, N = D.N;
   const int npair = (M + 1) >> 1;
-  const int NW = (T + kWave * IPL - 1) / (kWave * IPL);
-  const int spb = 4 / NW;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int sl = wave / NW;
-  const int wi = wave - sl * NW;
-  const int j = bi.y * spb + sl;
+  const int NW = h.NW, spb = h.spb, wave = h.wave, lane = h.lane, sl = h.sl, wi = h.wi;
+  const int j = rank * spb + sl;
   const bool active = (sl < spb) && (j < N);
   int tt[IPL];
   bool tv[IPL];
@@ -762,47 +828,15 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     tt[u] = t < T ? t : T - 1;
   }
   const size_t slot_off = (size_t)D.row_off;
+  const Scal &S = U.S;
+  const Lane(&L)[IPL] = U.L;
 
-  stage_neighbours(D, P, s_obs);
-  if constexpr (ROAD) stage_road(D, s_road);
   // samples in the rows already: the caller's, or the decoder sampler's
   const bool forced = D.init_mode == kInitForced || decoded_start(D, P, l);
   const bool structured = !forced && l == 0 && D.init_mode == kInitStructured;
-  if (!forced && !structured) load_distribution(A, D, P, bi.x, l, bi.y == 0, s_mu, s_chol);
-  const Scal S = make_scal(D, P);
-
-  // Basis rows of this lane's instants and the fixed part of the trajectory.
-  const float *Bt = A.basis + D.basis_off;
-  const int Tp = D.basis_tpad;
-  Lane L[IPL];
-#pragma unroll
-  for (int u = 0; u < IPL; ++u) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      L[u].bx[c] = Bt[(kColW + c) * Tp + tt[u]];
-      L[u].bdx[c] = Bt[(kColWd + c) * Tp + tt[u]];
-      L[u].bddx[c] = Bt[(kColWdd + c) * Tp + tt[u]];
-    }
-    L[u].by7 = Bt[(kColY7 + 0) * Tp + tt[u]];
-    L[u].bdy7 = Bt[(kColY7 + 1) * Tp + tt[u]];
-    L[u].bddy7 = Bt[(kColY7 + 2) * Tp + tt[u]];
-    const State6 f = fixed_part(Bt, Tp, tt[u], D, P);
-    L[u].xf = f.x;
-    L[u].xdf = f.xd;
-    L[u].xddf = f.xdd;
-    L[u].yf = f.y;
-    L[u].ydf = f.yd;
-    L[u].yddf = f.ydd;
-  }
+  if (!forced && !structured) load_distribution(A, D, P, slot, l, rank == 0, s_mu, s_chol);
   const int v = lane >> 2;
-  float arow[16];
-  float Dv;
-  {
-    const float *Pj = A.proj + (size_t)D.tm_idx * kProjFloats;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) arow[c] = Pj[v * 16 + c];
-    Dv = Pj[256 + v];
-  }
+  const float Dv = U.Dv;
   const uint64_t seed = D.seed;
   const int draw_iter = D.first_iter + l;
   __syncthreads();  // neighbour table and distribution ready
@@ -888,7 +922,7 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
     for (int c = 0; c < 15; ++c) rs[c] = bcast(rhs, 4 * c);
     float dz = 0.f;
 #pragma unroll
-    for (int c = 0; c < 15; ++c) dz = fmaf(arow[c], rs[c], dz);
+    for (int c = 0; c < 15; ++c) dz = fmaf(U.arow[c], rs[c], dz);
     z += dz;
 #pragma unroll
     for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
@@ -909,18 +943,36 @@ __global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams
   const float rr = combine(rb, lane == 0, 0);
   const float cc = combine(cb, lane == 0, 1);
 
-  if (!active) return;
-  const size_t row = slot_off + j;
-  // all 16 entries (the pad one is 0), so each row is one whole 64-byte line;
-  // every wave of the sample holds the same z, the first one stores it
-  if (wi == 0 && (lane & 3) == 0) A.zs[row * kZ + v] = z;
-  if (wi == 0 && lane == 0) {
-    A.resid[row] = rr;
-    A.cost[row] = cc;
+  if (active) {
+    const size_t row = slot_off + j;
+    // all 16 entries (the pad one is 0), so each row is one whole 64-byte
+    // line; every wave of the sample holds the same z, the first stores it
+    if (wi == 0 && (lane & 3) == 0) A.zs[row * kZ + v] = z;
+    if (wi == 0 && lane == 0) {
+      A.resid[row] = rr;
+      A.cost[row] = cc;
+    }
+    if (A.xi_star_out != nullptr && wi == 0 && ((lane & 3) == 0 || lane == 61))
+      write_xi(D, P, A.xi_star_out + (size_t)j * 22, A.xi_bar_out + (size_t)j * 22, (lane & 3) == 0 ? v : 99, z,
+               zb, lane == 61);
   }
-  if (A.xi_star_out != nullptr && wi == 0 && ((lane & 3) == 0 || lane == 61))
-    write_xi(D, P, A.xi_star_out + (size_t)j * 22, A.xi_bar_out + (size_t)j * 22, (lane & 3) == 0 ? v : 99, z,
-             zb, lane == 61);
+}
+
+// One upper iteration of the launch's requests: workgroup b serves the
+// samples of rank b - prefix[slot] of its request.
+template <int IPL, bool ROAD>
+__global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
+  extern __shared__ float4 s_obs[];
+  __shared__ float s_red[2][4 * IPL][16];
+  __shared__ double s_mu[8], s_chol[64];
+  __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
+
+  const int2 bi = block_slot(A);
+  const ReqDesc &D = A.desc[bi.x];
+  const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
+  LowerSetup<IPL> U;
+  lower_setup<IPL, ROAD>(A, P, D, s_obs, s_road, U);
+  lower_item<IPL, ROAD>(A, P, D, bi.x, bi.y, l, U, s_obs, s_road, s_red, s_mu, s_chol);
 }
 
 // ---------------------------------------------------------------------------
@@ -1716,24 +1768,88 @@ __device__ void sample_moments(const float *p, int N, double *s_mu, double *s_si
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, MethodParams P) {
-  __shared__ uint32_t s_key[PLAN_MAX_N];  // residual keys
-  __shared__ float s_c[PLAN_MAX_N];       // c_u + r
-  __shared__ uint32_t s_ces[kMaxCes];
-  __shared__ __align__(16) unsigned long long s_key2[kSelBlock + 2];  // (key << 32) | CES position
-  __shared__ unsigned long long s_bestw[kSelBlock / kWave];
-  __shared__ uint32_t s_es[kMaxCes];
-  __shared__ uint32_t s_hist[256];
-  __shared__ uint32_t s_tmp[32];
-  __shared__ uint32_t s_wmin[kSelBlock / kWave];
-  __shared__ double s_w[kMaxEs];
-  __shared__ __align__(16) float s_p[kMaxEs][8];
-  __shared__ double s_mu[8], s_sig[64];
-  __shared__ double s_part[4][64 + 8];
-  __shared__ double s_wsum[4];
-  __shared__ uint32_t s_first;
+// LDS of the selection / update of one request: the select kernel's static
+// arrays, or (fused iterations) a part of the lower kernel's dynamic LDS
+// with s_key and s_c sized for the request's N.
+struct SelLds {
+  uint32_t *s_key;                 // [N] residual keys
+  float *s_c;                      // [N] c_u + r
+  uint32_t *s_ces;                 // [kMaxCes]
+  unsigned long long *s_key2;      // [kSelBlock + 2] (key << 32) | CES position, 16-byte aligned
+  unsigned long long *s_bestw;     // [kSelBlock / kWave]
+  uint32_t *s_es;                  // [kMaxCes]
+  uint32_t *s_hist;                // [256]
+  uint32_t *s_tmp;                 // [32]
+  uint32_t *s_wmin;                // [kSelBlock / kWave]
+  double *s_w;                     // [kMaxEs]
+  float (*s_p)[8];                 // [kMaxEs][8], 16-byte aligned
+  double *s_mu, *s_sig;            // [8], [64]
+  double (*s_part)[64 + 8];        // [4][72]
+  double *s_wsum;                  // [4]
+  uint32_t *s_first;               // [1]
+  double (*s_rc64)[2];             // [3][2]
+};
 
-  const int slot = A.slots[blockIdx.x];
+// Bytes of a SelLds for n_keys keys (16-byte aligned parts, in the order
+// sel_lds_carve lays them out).
+__host__ __device__ constexpr size_t sel_lds_bytes(int n_keys) {
+  return 16 * (((size_t)n_keys * 4 + 15) / 16) * 2 + 16 * ((kMaxCes * 4 + 15) / 16) * 2 +
+         16 * (((kSelBlock + 2) * 8 + 15) / 16) + 16 * ((kSelBlock / kWave * 8 + 15) / 16) + 16 * (256 * 4 / 16) +
+         16 * (32 * 4 / 16) + 16 * ((kSelBlock / kWave * 4 + 15) / 16) + 16 * (kMaxEs * 8 / 16) +
+         16 * (kMaxEs * 32 / 16) + 16 * (8 * 8 / 16) + 16 * (64 * 8 / 16) + 16 * (4 * 72 * 8 / 16) + 16 * 2 + 16 +
+         16 * (3 * 2 * 8 / 16);
+}
+
+__device__ inline SelLds sel_lds_carve(char *base, int n_keys) {
+  SelLds L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> char * {
+    char *q = base + o;
+    o += 16 * ((bytes + 15) / 16);
+    return q;
+  };
+  L.s_key = reinterpret_cast<uint32_t *>(take((size_t)n_keys * 4));
+  L.s_c = reinterpret_cast<float *>(take((size_t)n_keys * 4));
+  L.s_ces = reinterpret_cast<uint32_t *>(take(kMaxCes * 4));
+  L.s_es = reinterpret_cast<uint32_t *>(take(kMaxCes * 4));
+  L.s_key2 = reinterpret_cast<unsigned long long *>(take((kSelBlock + 2) * 8));
+  L.s_bestw = reinterpret_cast<unsigned long long *>(take(kSelBlock / kWave * 8));
+  L.s_hist = reinterpret_cast<uint32_t *>(take(256 * 4));
+  L.s_tmp = reinterpret_cast<uint32_t *>(take(32 * 4));
+  L.s_wmin = reinterpret_cast<uint32_t *>(take(kSelBlock / kWave * 4));
+  L.s_w = reinterpret_cast<double *>(take(kMaxEs * 8));
+  L.s_p = reinterpret_cast<float(*)[8]>(take(kMaxEs * 32));
+  L.s_mu = reinterpret_cast<double *>(take(8 * 8));
+  L.s_sig = reinterpret_cast<double *>(take(64 * 8));
+  L.s_part = reinterpret_cast<double(*)[72]>(take(4 * 72 * 8));
+  L.s_wsum = reinterpret_cast<double *>(take(4 * 8));
+  L.s_first = reinterpret_cast<uint32_t *>(take(4));
+  L.s_rc64 = reinterpret_cast<double(*)[2]>(take(3 * 2 * 8));
+  return L;
+}
+
+// ConstraintEliteSet, EliteSet and the update of mu, Sigma (and on the last
+// iteration the result) for the request in `slot` at upper iteration l
+// (l_uniform, or the descriptor's cur_iter), by one workgroup of kSelBlock
+// threads.
+__device__ __forceinline__ void select_update_body(const SelArgs &A, const MethodParams &P, int slot,
+                                                   const SelLds &Ls) {
+  uint32_t *const s_key = Ls.s_key;
+  float *const s_c = Ls.s_c;
+  uint32_t *const s_ces = Ls.s_ces;
+  unsigned long long *const s_key2 = Ls.s_key2;
+  unsigned long long *const s_bestw = Ls.s_bestw;
+  uint32_t *const s_es = Ls.s_es;
+  uint32_t *const s_hist = Ls.s_hist;
+  uint32_t *const s_tmp = Ls.s_tmp;
+  uint32_t *const s_wmin = Ls.s_wmin;
+  double *const s_w = Ls.s_w;
+  float(*const s_p)[8] = Ls.s_p;
+  double *const s_mu = Ls.s_mu, *const s_sig = Ls.s_sig;
+  double(*const s_part)[64 + 8] = Ls.s_part;
+  double *const s_wsum = Ls.s_wsum;
+  uint32_t &s_first = *Ls.s_first;
+
   ReqDesc &D = A.desc[slot];
   DistState &Sd = A.dist[slot];
   ResultRec &R = A.result[slot];
@@ -1935,7 +2051,7 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
     // summed per wave in lane order and then over the waves in wave order;
     // they set the result's residual, cost and infeasible flag, and the
     // trajectory's positions at every instant are stored.
-    __shared__ double s_rc64[3][2];
+    double(*const s_rc64)[2] = Ls.s_rc64;
     if (tid >= 64) {
       const int t = tid - 64;
       const uint32_t b = jbest;
@@ -1995,6 +2111,187 @@ __global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, Met
       A.tr_c[tb + i] = cu[i];
     }
   }
+}
+
+__global__ void __launch_bounds__(kSelBlock) select_update_kernel(SelArgs A, MethodParams P) {
+  __shared__ uint32_t s_key[PLAN_MAX_N];
+  __shared__ float s_c[PLAN_MAX_N];
+  __shared__ uint32_t s_ces[kMaxCes];
+  __shared__ __align__(16) unsigned long long s_key2[kSelBlock + 2];
+  __shared__ unsigned long long s_bestw[kSelBlock / kWave];
+  __shared__ uint32_t s_es[kMaxCes];
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_tmp[32];
+  __shared__ uint32_t s_wmin[kSelBlock / kWave];
+  __shared__ double s_w[kMaxEs];
+  __shared__ __align__(16) float s_p[kMaxEs][8];
+  __shared__ double s_mu[8], s_sig[64];
+  __shared__ double s_part[4][64 + 8];
+  __shared__ double s_wsum[4];
+  __shared__ uint32_t s_first;
+  __shared__ double s_rc64[3][2];
+  const SelLds Ls{s_key, s_c, s_ces, s_key2, s_bestw, s_es, s_hist, s_tmp, s_wmin, s_w, s_p, s_mu, s_sig,
+                  s_part, s_wsum, &s_first, s_rc64};
+  select_update_body(A, P, A.slots[blockIdx.x], Ls);
+}
+
+// ---------------------------------------------------------------------------
+// Every upper iteration of a launch group in one launch (Alg. 1's loop on
+// the device).
+//
+// The launch has one workgroup per work item: item g = l W + w (W
+// workgroups per iteration, w in the launch's workgroup order) is the
+// samples of rank w - prefix[i] of active request i at upper iteration l. A
+// workgroup takes its item from a counter when it starts, so items are taken
+// in increasing order, and only by workgroups that are running. The
+// workgroup that completes the last item of request i at iteration l runs
+// that request's selection and update (the body of select_update_kernel) and
+// then publishes l + 1; an item of iteration l + 1 does its request set-up
+// and then waits for that before it draws. Every item an item waits for has
+// a smaller index and was taken by a running workgroup, so the launch
+// finishes however many workgroups are resident.
+//
+// Waits are bounded: after wait_ticks of the wall clock (or once another
+// workgroup has given up) a workgroup sets the give-up word and skips its
+// item; later workgroups skip theirs, and the requests whose updates did not
+// all run get status PLAN_E_TIMEOUT. The last workgroup to finish sets the
+// control words back to zero for the next launch.
+//
+// Control words (zero at launch):
+//   [0] next work item   [1] give-up word   [2] workgroups finished
+//   [4 + i]              workgroups of request i done (over all iterations)
+//   [4 + n_act + i]      updates of request i that have run
+struct FusedArgs {
+  uint32_t *ctl;
+  uint64_t wait_ticks;  // wall-clock ticks a wait may last
+};
+
+// Thread 0 of a workgroup: wait until *ready >= l, with the bounds above.
+// True: the update has run and its writes are visible to the workgroup
+// after the next barrier.
+__device__ bool wait_update(const uint32_t *ready, uint32_t l, uint32_t *gave_up, uint64_t wait_ticks) {
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  for (;;) {
+    if (__hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= l) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
+    if (__hip_atomic_load(gave_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if ((uint64_t)wall_clock64() - t0 > wait_ticks) {
+      __hip_atomic_store(gave_up, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+}
+
+template <int IPL, bool ROAD>
+__global__ void __launch_bounds__(kBlock) lower_fused_kernel(LowerArgs A, SelArgs SA, MethodParams P, FusedArgs F) {
+  extern __shared__ float4 s_dyn[];  // neighbour table, then the selection's arrays
+  __shared__ float s_red[2][4 * IPL][16];
+  __shared__ double s_mu[8], s_chol[64];
+  __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
+  __shared__ int s_msg[3];
+
+  const int n_act = A.n_act;
+  const int W = A.blk_prefix[n_act];
+  uint32_t *const claim = F.ctl, *const gave_up = F.ctl + 1, *const finished = F.ctl + 2;
+  uint32_t *const done = F.ctl + 4, *const ready = F.ctl + 4 + n_act;
+  if (threadIdx.x == 0) {
+    int g = -1;
+    if (__hip_atomic_load(gave_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      g = (int)__hip_atomic_fetch_add(claim, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_msg[0] = g;
+  }
+  __syncthreads();
+  // values broadcast through LDS are uniform: readfirstlane keeps them, and
+  // every address derived from them, in scalar registers
+  const int g = __builtin_amdgcn_readfirstlane(s_msg[0]);
+  if (g >= 0 && g < W * P.L) {
+    const int l = g / W, w = g - l * W;
+    int lo = 0, hi = n_act - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (A.blk_prefix[mid] <= w) lo = mid;
+      else hi = mid - 1;
+    }
+    const int pos = lo, slot = A.act_slots[pos];
+    const ReqDesc &D = A.desc[slot];
+    LowerSetup<IPL> U;
+    lower_setup<IPL, ROAD>(A, P, D, s_dyn, s_road, U);
+    bool go = true;
+    if (l > 0) {
+      if (threadIdx.x == 0) s_msg[1] = wait_update(ready + pos, (uint32_t)l, gave_up, F.wait_ticks);
+      __syncthreads();
+      go = __builtin_amdgcn_readfirstlane(s_msg[1]) != 0;
+    }
+    if (go) {
+      lower_item<IPL, ROAD>(A, P, D, slot, w - A.blk_prefix[pos], l, U, s_dyn, s_road, s_red, s_mu, s_chol);
+      // every wave's rows written and its reads done, at device scope,
+      // before the workgroup counts itself
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t nb = (uint32_t)(A.blk_prefix[pos + 1] - A.blk_prefix[pos]);
+        const uint32_t old = __hip_atomic_fetch_add(done + pos, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_msg[2] = old + 1 == nb * (uint32_t)(l + 1);
+      }
+      __syncthreads();
+      if (__builtin_amdgcn_readfirstlane(s_msg[2])) {
+        // the last item of this request at iteration l: its update
+        SelArgs sa = SA;
+        sa.l_uniform = l;
+        select_update_body(sa, P, slot, sel_lds_carve(reinterpret_cast<char *>(s_dyn), PLAN_MAX_N));
+        // the update's writes and reads complete before the next iteration
+        // may overwrite the rows
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+          __hip_atomic_store(ready + pos, (uint32_t)(l + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_msg[0] = __hip_atomic_fetch_add(finished, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  if (!__builtin_amdgcn_readfirstlane(s_msg[0])) return;
+  // the last workgroup to finish
+  if (__hip_atomic_load(gave_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+    for (int i = threadIdx.x; i < n_act; i += kBlock)
+      if (__hip_atomic_load(ready + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)P.L)
+        SA.result[A.act_slots[i]].status = PLAN_E_TIMEOUT;
+  __syncthreads();  // every thread has read the words before they are cleared
+  for (int i = threadIdx.x; i < 4 + 2 * n_act; i += kBlock) F.ctl[i] = 0u;
+}
+
+// Dynamic LDS of a fused launch: the neighbour table or the selection's
+// arrays, whichever is larger. The selection's arrays are sized for
+// PLAN_MAX_N keys whatever the requests' N: at fixed offsets their addresses
+// are constants.
+size_t fused_lds_bytes(size_t obs_lds) {
+  return obs_lds > sel_lds_bytes(PLAN_MAX_N) ? obs_lds : sel_lds_bytes(PLAN_MAX_N);
+}
+
+// Fused launch of one launch group: nblocks workgroups per iteration, one
+// launch workgroup per (iteration, workgroup).
+hipError_t launch_lower_fused(const LowerArgs &a, const SelArgs &sa, const MethodParams &p, uint32_t *ctl,
+                              int nblocks, int ipl, bool road, size_t obs_lds, uint64_t wait_ticks, hipStream_t st,
+                              hipEvent_t ev0, hipEvent_t ev1) {
+  if (ipl != 1 && ipl != 2) return hipErrorInvalidValue;
+  if (nblocks <= 0 || p.L <= 0 || (int64_t)nblocks * p.L > 0x7fffffff) return hipErrorInvalidValue;
+  auto kern = ipl == 1 ? (road ? lower_fused_kernel<1, true> : lower_fused_kernel<1, false>)
+                       : (road ? lower_fused_kernel<2, true> : lower_fused_kernel<2, false>);
+  const size_t lds = fused_lds_bytes(obs_lds);
+  FusedArgs F;
+  F.ctl = ctl;
+  F.wait_ticks = wait_ticks;
+  const int grid = nblocks * p.L;
+  if (ev0)
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), (uint32_t)lds, st, ev0, ev1, 0, a, sa, p, F);
+  else
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, st, a, sa, p, F);
+  return hipGetLastError();
 }
 
 hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, int ipl, bool road, size_t lds,

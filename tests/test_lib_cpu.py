@@ -87,7 +87,8 @@ def test_config_defaults_and_workspace(pl):
                                   dict(precision=1, T_set=[50, 200]), dict(precision=2, T_set=[50, 200]),
                                   dict(behaviour=2), dict(sampler=3),
                                   dict(behaviour=1, w_s=0.0), dict(served_run_ahead=4),
-                                  dict(served_run_ahead=-1)])
+                                  dict(served_run_ahead=-1), dict(fused_iters=2), dict(fused_iters=-1),
+                                  dict(fused_iters=1, fused_wait_us=0)])
 def test_invalid_config_rejected_before_device(pl, over):
     cfg = pl.plan_config_init(**over)
     assert pl.plan_workspace_bytes(cfg) == 0

@@ -18,6 +18,13 @@ def pl():
     return pl
 
 
+@pytest.fixture(params=[0, 1], ids=["ticked", "fused"])
+def mode(request):
+    """plan_config.fused_iters: per-iteration host ticks, or each admission's
+    whole solve enqueued at once (fused launches)."""
+    return request.param
+
+
 MIX = [(64, 50, 4), (300, 100, 10), (17, 100, 20), (512, 50, 10), (1, 100, 4), (250, 100, 20),
        (128, 50, 20), (700, 100, 4)]
 
@@ -30,14 +37,15 @@ def reqs_of(pl, cfgid=4):
     return out
 
 
-def cfg_of(pl, **over):
-    kw = dict(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=8, upper_iters=3, max_N=1024, max_requests=8)
+def cfg_of(pl, mode=1, **over):
+    kw = dict(T_set=[50, 100], M_set=[4, 10, 20], proj_iters=8, upper_iters=3, max_N=1024, max_requests=8,
+              fused_iters=mode)
     kw.update(over)
     return pl.plan_config_init(**kw)
 
 
 def alone_results(pl, reqs):
-    h = pl.plan_create(cfg_of(pl))
+    h = pl.plan_create(cfg_of(pl, 0))
     return [pl.plan_solve_batch(h, [r])[0] for r in reqs]
 
 
@@ -64,10 +72,10 @@ def same(a, b):
             and np.array_equal(a.mu, b.mu) and np.array_equal(a.sigma, b.sigma))
 
 
-def test_served_all_at_once_equals_alone(pl):
+def test_served_all_at_once_equals_alone(pl, mode):
     reqs = reqs_of(pl)
     ref = alone_results(pl, reqs)
-    h = pl.plan_create(cfg_of(pl))
+    h = pl.plan_create(cfg_of(pl, mode))
     tickets = [pl.plan_submit(h, r) for r in reqs]
     got, _, _ = drain(pl, h, tickets)
     for i, t in enumerate(tickets):
@@ -75,14 +83,14 @@ def test_served_all_at_once_equals_alone(pl):
         assert got[t].latency_s > 0
 
 
-def test_poll_done_returns_each_ticket_once_and_equals_alone(pl):
+def test_poll_done_returns_each_ticket_once_and_equals_alone(pl, mode):
     """plan_poll_done hands back every finished request in ticket order,
     each exactly once, with the result (and trajectory) it has alone; a
     capacity smaller than the finished count leaves the rest for the next
     call; plan_poll then knows none of them."""
     reqs = reqs_of(pl)
     ref = alone_results(pl, reqs)
-    h = pl.plan_create(cfg_of(pl))
+    h = pl.plan_create(cfg_of(pl, mode))
     assert pl.plan_poll_done(h, 4) == []
     tickets = []
     for i, r in enumerate(reqs):
@@ -112,10 +120,10 @@ def test_poll_done_returns_each_ticket_once_and_equals_alone(pl):
     assert pl.plan_poll_done(h, 8) == []
 
 
-def test_served_staggered_arrivals_equal_alone(pl):
+def test_served_staggered_arrivals_equal_alone(pl, mode):
     reqs = reqs_of(pl)
     ref = alone_results(pl, reqs)
-    h = pl.plan_create(cfg_of(pl))
+    h = pl.plan_create(cfg_of(pl, mode))
     tickets = []
     for i, r in enumerate(reqs):
         tickets.append(pl.plan_submit(h, r))
@@ -128,13 +136,13 @@ def test_served_staggered_arrivals_equal_alone(pl):
 
 
 @pytest.mark.parametrize("ahead", [1, 3])
-def test_served_run_ahead_equals_alone(pl, ahead):
+def test_served_run_ahead_equals_alone(pl, mode, ahead):
     """With iterations enqueued ahead of the GPU (served_run_ahead), arrivals
     during the run still give each request its result alone, bit for bit,
     and every request retires."""
     reqs = reqs_of(pl)
     ref = alone_results(pl, reqs)
-    h = pl.plan_create(cfg_of(pl, served_run_ahead=ahead))
+    h = pl.plan_create(cfg_of(pl, mode, served_run_ahead=ahead))
     tickets = []
     for i, r in enumerate(reqs):
         tickets.append(pl.plan_submit(h, r))
@@ -148,11 +156,11 @@ def test_served_run_ahead_equals_alone(pl, ahead):
     assert pl.plan_solve_batch(h, [reqs[0]])[0].status == 0
 
 
-def test_served_admission_respects_sample_budget(pl):
+def test_served_admission_respects_sample_budget(pl, mode):
     reqs = reqs_of(pl)
     ref = alone_results(pl, reqs)
     budget = 800
-    h = pl.plan_create(cfg_of(pl, sample_budget=budget, max_requests=3))
+    h = pl.plan_create(cfg_of(pl, mode, sample_budget=budget, max_requests=3))
     tickets = [pl.plan_submit(h, r) for r in reqs]
     done, ticks = {}, 0
     while len(done) < len(tickets):
@@ -174,9 +182,9 @@ def test_served_admission_respects_sample_budget(pl):
     assert e.value.status == pl.PLAN_E_NOMEM
 
 
-def test_served_rejects_bad_requests_and_mixing(pl):
+def test_served_rejects_bad_requests_and_mixing(pl, mode):
     reqs = reqs_of(pl)
-    h = pl.plan_create(cfg_of(pl))
+    h = pl.plan_create(cfg_of(pl, mode))
     bad = pl.Request(N=10, T=70, ego=reqs[0].ego, obstacles=reqs[0].obstacles, seed=1)
     with pytest.raises(pl.PlanError) as e:
         pl.plan_submit(h, bad)
