@@ -81,6 +81,7 @@ bool mfma_f32(const plan_config &c) { return c.precision == PLAN_PREC_FP32_MFMA;
 // tile pairs and their total.
 size_t lds_bytes(int M, int T, bool mfma, bool f32 = false) {
   size_t b = (size_t)((M + 1) / 2) * T * sizeof(float4);
+  if (!mfma && M > 0) b += (size_t)kObsPad * sizeof(float4);
   if (mfma) {
     const size_t NT = (size_t)((T + 3) / 4), NI = 4 * NT;
     b += (f32 ? NI * kEv32InstFloats * 4 : NI * kEvInstHalfs * 2) +

@@ -355,10 +355,13 @@ __device__ __forceinline__ void near_update(float q, float dx, float dy, float &
 // subtractions and two compares; it pays where a lane carries two instants
 // (measured -10% at M = 20), not with one instant per lane or on the matrix
 // cores (within +-2%), where the launches leave it out.
+// `live`: the lanes whose instant is inside the horizon (the others take no
+// part in the gate).
 template <bool GATE>
-__device__ __forceinline__ void pair_update(float xs, float ys, const float4 &o, float &ax, float &ay) {
+__device__ __forceinline__ void pair_update(float xs, float ys, const float4 &o, uint64_t live, float &ax,
+                                            float &ay) {
   const float dx0 = xs - o.x, dx1 = xs - o.z;
-  if (!GATE || __builtin_amdgcn_ballot_w64(fabsf(dx0) < 1.f || fabsf(dx1) < 1.f) != 0) {
+  if (!GATE || (__builtin_amdgcn_ballot_w64(fminf(fabsf(dx0), fabsf(dx1)) < 1.f) & live) != 0) {
     const float dy0 = ys - o.y, dy1 = ys - o.w;
     const float q0 = fmaf(dx0, dx0, dy0 * dy0), q1 = fmaf(dx1, dx1, dy1 * dy1);
     near_update(q0, dx0, dy0, ax, ay);
@@ -374,7 +377,7 @@ __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, i
   float4 cur = obs[t];
   for (int c = 0; c < npair; ++c) {
     const float4 nxt = obs[(c + 1 < npair ? c + 1 : c) * T + t];
-    pair_update<false>(xs, ys, cur, ax, ay);
+    pair_update<false>(xs, ys, cur, ~0ull, ax, ay);
     cur = nxt;
   }
 }
@@ -441,10 +444,11 @@ __device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const
 // One target pass over this lane's IPL instants (slots): the trajectory at
 // each, the neighbour sums of all slots in one loop over the neighbour pairs
 // (the slots' dependency chains interleave), then the targets of each slot.
+// t0: slot 0's instant, unclamped.
 template <int IPL, bool ROAD>
 __device__ __forceinline__ void target_pass(const Lane (&L)[IPL], const Scal &S, const float (&zs)[15],
                                             const float4 *__restrict__ obs, const float4 *__restrict__ road,
-                                            int npair, int T, const int (&tt)[IPL], const bool (&tv)[IPL],
+                                            int npair, int T, int t0, const int (&tt)[IPL], const bool (&tv)[IPL],
                                             float (&da_prev)[IPL], Corr (&cr)[IPL]) {
   State6 st[IPL];
   float xs[IPL], ys[IPL], ax[IPL], ay[IPL];
@@ -456,20 +460,43 @@ __device__ __forceinline__ void target_pass(const Lane (&L)[IPL], const Scal &S,
     ax[u] = 0.f;
     ay[u] = 0.f;
   }
-  if (npair > 0) {
-    float4 cur[IPL];
-#pragma unroll
-    for (int u = 0; u < IPL; ++u) cur[u] = obs[tt[u]];
+  if (IPL == 1 && npair > 0) {
+    // one entry ahead (the update is branch-free here, and a small launch
+    // is bound by its latency)
+    float4 cur = obs[tt[0]];
     for (int c = 0; c < npair; ++c) {
-      const int cn = c + 1 < npair ? c + 1 : c;
-      float4 nxt[IPL];
+      const float4 nxt = obs[(c + 1 < npair ? c + 1 : c) * T + tt[0]];
+      pair_update<false>(xs[0], ys[0], cur, ~0ull, ax[0], ay[0]);
+      cur = nxt;
+    }
+  } else if (npair > 0) {
+    // Entries of pairs c and c + 1 in alternating registers (no copies
+    // between steps). Slot u reads instant t0 + 64 u unclamped, an immediate
+    // offset from slot 0's address: past the horizon that is another pair's
+    // row or the far padding, and such lanes are not live.
+    const float4 *base = obs + t0;
+    uint64_t live[IPL];
 #pragma unroll
-      for (int u = 0; u < IPL; ++u) nxt[u] = obs[cn * T + tt[u]];
+    for (int u = 0; u < IPL; ++u) live[u] = __builtin_amdgcn_ballot_w64(tv[u]);
+    float4 a[IPL], b[IPL];
 #pragma unroll
-      for (int u = 0; u < IPL; ++u) {
-        pair_update<IPL == 2>(xs[u], ys[u], cur[u], ax[u], ay[u]);
-        cur[u] = nxt[u];
-      }
+    for (int u = 0; u < IPL; ++u) a[u] = base[u * kWave];
+    int c = 0;
+    for (; c + 1 < npair; c += 2) {
+      const float4 *pb = base + (c + 1) * T;
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) b[u] = pb[u * kWave];
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) pair_update<IPL == 2>(xs[u], ys[u], a[u], live[u], ax[u], ay[u]);
+      const float4 *pa = base + (c + 2 < npair ? c + 2 : c + 1) * T;
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) a[u] = pa[u * kWave];
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) pair_update<IPL == 2>(xs[u], ys[u], b[u], live[u], ax[u], ay[u]);
+    }
+    if (c < npair) {
+#pragma unroll
+      for (int u = 0; u < IPL; ++u) pair_update<IPL == 2>(xs[u], ys[u], a[u], live[u], ax[u], ay[u]);
     }
   }
 #pragma unroll
@@ -534,9 +561,12 @@ __device__ __forceinline__ int2 block_slot(const LowerArgs &A) {
 // Neighbour positions relative to the reference line x0 + vx0 t, divided by
 // the ellipse axes, two neighbours per entry [pair][T] (an odd last one is
 // paired with a point far away). Constant velocities as in the collision
-// row of Table ineq_list.
-__device__ void stage_neighbours(const ReqDesc &D, const MethodParams &P, float4 *s_obs) {
+// row of Table ineq_list. `pad` entries after the last pair hold far points
+// (the vector-ALU kernel reads up to kObsPad entries past a pair's row).
+__device__ void stage_neighbours(const ReqDesc &D, const MethodParams &P, float4 *s_obs, int pad = 0) {
   const int T = D.T, M = D.M, npair = (M + 1) >> 1;
+  if (npair > 0)
+    for (int i = threadIdx.x; i < pad; i += blockDim.x) s_obs[npair * T + i] = make_float4(1e18f, 1e18f, 1e18f, 1e18f);
   const double x0 = D.ego[0], vx0 = D.ego[2];
   const double ia = 1.0 / P.ell_a, ib = 1.0 / P.ell_b;
   for (int idx = threadIdx.x; idx < npair * T; idx += blockDim.x) {
@@ -769,7 +799,7 @@ __device__ __forceinline__ void lower_setup(const LowerArgs &A, const MethodPara
                                             float4 *s_obs, float4 *s_road, LowerSetup<IPL> &U) {
   const LowerShape h = lower_shape<IPL>(D.T);
   const int T = D.T;
-  stage_neighbours(D, P, s_obs);
+  stage_neighbours(D, P, s_obs, kObsPad);
   if constexpr (ROAD) stage_road(D, s_road);
   U.S = make_scal(D, P);
   // Basis rows of this lane's instants and the fixed part of the trajectory.
@@ -898,7 +928,7 @@ __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParam
   };
   Corr cr[IPL];
   auto pass = [&]() -> float {
-    target_pass<IPL, ROAD>(L, S, zs, obs, s_road, npair, T, tt, tv, da_prev, cr);
+    target_pass<IPL, ROAD>(L, S, zs, obs, s_road, npair, T, wi * IPL * kWave + lane, tt, tv, da_prev, cr);
     float r[IPL];
 #pragma unroll
     for (int u = 0; u < IPL; ++u) {

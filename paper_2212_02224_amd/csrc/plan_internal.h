@@ -18,6 +18,9 @@ constexpr int kStep1Floats = 16 * 8 + 16 * 4;
 constexpr int kProjFloats = 16 * 16 + 16;
 constexpr int kMaxCes = 1024;        // LDS bound of the ConstraintEliteSet
 constexpr int kMaxEs = 256;          // LDS bound of the EliteSet
+// Far entries after the vector-ALU kernel's neighbour table: its lanes read
+// their slots' instants unclamped, up to 64 IPL ceil(T / (64 IPL)) - 1 < T + 128.
+constexpr int kObsPad = 128;
 // Matrix-core (FP16 high/low) lower level.
 constexpr int kMfmaMaxT = 128;       // horizon limit of the matrix-core kernel
 constexpr int kMfmaMaxPairs = kMfmaMaxT / 8;  // pairs of 4-instant tiles
