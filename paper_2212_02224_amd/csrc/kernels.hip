@@ -302,6 +302,34 @@ __device__ __forceinline__ RoadAt road_at(const Scal &S, const float4 *__restric
   return r;
 }
 
+// reduce16's sums, bit for bit, through LDS. Before its two quad steps,
+// reduce16 leaves lane l (p = l & 15) the sum of value l >> 2 over lanes
+// q + {0, 32, 16, 48} for q = p, p ^ 15, p ^ 7, p ^ 8, as the balanced tree
+// ((G(p) + G(p^15)) + (G(p^7) + G(p^8))), G(q) = (v_q + v_q+32) + (v_q+16 +
+// v_q+48). Here every lane writes its 16 values to its row of s_w (this
+// wave's 64 x kRedStride floats), adds the same 16 values in the same tree,
+// and finishes with the same quad steps: 17 vector instructions against 35,
+// for 4 row writes and 16 reads. The wave's own LDS operations run in order,
+// so the reads see the writes, and a later call's writes follow this call's
+// reads.
+constexpr int kRedStride = 20;  // 16-byte rows; reads at most 2-way bank conflicts
+__device__ __forceinline__ float reduce16_lds(const float (&v)[16], int lane, float *s_w) {
+  float4 *row = reinterpret_cast<float4 *>(s_w + lane * kRedStride);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) row[j] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+  __builtin_amdgcn_wave_barrier();
+  const int k = lane >> 2, p = lane & 15;
+  auto grp = [&](int q) -> float {
+    const float *c = s_w + q * kRedStride + k;
+    return (c[0] + c[32 * kRedStride]) + (c[16 * kRedStride] + c[48 * kRedStride]);
+  };
+  float d = (grp(p) + grp(p ^ 15)) + (grp(p ^ 7) + grp(p ^ 8));
+  __builtin_amdgcn_wave_barrier();
+  d += dpp<kDppQuadSwap2>(d);
+  d += dpp<kDppQuadSwap1>(d);
+  return d;
+}
+
 struct State6 {
   float x, xd, xdd, y, yd, ydd;
 };
@@ -838,11 +866,12 @@ __device__ __forceinline__ void lower_setup(const LowerArgs &A, const MethodPara
 // iteration l, with the request's set-up in U and LDS: the sample p_j,
 // step 1, K projection iterations, residual and upper cost, rows written.
 // Every thread of the workgroup calls it (it holds barriers).
+// s_gred: 4 x 64 x kRedStride floats for the two-instants-per-lane sums.
 template <int IPL, bool ROAD>
 __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParams &P, const ReqDesc &D, int slot,
                                            int rank, int l, const LowerSetup<IPL> &U, const float4 *s_obs,
                                            const float4 *s_road, float (*s_red)[4 * IPL][16], double *s_mu,
-                                           double *s_chol) {
+                                           double *s_chol, float *s_gred) {
   const LowerShape h = lower_shape<IPL>(D.T);
   const int T = D.T, M = D.M, N = D.N;
   const int npair = (M + 1) >> 1;
@@ -934,7 +963,8 @@ __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParam
     for (int u = 0; u < IPL; ++u) {
       float g[16];
       g_of(L[u], cr[u], g);
-      r[u] = reduce16(g, lane);
+      if constexpr (IPL == 2) r[u] = reduce16_lds(g, lane, s_gred + wave * kWave * kRedStride);
+      else r[u] = reduce16(g, lane);
     }
     const float acc = combine(r, (lane & 3) == 0, v);
     if (NW > 1) buf ^= 1;
@@ -989,20 +1019,24 @@ __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParam
 }
 
 // One upper iteration of the launch's requests: workgroup b serves the
-// samples of rank b - prefix[slot] of its request.
+// samples of rank b - prefix[slot] of its request. Three waves per SIMD with
+// two instants per lane (the road variant would otherwise take a few more
+// registers than that allows).
 template <int IPL, bool ROAD>
-__global__ void __launch_bounds__(kBlock) lower_kernel(LowerArgs A, MethodParams P) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IPL == 2 ? 3 : 4)))
+lower_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_obs[];
   __shared__ float s_red[2][4 * IPL][16];
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
+  __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kWave * kRedStride : 4];
 
   const int2 bi = block_slot(A);
   const ReqDesc &D = A.desc[bi.x];
   const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
   LowerSetup<IPL> U;
   lower_setup<IPL, ROAD>(A, P, D, s_obs, s_road, U);
-  lower_item<IPL, ROAD>(A, P, D, bi.x, bi.y, l, U, s_obs, s_road, s_red, s_mu, s_chol);
+  lower_item<IPL, ROAD>(A, P, D, bi.x, bi.y, l, U, s_obs, s_road, s_red, s_mu, s_chol, s_gred);
 }
 
 // ---------------------------------------------------------------------------
@@ -2221,6 +2255,7 @@ __global__ void __launch_bounds__(kBlock) lower_fused_kernel(LowerArgs A, SelArg
   __shared__ float s_red[2][4 * IPL][16];
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
+  __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kWave * kRedStride : 4];
   __shared__ int s_msg[3];
 
   const int n_act = A.n_act;
@@ -2256,7 +2291,8 @@ __global__ void __launch_bounds__(kBlock) lower_fused_kernel(LowerArgs A, SelArg
       go = __builtin_amdgcn_readfirstlane(s_msg[1]) != 0;
     }
     if (go) {
-      lower_item<IPL, ROAD>(A, P, D, slot, w - A.blk_prefix[pos], l, U, s_dyn, s_road, s_red, s_mu, s_chol);
+      lower_item<IPL, ROAD>(A, P, D, slot, w - A.blk_prefix[pos], l, U, s_dyn, s_road, s_red, s_mu, s_chol,
+                            s_gred);
       // every wave's rows written and its reads done, at device scope,
       // before the workgroup counts itself
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
