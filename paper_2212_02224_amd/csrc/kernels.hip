@@ -306,22 +306,24 @@ __device__ __forceinline__ RoadAt road_at(const Scal &S, const float4 *__restric
 // reduce16 leaves lane l (p = l & 15) the sum of value l >> 2 over lanes
 // q + {0, 32, 16, 48} for q = p, p ^ 15, p ^ 7, p ^ 8, as the balanced tree
 // ((G(p) + G(p^15)) + (G(p^7) + G(p^8))), G(q) = (v_q + v_q+32) + (v_q+16 +
-// v_q+48). Here every lane writes its 16 values to its row of s_w (this
-// wave's 64 x kRedStride floats), adds the same 16 values in the same tree,
-// and finishes with the same quad steps: 17 vector instructions against 35,
-// for 4 row writes and 16 reads. The wave's own LDS operations run in order,
-// so the reads see the writes, and a later call's writes follow this call's
-// reads.
-constexpr int kRedStride = 20;  // 16-byte rows; reads at most 2-way bank conflicts
+// v_q+48). Here value k of lane s goes to s_w[64 k + 4 (s & 15) + (s >> 4)]
+// (this wave's 16 x 64 floats), so the four values of G(q) are one 16-byte
+// read; lane l adds the same 16 values in the same tree and finishes with
+// the same quad steps: 17 vector instructions against 35. The writes of one
+// value and the 16-byte reads each touch 64 distinct banks. The wave's own
+// LDS operations run in order, so the reads see the writes, and a later
+// call's writes follow this call's reads.
+constexpr int kRedFloats = 16 * 64;  // per wave
 __device__ __forceinline__ float reduce16_lds(const float (&v)[16], int lane, float *s_w) {
-  float4 *row = reinterpret_cast<float4 *>(s_w + lane * kRedStride);
+  float *col = s_w + 4 * (lane & 15) + (lane >> 4);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) row[j] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+  for (int k = 0; k < 16; ++k) col[64 * k] = v[k];
   __builtin_amdgcn_wave_barrier();
-  const int k = lane >> 2, p = lane & 15;
+  const int p = lane & 15;
+  const float4 *row = reinterpret_cast<const float4 *>(s_w + 64 * (lane >> 2));
   auto grp = [&](int q) -> float {
-    const float *c = s_w + q * kRedStride + k;
-    return (c[0] + c[32 * kRedStride]) + (c[16 * kRedStride] + c[48 * kRedStride]);
+    const float4 x = row[q];
+    return (x.x + x.z) + (x.y + x.w);
   };
   float d = (grp(p) + grp(p ^ 15)) + (grp(p ^ 7) + grp(p ^ 8));
   __builtin_amdgcn_wave_barrier();
@@ -866,7 +868,7 @@ __device__ __forceinline__ void lower_setup(const LowerArgs &A, const MethodPara
 // iteration l, with the request's set-up in U and LDS: the sample p_j,
 // step 1, K projection iterations, residual and upper cost, rows written.
 // Every thread of the workgroup calls it (it holds barriers).
-// s_gred: 4 x 64 x kRedStride floats for the two-instants-per-lane sums.
+// s_gred: 4 x kRedFloats floats for the two-instants-per-lane sums.
 template <int IPL, bool ROAD>
 __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParams &P, const ReqDesc &D, int slot,
                                            int rank, int l, const LowerSetup<IPL> &U, const float4 *s_obs,
@@ -963,7 +965,7 @@ __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParam
     for (int u = 0; u < IPL; ++u) {
       float g[16];
       g_of(L[u], cr[u], g);
-      if constexpr (IPL == 2) r[u] = reduce16_lds(g, lane, s_gred + wave * kWave * kRedStride);
+      if constexpr (IPL == 2) r[u] = reduce16_lds(g, lane, s_gred + wave * kRedFloats);
       else r[u] = reduce16(g, lane);
     }
     const float acc = combine(r, (lane & 3) == 0, v);
@@ -1029,7 +1031,7 @@ lower_kernel(LowerArgs A, MethodParams P) {
   __shared__ float s_red[2][4 * IPL][16];
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
-  __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kWave * kRedStride : 4];
+  __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kRedFloats : 4];
 
   const int2 bi = block_slot(A);
   const ReqDesc &D = A.desc[bi.x];
@@ -2255,7 +2257,7 @@ __global__ void __launch_bounds__(kBlock) lower_fused_kernel(LowerArgs A, SelArg
   __shared__ float s_red[2][4 * IPL][16];
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
-  __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kWave * kRedStride : 4];
+  __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kRedFloats : 4];
   __shared__ int s_msg[3];
 
   const int n_act = A.n_act;
