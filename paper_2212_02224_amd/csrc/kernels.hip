@@ -818,7 +818,7 @@ template <int IPL>
 struct LowerSetup {
   Lane L[IPL];
   Scal S;
-  float arow[16];
+  float arow[4];  // A^-1[v][4 (lane & 3) + i], v = lane >> 2
   float Dv;
 };
 
@@ -860,7 +860,7 @@ __device__ __forceinline__ void lower_setup(const LowerArgs &A, const MethodPara
   const int v = h.lane >> 2;
   const float *Pj = A.proj + (size_t)D.tm_idx * kProjFloats;
 #pragma unroll
-  for (int c = 0; c < 16; ++c) U.arow[c] = Pj[v * 16 + c];
+  for (int i = 0; i < 4; ++i) U.arow[i] = Pj[v * 16 + 4 * (h.lane & 3) + i];
   U.Dv = Pj[256 + v];
 }
 
@@ -976,15 +976,19 @@ __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParam
   float Gv = pass();
 
   const int K = P.K;
+  const int rs_addr = 64 * (lane & 3);  // byte address of lane 16 (lane & 3), the row's first rhs of this quarter
   for (int k = 1; k <= K; ++k) {
-    // xi-update (eq. split_xy) in the free coordinates
+    // xi-update (eq. split_xy) in the free coordinates: lane 4 v + j adds
+    // the terms k = 4 j .. 4 j + 3 of row v of A^-1 (rhs_k from lane 4 k, a
+    // cross-lane read on the LDS crossbar), and the four quarter sums are
+    // added over the lane quad, (q0 + q1) + (q2 + q3) in every lane
     const float rhs = fmaf(Dv, zb - z, fmaf(S.rho, Gv, mu));
-    float rs[15];
-#pragma unroll
-    for (int c = 0; c < 15; ++c) rs[c] = bcast(rhs, 4 * c);
     float dz = 0.f;
 #pragma unroll
-    for (int c = 0; c < 15; ++c) dz = fmaf(U.arow[c], rs[c], dz);
+    for (int i = 0; i < 4; ++i)
+      dz = fmaf(U.arow[i], __int_as_float(__builtin_amdgcn_ds_bpermute(rs_addr + 16 * i, __float_as_int(rhs))), dz);
+    dz += dpp<kDppQuadSwap1>(dz);
+    dz += dpp<kDppQuadSwap2>(dz);
     z += dz;
 #pragma unroll
     for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
