@@ -868,12 +868,13 @@ __device__ __forceinline__ void lower_setup(const LowerArgs &A, const MethodPara
 // iteration l, with the request's set-up in U and LDS: the sample p_j,
 // step 1, K projection iterations, residual and upper cost, rows written.
 // Every thread of the workgroup calls it (it holds barriers).
-// s_gred: 4 x kRedFloats floats for the two-instants-per-lane sums.
+// s_gred: 4 x kRedFloats floats for the two-instants-per-lane sums; s_zb: 4 x
+// 16 floats for its coefficient broadcasts.
 template <int IPL, bool ROAD>
 __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParams &P, const ReqDesc &D, int slot,
                                            int rank, int l, const LowerSetup<IPL> &U, const float4 *s_obs,
                                            const float4 *s_road, float (*s_red)[4 * IPL][16], double *s_mu,
-                                           double *s_chol, float *s_gred) {
+                                           double *s_chol, float *s_gred, float *s_zb) {
   const LowerShape h = lower_shape<IPL>(D.T);
   const int T = D.T, M = D.M, N = D.N;
   const int npair = (M + 1) >> 1;
@@ -921,8 +922,28 @@ __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParam
   }
   float z = zb, mu = 0.f;
   float zs[15];
+  // Every lane's copy of the 15 coefficients (lane 4 c holds coefficient c):
+  // v_readlane to scalar registers, or with two instants per lane through
+  // this wave's 16 words of LDS (one write, four 16-byte broadcast reads, no
+  // vector instructions; the wave's LDS operations run in order).
+  auto broadcast_z = [&]() {
+    if constexpr (IPL == 2) {
+      float *w = s_zb + 16 * wave;
+      if ((lane & 3) == 0) w[lane >> 2] = z;
+      __builtin_amdgcn_wave_barrier();
+      const float4 *w4 = reinterpret_cast<const float4 *>(w);
+      const float4 q0 = w4[0], q1 = w4[1], q2 = w4[2], q3 = w4[3];
+      zs[0] = q0.x; zs[1] = q0.y; zs[2] = q0.z; zs[3] = q0.w;
+      zs[4] = q1.x; zs[5] = q1.y; zs[6] = q1.z; zs[7] = q1.w;
+      zs[8] = q2.x; zs[9] = q2.y; zs[10] = q2.z; zs[11] = q2.w;
+      zs[12] = q3.x; zs[13] = q3.y; zs[14] = q3.z;
+      __builtin_amdgcn_wave_barrier();
+    } else {
 #pragma unroll
-  for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
+      for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
+    }
+  };
+  broadcast_z();
 
   // Initial d_a: clip(|a(xi_bar)|, 0, a_max).
   float da_prev[IPL];
@@ -990,8 +1011,7 @@ __device__ __forceinline__ void lower_item(const LowerArgs &A, const MethodParam
     dz += dpp<kDppQuadSwap1>(dz);
     dz += dpp<kDppQuadSwap2>(dz);
     z += dz;
-#pragma unroll
-    for (int c = 0; c < 15; ++c) zs[c] = bcast(z, 4 * c);
+    broadcast_z();
     if (k < K) {
       Gv = pass();
       mu = fmaf(0.5f * S.rho, Gv, mu);  // eq. update_lagrange
@@ -1036,13 +1056,14 @@ lower_kernel(LowerArgs A, MethodParams P) {
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
   __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kRedFloats : 4];
+  __shared__ __align__(16) float s_zb[IPL == 2 ? 4 * 16 : 4];
 
   const int2 bi = block_slot(A);
   const ReqDesc &D = A.desc[bi.x];
   const int l = A.l_uniform >= 0 ? A.l_uniform : D.cur_iter;
   LowerSetup<IPL> U;
   lower_setup<IPL, ROAD>(A, P, D, s_obs, s_road, U);
-  lower_item<IPL, ROAD>(A, P, D, bi.x, bi.y, l, U, s_obs, s_road, s_red, s_mu, s_chol, s_gred);
+  lower_item<IPL, ROAD>(A, P, D, bi.x, bi.y, l, U, s_obs, s_road, s_red, s_mu, s_chol, s_gred, s_zb);
 }
 
 // ---------------------------------------------------------------------------
@@ -2262,6 +2283,7 @@ __global__ void __launch_bounds__(kBlock) lower_fused_kernel(LowerArgs A, SelArg
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float4 s_road[ROAD ? PLAN_MAX_ROAD : 1];
   __shared__ __align__(16) float s_gred[IPL == 2 ? 4 * kRedFloats : 4];
+  __shared__ __align__(16) float s_zb[IPL == 2 ? 4 * 16 : 4];
   __shared__ int s_msg[3];
 
   const int n_act = A.n_act;
@@ -2298,7 +2320,7 @@ __global__ void __launch_bounds__(kBlock) lower_fused_kernel(LowerArgs A, SelArg
     }
     if (go) {
       lower_item<IPL, ROAD>(A, P, D, slot, w - A.blk_prefix[pos], l, U, s_dyn, s_road, s_red, s_mu, s_chol,
-                            s_gred);
+                            s_gred, s_zb);
       // every wave's rows written and its reads done, at device scope,
       // before the workgroup counts itself
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
