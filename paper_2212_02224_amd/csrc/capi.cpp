@@ -103,15 +103,19 @@ int blocks_for(int N, int T, bool mfma, int ipl = 1) {
   return (N + spb - 1) / spb;
 }
 
-// Two instants per lane or one? Both give the same results. Workgroups run
-// in rounds of 4 per CU (one instant per lane, 120 VGPRs) or 3 per CU (two,
-// 162 VGPRs), and a round of two instants per lane takes about 1.45 times one
-// of one instant per lane (measured on full launches of N = 512..4096,
-// T = 100, M = 4..20); the variant with the fewer weighted rounds is taken.
+// Two instants per lane or one? Both give the same results. A workgroup of
+// two instants per lane holds 4 samples (one wave each), one of one instant
+// per lane 2 samples (two waves each, T = 100), so the first has half the
+// waves: it is faster once its launch gives every SIMD about two waves, and
+// slower below that, where the latency of each wave's chain is not hidden.
+// Lower-kernel time per launch at T = 100 (one instant / two instants per
+// lane): 1000 samples 37.1 / 43.2 us (M = 10), 46.8 / 56.1 us (M = 20); 2048
+// samples 52.9 / 49.4, 65.8 / 62.3; 4096 samples 89.7 / 88.4, 111.1 / 112.8;
+// 8192 samples 161 / 140, 198 / 180; 524288 samples 9.25 / 7.90 ms,
+// 11.0 / 10.0 ms. Two instants per lane from 2 workgroups per CU on.
 bool use_ipl2(int blocks1, int blocks2, int n_cu) {
-  const int r1 = (blocks1 + 4 * n_cu - 1) / (4 * n_cu);
-  const int r2 = (blocks2 + 3 * n_cu - 1) / (3 * n_cu);
-  return 29 * r2 < 20 * r1;
+  (void)blocks1;
+  return blocks2 >= 2 * n_cu;
 }
 
 // Lower-level launches of one upper iteration: one per horizon length in the
