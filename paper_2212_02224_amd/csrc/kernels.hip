@@ -383,8 +383,9 @@ __device__ __forceinline__ void near_update(float q, float dx, float dy, float &
 // update), hence the gate changes no result. On the headline's scenes about
 // 90% of (wave, neighbour) pairs fail it, so the common case costs two
 // subtractions and two compares; it pays where a lane carries two instants
-// (measured -10% at M = 20), not with one instant per lane or on the matrix
-// cores (within +-2%), where the launches leave it out.
+// (measured -10% at M = 20) and in the FP32 matrix-core form (-7%), not with
+// one instant per lane (within +-2%) or in the FP16 split (much slower), where
+// the launches leave it out.
 // `live`: the lanes whose instant is inside the horizon (the others take no
 // part in the gate).
 template <bool GATE>
@@ -399,17 +400,27 @@ __device__ __forceinline__ void pair_update(float xs, float ys, const float4 &o,
   }
 }
 
+// Neighbour sums of one lane's instant t (the matrix-core kernels): the
+// entries of pairs c and c + 1 in alternating registers. GATE (the FP32
+// matrix-core form: 91.2 -> 85.1 ms at the headline shape) skips a pair as
+// pair_update does; the FP16 split leaves it out (its branches cost it the
+// overlap of its matrix products with the vector work: 78 -> 118 ms).
+template <bool GATE>
 __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, int npair, int T, int t,
-                                               float xs, float ys, float &ax, float &ay) {
+                                               float xs, float ys, uint64_t live, float &ax, float &ay) {
   ax = 0.f;
   ay = 0.f;
   if (npair == 0) return;
-  float4 cur = obs[t];
-  for (int c = 0; c < npair; ++c) {
-    const float4 nxt = obs[(c + 1 < npair ? c + 1 : c) * T + t];
-    pair_update<false>(xs, ys, cur, ~0ull, ax, ay);
-    cur = nxt;
+  const float4 *p = obs + t;
+  float4 a = p[0], b;
+  int c = 0;
+  for (; c + 1 < npair; c += 2) {
+    b = p[(c + 1) * T];
+    pair_update<GATE>(xs, ys, a, live, ax, ay);
+    a = p[(c + 2 < npair ? c + 2 : c + 1) * T];
+    pair_update<GATE>(xs, ys, b, live, ax, ay);
   }
+  if (c < npair) pair_update<GATE>(xs, ys, a, live, ax, ay);
 }
 
 // Differences between the targets of one (alpha, d) step and the current
@@ -462,12 +473,12 @@ __device__ __forceinline__ Corr targets_from(const State6 &s, const Scal &S, con
   return c;
 }
 
-template <bool ROAD>
+template <bool ROAD, bool GATE>
 __device__ __forceinline__ Corr targets_at(const State6 &s, const Scal &S, const float4 *__restrict__ obs,
                                            const float4 *__restrict__ road, int npair, int T, int t, bool tv,
                                            float &da_prev) {
   float ax, ay;
-  neighbour_pass(obs, npair, T, t, s.x * S.ia, s.y * S.ib, ax, ay);
+  neighbour_pass<GATE>(obs, npair, T, t, s.x * S.ia, s.y * S.ib, __builtin_amdgcn_ballot_w64(tv), ax, ay);
   return targets_from(s, S, road_at<ROAD>(S, road, s.x, t), ax, ay, tv, da_prev);
 }
 
@@ -1410,7 +1421,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
             const int t = 4 * tile + g;
             const State6 st = evaluate(tile, co);
             if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-            acc = accumulate(tile, targets_at<ROAD>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
+            acc = accumulate(tile, targets_at<ROAD, F32>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
                                                     active && t < T, da[i]),
                              acc);
           }
