@@ -585,12 +585,22 @@ __device__ __forceinline__ void residual_at(const State6 &s, const Scal &S, cons
   cost = tv ? e * e : 0.f;
 }
 
-// Workgroup -> slot: binary search of the workgroup index in the prefix
-// counts of the launch's active slots (uniform scalar loads). Returns the
-// slot and the workgroup's rank within it.
+// Logical workgroup index of dispatched workgroup b out of n. Workgroups go
+// round-robin to the 8 XCDs (b % 8), each with its own L2; XCD x takes one
+// contiguous range of logical workgroups, so neighbouring samples' residual
+// and cost words (4 bytes each, a few samples per workgroup) meet in one L2
+// and reach HBM as whole sectors. A bijection for any n.
+__device__ __forceinline__ int xcd_logical(int b, int n) {
+  const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + i;
+}
+
+// Workgroup -> slot: binary search of the logical workgroup index in the
+// prefix counts of the launch's active slots (uniform scalar loads). Returns
+// the slot and the workgroup's rank within it.
 __device__ __forceinline__ int2 block_slot(const LowerArgs &A) {
   int lo = 0, hi = A.n_act - 1;
-  const int b = blockIdx.x;
+  const int b = xcd_logical(blockIdx.x, gridDim.x);
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (A.blk_prefix[mid] <= b) lo = mid;
