@@ -435,8 +435,15 @@ def plan_poll_done(h: Handle, max_n: int = 64) -> list[tuple[int, Result]]:
     """Every finished served request (up to max_n), in ticket order, as
     (ticket, Result) pairs; an empty list while none has finished."""
     Tmax = max(int(h.cfg.T_set[i]) for i in range(h.cfg.n_T))
-    out = _Results([Tmax] * max_n)
-    tickets = (C.c_uint64 * max(1, max_n))()
+    # one result buffer per handle, grown on demand: a served loop calls this
+    # every tick, and building max_n trajectory buffers each time would cost
+    # more host time than the tick itself
+    buf = getattr(h, "_poll_buf", None)
+    if buf is None or buf[0] < max(1, max_n):
+        cap = max(1, max_n)
+        buf = (cap, _Results([Tmax] * cap), (C.c_uint64 * cap)())
+        h._poll_buf = buf
+    _, out, tickets = buf
     n = C.c_int32()
     _check(load().plan_poll_done(h.ptr, tickets, out.arr, max_n, C.byref(n)), h.ptr)
     got = []
@@ -445,7 +452,7 @@ def plan_poll_done(h: Handle, max_n: int = 64) -> list[tuple[int, Result]]:
         T = getattr(h, "_ticket_T", {}).pop(t, Tmax)
         r = out.result(i)
         if r.traj is not None:
-            r.traj = r.traj[:T]
+            r.traj = r.traj[:T].copy()  # the buffer is reused by the next call
         got.append((t, r))
     return got
 
