@@ -141,8 +141,9 @@ def cpu_baseline_leg(pl, workload, n_sub=8, acc_scenes=2, acc_samples=512):
     samples on every granted thread; QP-solves/s, and the whole job's time
     extrapolated from it. Beside it: a single-thread figure (one C2 plan of
     250 samples, per-solve rate and the C2 plan time extrapolated to
-    N = 1000), one whole C2 plan on every thread, and one C1 plan single
-    threaded.
+    N = 1000), one whole C2 plan on every thread, one C1 plan single
+    threaded, and the served stream (C4) from the first upper iteration of
+    one request per (N, T) pair of its mix on every thread, extrapolated.
 
     Accuracy: the oracle's samples of acc_scenes headline scenes (its own
     draw, acc_samples each) through the oracle's lower level and through
@@ -191,6 +192,27 @@ def cpu_baseline_leg(pl, workload, n_sub=8, acc_scenes=2, acc_samples=512):
         "c1_plan_s": dtc1, "sample": "one C2 plan of 250 samples (L=5, K=20, T=100, M=10) and one C1 plan "
                                      "(N=64, L=3, K=10, T=50, M=4), one thread"}
     out["cpu_baseline"]["c2_plan_all_threads"] = {"solves_per_s": c2["N"] * c2["L"] / dt2, "plan_s": dt2}
+    # C4, the served stream: the first upper iteration of one request for
+    # each (N, T) of the stream's mix (its first request with that pair, so
+    # its own M and scene), every thread; the stream's oracle time (L upper
+    # iterations of every request) extrapolated by its solve count
+    mix = workload.served_mix(SERVED_REQUESTS, SERVED_SEED)
+    picked = {}
+    for i, (N, M, T) in enumerate(mix):
+        picked.setdefault((N, T), (i, N, M, T))
+    t0 = time.perf_counter()
+    sub = 0
+    for i, N, M, T in sorted(picked.values()):
+        s = workload.scene(4, i, M)
+        oracle.plan(oracle.default_params(T=T, M=M, K=SERVED_K, L=1), oracle.Scene(s.ego, s.obstacles), s.seed, N)
+        sub += N
+    dt4 = time.perf_counter() - t0
+    total4 = sum(N for N, _, _ in mix) * SERVED_L
+    out["cpu_baseline"]["c4_stream_all_threads"] = {
+        "solves_per_s": sub / dt4, "subset_s": dt4, "stream_s_extrapolated": total4 * dt4 / sub,
+        "sample": f"first upper iteration of {len(picked)} of the served stream's {SERVED_REQUESTS} requests, "
+                  f"one per (N, T) pair (K={SERVED_K}, M and scene their own, {sub} solves, {dt4:.1f} s); "
+                  f"the stream's {total4} solves (L={SERVED_L}) extrapolated"}
     # accuracy of each GPU precision against the oracle, teacher-forced
     acc = {}
     for prec, name in ((pl.PLAN_PREC_FP32, "fp32_valu"), (pl.PLAN_PREC_FP32_MFMA, "fp32_mfma"),
@@ -266,15 +288,18 @@ def _run_served(pl, h, reqs, arrivals):
     return lat, time.perf_counter() - t0
 
 
-def served_bench(pl, workload, torch, n_req=256, slots=64, loads=(0.5, 0.7, 0.9)):
+SERVED_REQUESTS, SERVED_SEED, SERVED_L, SERVED_K = 256, 4, 5, 20
+
+
+def served_bench(pl, workload, torch, n_req=SERVED_REQUESTS, slots=64, loads=(0.5, 0.7, 0.9)):
     """The served stream in the FP32 and FP16-split forms, each with the host
     waiting for every iteration (served_run_ahead 0, the default) and with one
     iteration enqueued ahead, and in the FP32 matrix-core form: the saturated rate of each (all requests at t = 0), then
     the same Poisson arrival sequences for all at the given fractions of the
     FP32 saturated rate; p50/p99 latency."""
     import numpy as np
-    L, K = 5, 20
-    reqs = served_stream(pl, workload, n_req)
+    L, K = SERVED_L, SERVED_K
+    reqs = served_stream(pl, workload, n_req, SERVED_SEED)
     solves = sum(r.N for r in reqs) * L
     handles, out = {}, {}
     for name, prec, ahead in (("f32", 0, 0), ("fp16_split", 1, 0), ("fp32_mfma", 2, 0), ("f32_run_ahead1", 0, 1),
