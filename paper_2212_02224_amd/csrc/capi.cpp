@@ -96,9 +96,12 @@ int t_class(int T) { return T > kWave ? 2 : 1; }
 
 // Workgroups of one request. VALU kernel: ceil(T / (64 ipl)) waves per
 // sample with ipl instants per lane, 4 waves per group; matrix-core kernel:
-// 16 samples per group.
-int blocks_for(int N, int T, bool mfma, int ipl = 1) {
-  if (mfma) return (N + kMfmaSamples - 1) / kMfmaSamples;
+// 16 samples per group, or 8 in its one-pair-per-wave layout (half).
+int blocks_for(int N, int T, bool mfma, int ipl = 1, bool half = false) {
+  if (mfma) {
+    const int spb = half ? kMfmaSamples / 2 : kMfmaSamples;
+    return (N + spb - 1) / spb;
+  }
   const int spb = 4 / ((T + kWave * ipl - 1) / (kWave * ipl));
   return (N + spb - 1) / spb;
 }
@@ -126,6 +129,7 @@ struct LaunchSet {
   struct Group {
     int act_off = 0, n = 0, nblocks = 0, T = 0;
     int ipl = 1;        // VALU kernel: instants per lane
+    int tpw = 4;        // matrix-core kernel: 4 tiles per wave, or 1 (a tile pair over 8 samples)
     bool road = false;  // requests with a road profile
     size_t lds = 0;
   } grp[8];
@@ -660,6 +664,19 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
     gr.nblocks = blocks;
     prefix[pos + k] = blocks;
     gr.T = keys[kk];
+    if (mf && blocks < 2 * h->n_cu) {
+      // light load: workgroups of 8 samples, one tile pair per wave (twice
+      // the workgroups, half the serial work of each; the same arithmetic)
+      gr.tpw = 1;
+      blocks = 0;
+      for (int i = gr.act_off; i < pos; ++i) {
+        const ReqDesc &d = h->h_desc[act[i]];
+        prefix[i + k] = blocks;
+        blocks += blocks_for(d.N, d.T, true, 1, true);
+      }
+      gr.nblocks = blocks;
+      prefix[pos + k] = blocks;
+    }
     if (!mf && keys[kk] == 2) {
       int blocks2 = 0;
       for (int i = gr.act_off; i < pos; ++i) {
@@ -688,7 +705,11 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
   // only join the barriers), so its groups do not wait for each other. The
   // arithmetic per request is the same in any launch.
   int total = 0;
-  for (int kk = 0; kk < nkeys; ++kk) total += ls.grp[k0 + kk].nblocks;
+  if (mf) {
+    for (int i = pos0; i < pos0 + n; ++i) total += blocks_for(h->h_desc[act[i]].N, h->h_desc[act[i]].T, true);
+  } else {
+    for (int kk = 0; kk < nkeys; ++kk) total += ls.grp[k0 + kk].nblocks;
+  }
   const bool merge = nkeys > 1 && (mf ? total < 2 * h->n_cu : ls.grp[k0 + nkeys - 1].ipl == 1);
   if (!merge) return;
   LaunchSet::Group all;
@@ -696,11 +717,12 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
   all.act_off = pos0;
   all.n = n;
   all.T = mf ? ls.grp[k0 + nkeys - 1].T : 1;
+  all.tpw = 1;  // matrix-core: merged only under light load
   int blocks = 0;
   for (int i = pos0; i < pos0 + n; ++i) {
     const ReqDesc &d = h->h_desc[act[i]];
     prefix[i + k0] = blocks;
-    blocks += blocks_for(d.N, d.T, mf, 1);
+    blocks += blocks_for(d.N, d.T, mf, 1, mf);
     all.lds = std::max(all.lds, lds_bytes(d.M, d.T, mf, mfma_f32(h->cfg)));
   }
   prefix[pos0 + n + k0] = blocks;
@@ -749,10 +771,10 @@ plan_status launch_lower_group(plan_handle *h, const LaunchSet &ls, int k, int l
   return timed(
       h, 0,
       [&](hipEvent_t a, hipEvent_t b) {
-        // two tiles per wave while a launch cannot fill every CU with two
-        // workgroups, else four (same arithmetic either way)
-        const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
-        return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds,
+        // matrix cores: one tile pair per wave over 8 samples while 16-sample
+        // workgroups cannot give every CU two, else four tiles per wave
+        // (same arithmetic either way)
+        return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, gr.tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds,
                                       h->stream, a, b)
                   : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, a, b);
       },
@@ -1606,9 +1628,8 @@ plan_status plan_lower_solve_static(plan_handle *h, const plan_request *req, con
     la.cost = cost_upper;
     la.xi_bar_out = xi_bar;
     la.xi_star_out = xi_star;
-    const int tpw = gr.nblocks >= 2 * h->n_cu ? 4 : 2;
     const hipError_t e =
-        mf ? launch_lower_mfma(la, h->mp, gr.nblocks, tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds, h->stream,
+        mf ? launch_lower_mfma(la, h->mp, gr.nblocks, gr.tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds, h->stream,
                                nullptr, nullptr)
            : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(h, e, mf ? "lower_mfma_kernel" : "lower_kernel");

@@ -76,6 +76,7 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141;
+constexpr int kDppRowRor8 = 0x128;  // row_ror:8, lane i reads lane i ^ 8 of its row
 constexpr int kDppQuadSwap2 = 0x4e;  // quad_perm [2,3,0,1]
 constexpr int kDppQuadSwap1 = 0xb1;  // quad_perm [1,0,3,2]
 
@@ -1225,7 +1226,8 @@ __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int N, i
 //               its B element);
 //   xi-update   4 products per iteration (A^-1 in FP32, rhs transposed).
 template <int TPW, bool ROAD, bool F32>
-__global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_kernel(LowerArgs A, MethodParams P) {
+__global__ void __launch_bounds__(kWave *(TPW == 1 ? kMfmaMaxPairs : kMfmaMaxT / (4 * TPW)))
+    lower_mfma_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_dyn[];
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float s_rc[kMfmaMaxPairs][kMfmaSamples][2];
@@ -1241,7 +1243,12 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   const int NPr = (NT + 1) >> 1;       // tile pairs
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int n = lane & 15, g = lane >> 4;
-  const int j = bi.y * kMfmaSamples + n;
+  // TPW = 1: a workgroup of 8 samples, one tile pair per wave. Columns n and
+  // n + 8 of every product carry the same sample (its state held twice); the
+  // lanes of columns 8..15 take the pair's second tile (hh = 1).
+  constexpr bool kHalf = TPW == 1;
+  const int hh = kHalf ? n >> 3 : 0;
+  const int j = bi.y * (kHalf ? kMfmaSamples / 2 : kMfmaSamples) + (kHalf ? (n & 7) : n);
   const bool active = j < N;
   const size_t slot_off = (size_t)D.row_off;
 
@@ -1349,7 +1356,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
 #pragma unroll
     for (int u = 0; u < 4; ++u) zb[u] = step1_coef(step1_inputs(S1, D, 4 * g + u), P, pin);
   }
-  if (!forced && active && wave == 0 && g == 0) {
+  if (!forced && active && wave == 0 && g == 0 && hh == 0) {
     float4 *dst = reinterpret_cast<float4 *>(A.p + (slot_off + j) * 8);
     dst[0] = make_float4(pin[0], pin[1], pin[2], pin[3]);
     dst[1] = make_float4(pin[4], pin[5], pin[6], pin[7]);
@@ -1417,26 +1424,62 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
       return mma32(cl, dh, acc);
     }
   };
+  // N^T g of a tile pair: tile b's products accumulate onto tile a's sum.
   auto pass = [&](bool first) -> f4 {
     const CoefOps co = coef_ops(z);
+    if constexpr (kHalf) {
+      const int pair = wave, ta = 2 * pair;
+      if (ta < NT) {
+        // both tiles' products over all 16 columns; each lane keeps its
+        // column half's tile (the fixed part it reads is its own instant's)
+        const bool has_b = ta + 1 < NT;
+        const int t = 4 * (ta + hh) + g;
+        const State6 s0 = evaluate(ta, co), s1 = has_b ? evaluate(ta + 1, co) : s0;
+        const State6 st = hh ? s1 : s0;
+        if (first) da[0] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
+        const Corr c = targets_at<ROAD, F32>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1, active && t < T,
+                                             da[0]);
+        // tile a's sum of each sample sits in column n < 8; rotated to column
+        // n + 8 it starts tile b's products there, and the pair's sum comes
+        // back to column n (the same chain as one wave over both tiles). The
+        // rotations run on every lane before any per-lane choice: a lane
+        // switched off would read as zero.
+        const f4 a0 = accumulate(ta, c, f4{0.f, 0.f, 0.f, 0.f});
+        f4 rot, acc;
 #pragma unroll
-    for (int pr = 0; pr < TPW / 2; ++pr) {
-      const int pair = wave * (TPW / 2) + pr;
-      if (2 * pair < NT) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int u = 0; u < 4; ++u) rot[u] = dpp<kDppRowRor8>(a0[u]);
+        if (has_b) {
+          const f4 a1 = accumulate(ta + 1, c, rot);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int i = 2 * pr + h, tile = 2 * pair + h;
-          if (tile < NT) {
-            const int t = 4 * tile + g;
-            const State6 st = evaluate(tile, co);
-            if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-            acc = accumulate(tile, targets_at<ROAD, F32>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
-                                                    active && t < T, da[i]),
-                             acc);
-          }
+          for (int u = 0; u < 4; ++u) rot[u] = dpp<kDppRowRor8>(a1[u]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] = hh ? a1[u] : rot[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] = hh ? rot[u] : a0[u];
         }
         s_part[pair * kWave + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      }
+    } else {
+#pragma unroll
+      for (int pr = 0; pr < TPW / 2; ++pr) {
+        const int pair = wave * (TPW / 2) + pr;
+        if (2 * pair < NT) {
+          f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int i = 2 * pr + h, tile = 2 * pair + h;
+            if (tile < NT) {
+              const int t = 4 * tile + g;
+              const State6 st = evaluate(tile, co);
+              if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
+              acc = accumulate(tile, targets_at<ROAD, F32>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
+                                                      active && t < T, da[i]),
+                               acc);
+            }
+          }
+          s_part[pair * kWave + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        }
       }
     }
     __syncthreads();
@@ -1493,20 +1536,31 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
   {
     const CoefOps co = coef_ops(z);
 #pragma unroll
-    for (int pr = 0; pr < TPW / 2; ++pr) {
-      const int pair = wave * (TPW / 2) + pr;
+    for (int pr = 0; pr < (kHalf ? 1 : TPW / 2); ++pr) {
+      const int pair = kHalf ? wave : wave * (TPW / 2) + pr;
       if (2 * pair < NT) {
         float rr = 0.f, cc = 0.f;
+        if constexpr (kHalf) {
+          const int ta = 2 * pair, t = 4 * (ta + hh) + g;
+          const bool has_b = ta + 1 < NT;
+          const State6 s0 = evaluate(ta, co), s1 = has_b ? evaluate(ta + 1, co) : s0;
+          float r1, c1;
+          residual_at<ROAD>(hh ? s1 : s0, S, s_obs, s_road, npair, T, t < T ? t : T - 1, active && t < T, r1,
+                            c1);
+          rr = r1 + dpp<kDppRowRor8>(r1);  // tile a's term plus tile b's (column n ^ 8)
+          cc = c1 + dpp<kDppRowRor8>(c1);
+        } else {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int tile = 2 * pair + h;
-          if (tile < NT) {
-            const int t = 4 * tile + g;
-            float r1, c1;
-            residual_at<ROAD>(evaluate(tile, co), S, s_obs, s_road, npair, T, t < T ? t : T - 1,
-                              active && t < T, r1, c1);
-            rr += r1;
-            cc += c1;
+          for (int h = 0; h < 2; ++h) {
+            const int tile = 2 * pair + h;
+            if (tile < NT) {
+              const int t = 4 * tile + g;
+              float r1, c1;
+              residual_at<ROAD>(evaluate(tile, co), S, s_obs, s_road, npair, T, t < T ? t : T - 1,
+                                active && t < T, r1, c1);
+              rr += r1;
+              cc += c1;
+            }
           }
         }
         float a = rr, b = rr;
@@ -1532,7 +1586,7 @@ __global__ void __launch_bounds__(kWave *(kMfmaMaxT / (4 * TPW))) lower_mfma_ker
     }
   }
   __syncthreads();
-  if (wave != 0 || !active) return;
+  if (wave != 0 || !active || hh != 0) return;
   float rr = 0.f, cc = 0.f;
   for (int w = 0; w < NPr; ++w) {
     rr += s_rc[w][n][0];
@@ -2422,11 +2476,11 @@ hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, 
 }
 hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, bool f32,
                              int T, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if ((tpw != 2 && tpw != 4) || T < 1 || T > kMfmaMaxT) return hipErrorInvalidValue;
-  const int waves = (T + 4 * tpw - 1) / (4 * tpw);
-  auto kern = f32 ? (tpw == 2 ? (road ? lower_mfma_kernel<2, true, true> : lower_mfma_kernel<2, false, true>)
+  if ((tpw != 1 && tpw != 4) || T < 1 || T > kMfmaMaxT) return hipErrorInvalidValue;
+  const int waves = tpw == 1 ? ((T + 3) / 4 + 1) / 2 : (T + 4 * tpw - 1) / (4 * tpw);
+  auto kern = f32 ? (tpw == 1 ? (road ? lower_mfma_kernel<1, true, true> : lower_mfma_kernel<1, false, true>)
                               : (road ? lower_mfma_kernel<4, true, true> : lower_mfma_kernel<4, false, true>))
-                  : (tpw == 2 ? (road ? lower_mfma_kernel<2, true, false> : lower_mfma_kernel<2, false, false>)
+                  : (tpw == 1 ? (road ? lower_mfma_kernel<1, true, false> : lower_mfma_kernel<1, false, false>)
                               : (road ? lower_mfma_kernel<4, true, false> : lower_mfma_kernel<4, false, false>));
   if (ev0 != nullptr)
     hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(kWave * waves), (uint32_t)lds, st, ev0, ev1, 0, a, p);
