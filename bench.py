@@ -549,7 +549,7 @@ def plan_legs(pl, torch, workload, c, args, out):
             "precision": "fp16_split", "value": N * L * psteps / el3, "unit": "QP-solves/s",
             "ms_per_plan": 1e3 * el3 / psteps,
             "roofline": roofline(1, ms3["lower"] / max(1, cnt3["lower"]), N, T, M, K, cnt3["lower"], c["name"],
-                                 kernel="lower_mfma_kernel<2, false, false>"),
+                                 kernel="lower_mfma_kernel<1, false, false>"),
             "kernel_ms_per_step": {k: ms3[k] / psteps for k in ms3},
             "plan": {"best_index": res3.best_index, "cost_upper": res3.cost_upper, "residual": res3.residual}}
     return psteps, pwarm

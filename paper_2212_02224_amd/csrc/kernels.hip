@@ -1091,9 +1091,9 @@ lower_kernel(LowerArgs A, MethodParams P) {
 // ---------------------------------------------------------------------------
 // Lower level on the matrix cores (FP16 high/low split, FP32 accumulation).
 //
-// A workgroup serves 16 samples of one request with ceil(T / (4 TPW)) waves;
-// wave w owns the instant tiles TPW w .. TPW w + TPW - 1 (4 instants each;
-// TPW = 2 or 4, chosen per launch). Lane l of every
+// With TPW = 4 a workgroup serves 16 samples of one request with
+// ceil(T / 16) waves; wave w owns the instant tiles 4w .. 4w + 3 (4 instants
+// each). Lane l of every
 // wave belongs to sample n = l % 16 and to lane group g = l / 16, which holds
 //   * free coefficients 4g .. 4g + 3 of its sample (state z, z_bar, lambda),
 //   * at each tile, position / velocity / acceleration of both axes at
@@ -1108,11 +1108,15 @@ lower_kernel(LowerArgs A, MethodParams P) {
 // table is staged in LDS per workgroup. N^T g is accumulated per pair of
 // tiles (2p, 2p + 1) from zero; the pair sums meet in LDS, each of the 256
 // values is summed over the pairs in pair order by one thread, and every wave
-// applies the same update. The arithmetic is therefore the same for either
-// TPW: small launches use TPW = 2 (more waves, half the serial work per
-// workgroup), large ones TPW = 4 (two workgroups fit a CU and cover each
-// other's barriers). Everything between the products is the FP32 code of the
-// VALU kernel.
+// applies the same update. Large launches use TPW = 4 (two workgroups fit a
+// CU and cover each other's barriers). Small ones use TPW = 1: a workgroup
+// of 8 samples with one tile pair per wave (ceil(T / 8) waves, twice the
+// workgroups and half the serial work of 16-sample ones). There columns n
+// and n + 8 of every product carry sample n & 7, the lanes of columns 8..15
+// keep the pair's second tile, and that tile's N^T g products start from the
+// first tile's sum rotated across the row: every sum is formed as with
+// TPW = 4, so results are the same bit for bit. Everything between the
+// products is the FP32 code of the VALU kernel.
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
