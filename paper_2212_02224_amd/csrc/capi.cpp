@@ -665,17 +665,23 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
     prefix[pos + k] = blocks;
     gr.T = keys[kk];
     if (mf && blocks < 2 * h->n_cu) {
-      // light load: workgroups of 8 samples, one tile pair per wave (twice
-      // the workgroups, half the serial work of each; the same arithmetic)
-      gr.tpw = 1;
-      blocks = 0;
-      for (int i = gr.act_off; i < pos; ++i) {
-        const ReqDesc &d = h->h_desc[act[i]];
-        prefix[i + k] = blocks;
-        blocks += blocks_for(d.N, d.T, true, 1, true);
+      // lighter load: two tiles per wave, or while the 8-sample workgroups
+      // all fit the chip at once (one per CU), one tile pair per wave (twice
+      // the workgroups, half the serial work of each); the same arithmetic
+      int blocks8 = 0;
+      for (int i = gr.act_off; i < pos; ++i) blocks8 += blocks_for(h->h_desc[act[i]].N, 0, true, 1, true);
+      gr.tpw = 2;
+      if (blocks8 <= h->n_cu) {
+        gr.tpw = 1;
+        blocks = 0;
+        for (int i = gr.act_off; i < pos; ++i) {
+          const ReqDesc &d = h->h_desc[act[i]];
+          prefix[i + k] = blocks;
+          blocks += blocks_for(d.N, d.T, true, 1, true);
+        }
+        gr.nblocks = blocks;
+        prefix[pos + k] = blocks;
       }
-      gr.nblocks = blocks;
-      prefix[pos + k] = blocks;
     }
     if (!mf && keys[kk] == 2) {
       int blocks2 = 0;
@@ -717,12 +723,20 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
   all.act_off = pos0;
   all.n = n;
   all.T = mf ? ls.grp[k0 + nkeys - 1].T : 1;
-  all.tpw = 1;  // matrix-core: merged only under light load
+  // matrix-core: merged only under light load; one tile pair per wave while
+  // the 8-sample workgroups all fit the chip at once, else two tiles per wave
+  bool half = false;
+  if (mf) {
+    int blocks8 = 0;
+    for (int i = pos0; i < pos0 + n; ++i) blocks8 += blocks_for(h->h_desc[act[i]].N, 0, true, 1, true);
+    half = blocks8 <= h->n_cu;
+    all.tpw = half ? 1 : 2;
+  }
   int blocks = 0;
   for (int i = pos0; i < pos0 + n; ++i) {
     const ReqDesc &d = h->h_desc[act[i]];
     prefix[i + k0] = blocks;
-    blocks += blocks_for(d.N, d.T, mf, 1, mf);
+    blocks += blocks_for(d.N, d.T, mf, 1, half);
     all.lds = std::max(all.lds, lds_bytes(d.M, d.T, mf, mfma_f32(h->cfg)));
   }
   prefix[pos0 + n + k0] = blocks;
@@ -771,9 +785,7 @@ plan_status launch_lower_group(plan_handle *h, const LaunchSet &ls, int k, int l
   return timed(
       h, 0,
       [&](hipEvent_t a, hipEvent_t b) {
-        // matrix cores: one tile pair per wave over 8 samples while 16-sample
-        // workgroups cannot give every CU two, else four tiles per wave
-        // (same arithmetic either way)
+        // matrix cores: 4, 2 or 1 tiles per wave by load (same arithmetic)
         return mf ? launch_lower_mfma(la, h->mp, gr.nblocks, gr.tpw, gr.road, mfma_f32(h->cfg), gr.T, gr.lds,
                                       h->stream, a, b)
                   : launch_lower(la, h->mp, gr.nblocks, gr.ipl, gr.road, gr.lds, h->stream, a, b);

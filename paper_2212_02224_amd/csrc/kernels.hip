@@ -1091,9 +1091,9 @@ lower_kernel(LowerArgs A, MethodParams P) {
 // ---------------------------------------------------------------------------
 // Lower level on the matrix cores (FP16 high/low split, FP32 accumulation).
 //
-// With TPW = 4 a workgroup serves 16 samples of one request with
-// ceil(T / 16) waves; wave w owns the instant tiles 4w .. 4w + 3 (4 instants
-// each). Lane l of every
+// With TPW = 2 or 4 a workgroup serves 16 samples of one request with
+// ceil(T / (4 TPW)) waves; wave w owns the instant tiles TPW w .. TPW w +
+// TPW - 1 (4 instants each). Lane l of every
 // wave belongs to sample n = l % 16 and to lane group g = l / 16, which holds
 //   * free coefficients 4g .. 4g + 3 of its sample (state z, z_bar, lambda),
 //   * at each tile, position / velocity / acceleration of both axes at
@@ -1109,9 +1109,11 @@ lower_kernel(LowerArgs A, MethodParams P) {
 // tiles (2p, 2p + 1) from zero; the pair sums meet in LDS, each of the 256
 // values is summed over the pairs in pair order by one thread, and every wave
 // applies the same update. Large launches use TPW = 4 (two workgroups fit a
-// CU and cover each other's barriers). Small ones use TPW = 1: a workgroup
-// of 8 samples with one tile pair per wave (ceil(T / 8) waves, twice the
-// workgroups and half the serial work of 16-sample ones). There columns n
+// CU and cover each other's barriers), middle ones TPW = 2 (two tiles per
+// wave, 16 samples), and launches whose workgroups all fit the chip at once
+// TPW = 1: a workgroup of 8 samples with one tile pair per wave (ceil(T / 8)
+// waves, twice the workgroups and half the serial work of 16-sample ones;
+// a 13-wave workgroup takes a CU to itself). There columns n
 // and n + 8 of every product carry sample n & 7, the lanes of columns 8..15
 // keep the pair's second tile, and that tile's N^T g products start from the
 // first tile's sum rotated across the row: every sum is formed as with
@@ -2480,12 +2482,16 @@ hipError_t launch_lower(const LowerArgs &a, const MethodParams &p, int nblocks, 
 }
 hipError_t launch_lower_mfma(const LowerArgs &a, const MethodParams &p, int nblocks, int tpw, bool road, bool f32,
                              int T, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if ((tpw != 1 && tpw != 4) || T < 1 || T > kMfmaMaxT) return hipErrorInvalidValue;
+  if ((tpw != 1 && tpw != 2 && tpw != 4) || T < 1 || T > kMfmaMaxT) return hipErrorInvalidValue;
   const int waves = tpw == 1 ? ((T + 3) / 4 + 1) / 2 : (T + 4 * tpw - 1) / (4 * tpw);
-  auto kern = f32 ? (tpw == 1 ? (road ? lower_mfma_kernel<1, true, true> : lower_mfma_kernel<1, false, true>)
-                              : (road ? lower_mfma_kernel<4, true, true> : lower_mfma_kernel<4, false, true>))
-                  : (tpw == 1 ? (road ? lower_mfma_kernel<1, true, false> : lower_mfma_kernel<1, false, false>)
-                              : (road ? lower_mfma_kernel<4, true, false> : lower_mfma_kernel<4, false, false>));
+  using K = void (*)(LowerArgs, MethodParams);
+  const K k1 = f32 ? (road ? lower_mfma_kernel<1, true, true> : lower_mfma_kernel<1, false, true>)
+                   : (road ? lower_mfma_kernel<1, true, false> : lower_mfma_kernel<1, false, false>);
+  const K k2 = f32 ? (road ? lower_mfma_kernel<2, true, true> : lower_mfma_kernel<2, false, true>)
+                   : (road ? lower_mfma_kernel<2, true, false> : lower_mfma_kernel<2, false, false>);
+  const K k4 = f32 ? (road ? lower_mfma_kernel<4, true, true> : lower_mfma_kernel<4, false, true>)
+                   : (road ? lower_mfma_kernel<4, true, false> : lower_mfma_kernel<4, false, false>);
+  const K kern = tpw == 1 ? k1 : tpw == 2 ? k2 : k4;
   if (ev0 != nullptr)
     hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(kWave * waves), (uint32_t)lds, st, ev0, ev1, 0, a, p);
   else
