@@ -227,10 +227,13 @@ def test_mixed_served_equals_alone(pl, precision):
 
 @pytest.mark.parametrize("precision", [1, 2])
 def test_mixed_tiles_per_wave_does_not_change_results(pl, precision):
-    """A large launch runs four instant tiles per wave, a small one two; the
-    sums are formed per tile pair in a fixed order, so every request's result
-    is bitwise the same either way (here: alone = two, in a batch of 12k
-    samples = four)."""
+    """The matrix-core launch shape follows the load: four instant tiles per
+    wave for a large launch, two for a middle one, and one tile pair per wave
+    over 8-sample workgroups while those fit the chip at once. The sums are
+    formed per tile pair in one fixed chain, so every request's result is
+    bitwise the same in each (on 256 CUs: the 12k-sample batch runs four,
+    request 0 alone, 4096 samples, two, and request 3 alone, 64 samples, one
+    pair per wave)."""
     cfg = pl.plan_config_init(T_set=[100], M_set=[10], proj_iters=10, upper_iters=2, max_N=4096, max_requests=4,
                               precision=precision)
     h = pl.plan_create(cfg)
