@@ -89,9 +89,9 @@ typedef enum plan_status {
  *   PLAN_PREC_FP32_MFMA   the same dense products on the matrix cores in
  *                         FP32 (FP32 operands, FP32 accumulation; no
  *                         splitting), everything else as PLAN_PREC_FP32.
- *                         Groups of 16 samples per workgroup, so it pays on
- *                         large batches (thousands of samples in flight);
- *                         requires every T <= 128.
+ *                         Groups of 16 samples per workgroup (8 for small
+ *                         launches), so it pays on large batches (thousands
+ *                         of samples in flight); requires every T <= 128.
  * All modes draw the same samples and use the same selection and update;
  * a request's results depend on the mode, never on what else runs with it.
  */

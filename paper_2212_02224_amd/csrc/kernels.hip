@@ -1189,9 +1189,10 @@ __device__ __forceinline__ void coef_operands(f4 z, h4 &bx, h4 &by) {
   by = __builtin_bit_cast(h4, b);
 }
 
-// Draw of Alg. 1 for the 16 samples of a wave: lane group g runs Philox block
-// min(g, 2) and Box-Muller pair g of its sample; the same values as
-// wave_draw.
+// Draw of Alg. 1 for the 16 columns of a wave (column n: sample j; in the
+// 8-sample layout two columns draw the same sample): lane group g runs
+// Philox block min(g, 2) and Box-Muller pair g of the column's sample; the
+// same values as wave_draw.
 __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int N, int l, bool structured,
                            const double *mu, const double *chol, int lane, float (&p)[8]) {
   const int n = lane & 15, g = lane >> 4;
