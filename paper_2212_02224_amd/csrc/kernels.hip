@@ -403,9 +403,10 @@ __device__ __forceinline__ void pair_update(float xs, float ys, const float4 &o,
 
 // Neighbour sums of one lane's instant t (the matrix-core kernels): the
 // entries of pairs c and c + 1 in alternating registers. GATE (the FP32
-// matrix-core form: 91.2 -> 85.1 ms at the headline shape) skips a pair as
-// pair_update does; the FP16 split leaves it out (its branches cost it the
-// overlap of its matrix products with the vector work: 78 -> 118 ms).
+// matrix-core form: 91.2 -> 85.1 ms at the headline shape, and both forms'
+// 8-sample layout) skips a pair as pair_update does; the FP16 split's
+// 16-sample launches leave it out (its branches cost them the overlap of
+// their matrix products with the vector work: 78 -> 118 ms).
 template <bool GATE>
 __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, int npair, int T, int t,
                                                float xs, float ys, uint64_t live, float &ax, float &ay) {
@@ -1444,8 +1445,10 @@ __global__ void __launch_bounds__(kWave *(TPW == 1 ? kMfmaMaxPairs : kMfmaMaxT /
         const State6 s0 = evaluate(ta, co), s1 = has_b ? evaluate(ta + 1, co) : s0;
         const State6 st = hh ? s1 : s0;
         if (first) da[0] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-        const Corr c = targets_at<ROAD, F32>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1, active && t < T,
-                                             da[0]);
+        // the neighbour gate pays in this layout in both forms (FP16 split at
+        // C3: 53.1 -> 52.2 us), unlike the FP16 split's 16-sample launches
+        const Corr c = targets_at<ROAD, true>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1, active && t < T,
+                                              da[0]);
         // tile a's sum of each sample sits in column n < 8; rotated to column
         // n + 8 it starts tile b's products there, and the pair's sum comes
         // back to column n (the same chain as one wave over both tiles). The
