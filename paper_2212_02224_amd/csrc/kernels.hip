@@ -404,9 +404,9 @@ __device__ __forceinline__ void pair_update(float xs, float ys, const float4 &o,
 // Neighbour sums of one lane's instant t (the matrix-core kernels): the
 // entries of pairs c and c + 1 in alternating registers. GATE (the FP32
 // matrix-core form: 91.2 -> 85.1 ms at the headline shape, and both forms'
-// 8-sample layout) skips a pair as pair_update does; the FP16 split's
-// 16-sample launches leave it out (its branches cost them the overlap of
-// their matrix products with the vector work: 78 -> 118 ms).
+// lighter launches) skips a pair as pair_update does; the FP16 split's
+// launches of four tiles per wave leave it out (its branches cost them the
+// overlap of their matrix products with the vector work: 78 -> 118 ms).
 template <bool GATE>
 __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, int npair, int T, int t,
                                                float xs, float ys, uint64_t live, float &ax, float &ay) {
@@ -1446,7 +1446,7 @@ __global__ void __launch_bounds__(kWave *(TPW == 1 ? kMfmaMaxPairs : kMfmaMaxT /
         const State6 st = hh ? s1 : s0;
         if (first) da[0] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
         // the neighbour gate pays in this layout in both forms (FP16 split at
-        // C3: 53.1 -> 52.2 us), unlike the FP16 split's 16-sample launches
+        // C3: 53.1 -> 52.2 us)
         const Corr c = targets_at<ROAD, true>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1, active && t < T,
                                               da[0]);
         // tile a's sum of each sample sits in column n < 8; rotated to column
@@ -1483,8 +1483,11 @@ __global__ void __launch_bounds__(kWave *(TPW == 1 ? kMfmaMaxPairs : kMfmaMaxT /
               const int t = 4 * tile + g;
               const State6 st = evaluate(tile, co);
               if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-              acc = accumulate(tile, targets_at<ROAD, F32>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
-                                                      active && t < T, da[i]),
+              // the gate: in the FP32 form, and in the FP16 split with two
+              // tiles per wave (served p50 at 0.5 load 0.87 -> 0.77 ms); with
+              // four it costs the FP16 split its co-issue
+              acc = accumulate(tile, targets_at<ROAD, F32 || TPW == 2>(st, S, s_obs, s_road, npair, T,
+                                                                       t < T ? t : T - 1, active && t < T, da[i]),
                                acc);
             }
           }
