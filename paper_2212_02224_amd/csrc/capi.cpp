@@ -626,6 +626,19 @@ plan_status timed(plan_handle *h, int kind, F &&launch, const char *what) {
   return PLAN_OK;
 }
 
+// Workgroup prefix of the launch-set entries act[a0..a1) of group k (stored
+// at prefix[i + k], the total at prefix[a1 + k]) with blocks(request) each;
+// returns the total.
+template <class F>
+int set_prefix(const plan_handle *h, const int32_t *act, int32_t *prefix, int a0, int a1, int k, F blocks) {
+  int total = 0;
+  for (int i = a0; i < a1; ++i) {
+    prefix[i + k] = total;
+    total += blocks(h->h_desc[act[i]]);
+  }
+  prefix[a1 + k] = total;
+  return total;
+}
 // Launch groups of the slots slots[0..n), all with or all without a road
 // profile, appended to ls: group k's slots at act[off..off+n), its workgroup
 // prefix counts at prefix[off + k .. off + k + n].
@@ -673,14 +686,8 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
       gr.tpw = 2;
       if (blocks8 <= h->n_cu) {
         gr.tpw = 1;
-        blocks = 0;
-        for (int i = gr.act_off; i < pos; ++i) {
-          const ReqDesc &d = h->h_desc[act[i]];
-          prefix[i + k] = blocks;
-          blocks += blocks_for(d.N, d.T, true, 1, true);
-        }
-        gr.nblocks = blocks;
-        prefix[pos + k] = blocks;
+        gr.nblocks = set_prefix(h, act, prefix, gr.act_off, pos, k,
+                                [](const ReqDesc &d) { return blocks_for(d.N, d.T, true, 1, true); });
       }
     }
     if (!mf && keys[kk] == 2) {
@@ -691,14 +698,8 @@ void add_launch_groups(plan_handle *h, const int *slots, int n, bool road, Launc
       }
       if (use_ipl2(blocks, blocks2, h->n_cu)) {
         gr.ipl = 2;
-        blocks = 0;
-        for (int i = gr.act_off; i < pos; ++i) {
-          const ReqDesc &d = h->h_desc[act[i]];
-          prefix[i + k] = blocks;
-          blocks += blocks_for(d.N, d.T, false, 2);
-        }
-        gr.nblocks = blocks;
-        prefix[pos + k] = blocks;
+        gr.nblocks = set_prefix(h, act, prefix, gr.act_off, pos, k,
+                                [](const ReqDesc &d) { return blocks_for(d.N, d.T, false, 2); });
       }
     }
   }
