@@ -402,11 +402,9 @@ __device__ __forceinline__ void pair_update(float xs, float ys, const float4 &o,
 }
 
 // Neighbour sums of one lane's instant t (the matrix-core kernels): the
-// entries of pairs c and c + 1 in alternating registers. GATE (the FP32
-// matrix-core form: 91.2 -> 85.1 ms at the headline shape, and both forms'
-// lighter launches) skips a pair as pair_update does; the FP16 split's
-// launches of four tiles per wave leave it out (its branches cost them the
-// overlap of their matrix products with the vector work: 78 -> 118 ms).
+// entries of pairs c and c + 1 in alternating registers. GATE skips a pair
+// as pair_update does; every matrix-core launch takes it (at the headline
+// shape: FP32 form 91.2 -> 85.1 ms, FP16 split 77.7 -> 73.3 ms).
 template <bool GATE>
 __device__ __forceinline__ void neighbour_pass(const float4 *__restrict__ obs, int npair, int T, int t,
                                                float xs, float ys, uint64_t live, float &ax, float &ay) {
@@ -1233,9 +1231,12 @@ __device__ void group_draw(const MethodParams &P, uint64_t seed, int j, int N, i
 //               instants of the tile along K, each lane's own differences as
 //               its B element);
 //   xi-update   4 products per iteration (A^-1 in FP32, rhs transposed).
+// Four tiles per wave without the road profile: held to 128 registers per
+// lane (one is spilled), which keeps two 7-wave workgroups per CU; with 129
+// the FP16 split fits one and runs 50% longer.
 template <int TPW, bool ROAD, bool F32>
 __global__ void __launch_bounds__(kWave *(TPW == 1 ? kMfmaMaxPairs : kMfmaMaxT / (4 * TPW)))
-    lower_mfma_kernel(LowerArgs A, MethodParams P) {
+    __attribute__((amdgpu_waves_per_eu(TPW == 4 && !ROAD ? 4 : 1))) lower_mfma_kernel(LowerArgs A, MethodParams P) {
   extern __shared__ float4 s_dyn[];
   __shared__ double s_mu[8], s_chol[64];
   __shared__ float s_rc[kMfmaMaxPairs][kMfmaSamples][2];
@@ -1445,8 +1446,6 @@ __global__ void __launch_bounds__(kWave *(TPW == 1 ? kMfmaMaxPairs : kMfmaMaxT /
         const State6 s0 = evaluate(ta, co), s1 = has_b ? evaluate(ta + 1, co) : s0;
         const State6 st = hh ? s1 : s0;
         if (first) da[0] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-        // the neighbour gate pays in this layout in both forms (FP16 split at
-        // C3: 53.1 -> 52.2 us)
         const Corr c = targets_at<ROAD, true>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1, active && t < T,
                                               da[0]);
         // tile a's sum of each sample sits in column n < 8; rotated to column
@@ -1483,11 +1482,8 @@ __global__ void __launch_bounds__(kWave *(TPW == 1 ? kMfmaMaxPairs : kMfmaMaxT /
               const int t = 4 * tile + g;
               const State6 st = evaluate(tile, co);
               if (first) da[i] = fminf(fsqrt(fmaf(st.xdd, st.xdd, st.ydd * st.ydd)), S.a_max);
-              // the gate: in the FP32 form, and in the FP16 split with two
-              // tiles per wave (served p50 at 0.5 load 0.87 -> 0.77 ms); with
-              // four it costs the FP16 split its co-issue
-              acc = accumulate(tile, targets_at<ROAD, F32 || TPW == 2>(st, S, s_obs, s_road, npair, T,
-                                                                       t < T ? t : T - 1, active && t < T, da[i]),
+              acc = accumulate(tile, targets_at<ROAD, true>(st, S, s_obs, s_road, npair, T, t < T ? t : T - 1,
+                                                       active && t < T, da[i]),
                                acc);
             }
           }
